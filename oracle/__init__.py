@@ -1,0 +1,170 @@
+"""Plain FP64 CPU oracle for the Rusanov Finite Volume patch update.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it to check and to time the GPU path.  The product
+library never imports it, and it imports nothing from the product package.
+
+The arithmetic lives in ``fv_oracle.c`` (plain C, compiled with
+``-O2 -ffp-contract=off``, no fast-math); this module only builds it with gcc
+and marshals numpy arrays through ctypes.  Every function follows the paper's
+definitions: the conservative update (Sec. 2.2), the Rusanov flux (Eq. 2), the
+Euler user terms F_n / lambda_max,n (Sec. 5, Eq. 1 with B = S = delta = 0) and
+the per-patch eigenvalue reduction for the CFL condition (end of Sec. 2.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "fv_oracle.c")
+LIBRARY = os.path.join(_HERE, "libfvoracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+
+
+def build(source: str = SOURCE, output: str = LIBRARY, extra: list[str] | None = None) -> str:
+    """Compile the oracle with gcc.  Returns the path of the shared library."""
+    cmd = ["gcc", *CFLAGS, *(extra or []), "-o", output, source, "-lm"]
+    subprocess.run(cmd, check=True)
+    return output
+
+
+_lib = None
+
+
+def load(path: str | None = None, rebuild: bool = False):
+    """Load (building first if absent) the oracle library."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is None or rebuild:
+        if rebuild or not os.path.exists(LIBRARY) or os.path.getmtime(LIBRARY) < os.path.getmtime(SOURCE):
+            build()
+        _lib = _bind(ctypes.CDLL(LIBRARY))
+    return _lib
+
+
+def _bind(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    i32, f64 = ctypes.c_int32, ctypes.c_double
+    lib.fvo_batch_update.argtypes = [dp, dp, ip, lp, i32, i32, i32, f64, f64, f64, i32, dp, i32]
+    lib.fvo_batch_update.restype = ctypes.c_int
+    lib.fvo_batch_lambda.argtypes = [dp, ip, lp, i32, i32, i32, f64, dp]
+    lib.fvo_batch_lambda.restype = ctypes.c_int
+    lib.fvo_batch_wrap.argtypes = [dp, ip, lp, i32, i32, i32]
+    lib.fvo_batch_wrap.restype = ctypes.c_int
+    lib.fvo_flux.argtypes = [dp, i32, i32, f64, dp, dp]
+    lib.fvo_flux.restype = None
+    lib.fvo_rusanov.argtypes = [dp, dp, i32, i32, f64, dp]
+    lib.fvo_rusanov.restype = None
+    lib.fvo_max_threads.argtypes = []
+    lib.fvo_max_threads.restype = ctypes.c_int32
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _descriptors(sizes, offsets, num_patches):
+    sizes = np.ascontiguousarray(np.broadcast_to(np.asarray(sizes, dtype=np.int32), (num_patches,)))
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    assert offsets.shape == (num_patches,)
+    return sizes, offsets
+
+
+def batch_update(state_in: np.ndarray, sizes, offsets, dim: int, nq: int, dt: float, h: float,
+                 gamma: float = 1.4, periodic: bool = False, out: np.ndarray | None = None,
+                 want_lambda: bool = True, nthreads: int = 0, lib=None):
+    """One explicit Euler step of every patch.  Returns (out, lambda or None).
+
+    ``out`` defaults to a copy of ``state_in`` so that volumes the step does not
+    write (halos, corners) keep their input values.
+    """
+    lib = lib or load()
+    num_patches = len(offsets)
+    sizes, offsets = _descriptors(sizes, offsets, num_patches)
+    state_in = np.ascontiguousarray(state_in, dtype=np.float64)
+    if out is None:
+        out = state_in.copy()
+    lam = np.zeros(num_patches, dtype=np.float64) if want_lambda else None
+    rc = lib.fvo_batch_update(_dptr(state_in), _dptr(out),
+                              sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              num_patches, dim, nq, dt, h, gamma, int(bool(periodic)),
+                              _dptr(lam) if lam is not None else None, nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out, lam
+
+
+def batch_lambda(state: np.ndarray, sizes, offsets, dim: int, nq: int, gamma: float = 1.4, lib=None):
+    """Maximum wave speed over the interior of every patch of ``state``."""
+    lib = lib or load()
+    num_patches = len(offsets)
+    sizes, offsets = _descriptors(sizes, offsets, num_patches)
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    lam = np.zeros(num_patches, dtype=np.float64)
+    rc = lib.fvo_batch_lambda(_dptr(state), sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              num_patches, dim, nq, gamma, _dptr(lam))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return lam
+
+
+def batch_wrap(state: np.ndarray, sizes, offsets, dim: int, nq: int, lib=None) -> np.ndarray:
+    """Periodic self-wrap of every patch's face halo, in place; returns ``state``."""
+    lib = lib or load()
+    num_patches = len(offsets)
+    sizes, offsets = _descriptors(sizes, offsets, num_patches)
+    rc = lib.fvo_batch_wrap(_dptr(state), sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), num_patches, dim, nq)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return state
+
+
+def flux(q, n: int, nq: int, gamma: float = 1.4, lib=None):
+    """F_n(Q) and lambda_max,n(Q) of one volume."""
+    lib = lib or load()
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    f = np.zeros(nq)
+    lam = ctypes.c_double()
+    lib.fvo_flux(_dptr(q), n, nq, gamma, _dptr(f), ctypes.byref(lam))
+    return f, lam.value
+
+
+def rusanov(qL, qR, n: int, nq: int, gamma: float = 1.4, lib=None):
+    """Rusanov flux through one face."""
+    lib = lib or load()
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    f = np.zeros(nq)
+    lib.fvo_rusanov(_dptr(qL), _dptr(qR), n, nq, gamma, _dptr(f))
+    return f
+
+
+def max_threads(lib=None) -> int:
+    lib = lib or load()
+    return int(lib.fvo_max_threads())
+
+
+def run_steps(state: np.ndarray, sizes, offsets, dim: int, nq: int, dts, h: float, gamma: float = 1.4,
+              periodic: bool = False, nthreads: int = 0):
+    """Apply len(dts) steps with ping-pong buffers.  Returns (state, [lambda per step])."""
+    a = np.ascontiguousarray(state, dtype=np.float64).copy()
+    b = a.copy()
+    lams = []
+    for dt in dts:
+        b, lam = batch_update(a, sizes, offsets, dim, nq, dt, h, gamma, periodic, out=b, nthreads=nthreads)
+        lams.append(lam)
+        a, b = b, a
+    return a, lams

@@ -1,0 +1,281 @@
+/*
+ * fv_oracle.c -- plain FP64 CPU oracle for one explicit Euler step of the
+ * Rusanov Finite Volume scheme over a batch of halo-padded Cartesian patches
+ * (compressible Euler equations).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.  It shares no code, header, table or helper with
+ * the HIP path.
+ *
+ * It is written as the plain definition of the scheme, with no blocking,
+ * fusion or reordering:
+ *   - the update of a volume c over one time step (paper, Sec. 2.2, the
+ *     unnumbered update formula):
+ *         Q_new(c) = Q(c) + (dt/h) * sum_n [ Fhat_n(c - e_n/2) - Fhat_n(c + e_n/2) ]
+ *     i.e. the flux through the left face enters with "+", the flux through
+ *     the right face with "-" (Alg. 1, the two update microkernels);
+ *   - the Rusanov face flux (Eq. 2):
+ *         Fhat = 1/2 (F_n(Q_L) + F_n(Q_R)) - 1/2 max(lambda_n(Q_L), lambda_n(Q_R)) (Q_R - Q_L)
+ *   - the user terms F_n (flux along axis n) and lambda_max,n (largest wave
+ *     speed along n) of the compressible Euler equations, the PDE the paper's
+ *     experiments solve (Sec. 5, N = 2 + d; Eq. 1 with B = S = delta = 0);
+ *   - the per-patch maximum eigenvalue of the NEW solution that feeds the CFL
+ *     condition (end of Sec. 2.2).
+ *
+ * Readings of the paper where it is garbled or silent (all listed in the
+ * design notes of the repository):
+ *   - Eq. 2 prints the dissipation as (C/h)(Q+ - Q-) max(lambda); the
+ *     textbook Rusanov / local Lax-Friedrichs flux has C = 1/2 and no 1/h, and
+ *     that is what is computed here.
+ *   - The update formula prints "Delta t * h"; a conservative update of a
+ *     volume of size h^d through faces of size h^(d-1) scales by dt/h.
+ *   - lambda_max,n is the largest eigenvalue MAGNITUDE |u_n| + c.
+ *   - the face wave speeds use the OLD state; the final reduction uses the
+ *     new one.
+ *   - only face halo volumes are ever read: corner (2D) and edge/corner (3D)
+ *     halo volumes do not enter the result.
+ *   - the difference of the two face fluxes is formed first, then the
+ *     directional differences are summed in axis order ((x + y) + z), then
+ *     scaled by dt/h and added to Q.
+ *   - unknowns: N = 5 (rho, m_x, m_y, m_z, E) in 2D and 3D -- in 2D m_z is a
+ *     passive momentum (advected, no z flux, part of the kinetic energy) --
+ *     or the paper's N = 2 + d = 4 in 2D (rho, m_x, m_y, E).
+ *   - max() propagates NaN (any NaN in, NaN out).
+ *
+ * Layout: patch t starts at offsets[t] (in doubles).  Its (p+2)^d volumes are
+ * stored in x-fastest order, each volume holding its N unknowns contiguously
+ * (array of structures):  index = offsets[t] + ((k*(p+2) + j)*(p+2) + i)*N + q,
+ * with i, j, k in [0, p+1]; halo volumes sit at 0 and p+1.
+ *
+ * Compile with -O2 -ffp-contract=off and no fast-math: every operation below
+ * rounds once, in the order written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORA_MAXQ 5
+
+/* NaN-propagating maximum: if either argument is NaN the result is NaN. */
+static double ora_max(double a, double b)
+{
+    if (a != a) return a;
+    if (b != b) return b;
+    return (a > b) ? a : b;
+}
+
+/* Number of momentum components stored in a volume with nq unknowns. */
+static int ora_nmom(int nq) { return nq - 2; }
+
+/* Pressure of the ideal gas: p = (gamma - 1) (E - |m|^2 / (2 rho)). */
+static double ora_pressure(const double *q, int nq, double gamma)
+{
+    double rho = q[0];
+    double m2 = 0.0;
+    for (int a = 0; a < ora_nmom(nq); ++a) m2 = m2 + q[1 + a] * q[1 + a];
+    double E = q[nq - 1];
+    return (gamma - 1.0) * (E - 0.5 * m2 / rho);
+}
+
+/*
+ * User term F_n(Q) of the Euler equations along axis n, and
+ * lambda_max,n(Q) = |u_n| + c with c = sqrt(gamma p / rho).
+ *   F_n = ( m_n,  m_a u_n + p delta_{a n} (each stored momentum a),  (E + p) u_n )
+ */
+static void ora_flux(const double *q, int n, int nq, double gamma,
+                     double *f, double *lam)
+{
+    double rho = q[0];
+    double p = ora_pressure(q, nq, gamma);
+    double un = q[1 + n] / rho;
+    f[0] = q[1 + n];
+    for (int a = 0; a < ora_nmom(nq); ++a) {
+        double v = q[1 + a] * un;
+        if (a == n) v = v + p;
+        f[1 + a] = v;
+    }
+    f[nq - 1] = (q[nq - 1] + p) * un;
+    double c = sqrt(gamma * p / rho);
+    *lam = fabs(un) + c;
+}
+
+/* Rusanov flux through the face between left volume qL and right volume qR
+ * along axis n (Eq. 2, with the reading C = 1/2 and no 1/h). */
+static void ora_rusanov(const double *qL, const double *qR, int n, int nq,
+                        double gamma, double *fhat)
+{
+    double fL[ORA_MAXQ], fR[ORA_MAXQ], lL, lR;
+    ora_flux(qL, n, nq, gamma, fL, &lL);
+    ora_flux(qR, n, nq, gamma, fR, &lR);
+    double s = ora_max(lL, lR);
+    for (int q = 0; q < nq; ++q)
+        fhat[q] = 0.5 * (fL[q] + fR[q]) - 0.5 * s * (qR[q] - qL[q]);
+}
+
+/* Offset (in doubles) of volume (i, j, k) inside a padded patch. */
+static size_t ora_vol(int p, int dim, int i, int j, int k, int nq)
+{
+    size_t w = (size_t)(p + 2);
+    size_t kk = (dim == 3) ? (size_t)k : 0;
+    return ((kk * w + (size_t)j) * w + (size_t)i) * (size_t)nq;
+}
+
+/* Largest wave speed over the interior volumes of one padded patch state:
+ * max over interior c and axes n < dim of lambda_max,n(Q(c)). */
+static double ora_patch_lambda(const double *P, int p, int dim, int nq, double gamma)
+{
+    double lmax = 0.0;
+    int kend = (dim == 3) ? p : 1;
+    int kbeg = (dim == 3) ? 1 : 0;
+    for (int k = kbeg; k <= kend; ++k)
+        for (int j = 1; j <= p; ++j)
+            for (int i = 1; i <= p; ++i) {
+                const double *q = P + ora_vol(p, dim, i, j, k, nq);
+                for (int n = 0; n < dim; ++n) {
+                    double f[ORA_MAXQ], lam;
+                    ora_flux(q, n, nq, gamma, f, &lam);
+                    lmax = ora_max(lmax, lam);
+                }
+            }
+    return lmax;
+}
+
+/* Periodic self-wrap of the face halo of one output patch: on each axis the
+ * halo layer at 0 takes the interior layer at p and the halo layer at p+1 the
+ * interior layer at 1.  Faces only: corner / edge halo volumes are untouched. */
+static void ora_wrap_faces(double *P, int p, int dim, int nq)
+{
+    int kbeg = (dim == 3) ? 1 : 0, kend = (dim == 3) ? p : 0;
+    for (int k = kbeg; k <= kend; ++k)
+        for (int j = 1; j <= p; ++j) {
+            memcpy(P + ora_vol(p, dim, 0, j, k, nq), P + ora_vol(p, dim, p, j, k, nq), sizeof(double) * nq);
+            memcpy(P + ora_vol(p, dim, p + 1, j, k, nq), P + ora_vol(p, dim, 1, j, k, nq), sizeof(double) * nq);
+        }
+    for (int k = kbeg; k <= kend; ++k)
+        for (int i = 1; i <= p; ++i) {
+            memcpy(P + ora_vol(p, dim, i, 0, k, nq), P + ora_vol(p, dim, i, p, k, nq), sizeof(double) * nq);
+            memcpy(P + ora_vol(p, dim, i, p + 1, k, nq), P + ora_vol(p, dim, i, 1, k, nq), sizeof(double) * nq);
+        }
+    if (dim == 3)
+        for (int j = 1; j <= p; ++j)
+            for (int i = 1; i <= p; ++i) {
+                memcpy(P + ora_vol(p, dim, i, j, 0, nq), P + ora_vol(p, dim, i, j, p, nq), sizeof(double) * nq);
+                memcpy(P + ora_vol(p, dim, i, j, p + 1, nq), P + ora_vol(p, dim, i, j, 1, nq), sizeof(double) * nq);
+            }
+}
+
+/* One explicit Euler step of one patch: Q_new over the interior. */
+static void ora_patch_step(const double *Pin, double *Pout, int p, int dim, int nq,
+                           double dt, double h, double gamma)
+{
+    double r = dt / h;
+    int kbeg = (dim == 3) ? 1 : 0, kend = (dim == 3) ? p : 0;
+    for (int k = kbeg; k <= kend; ++k)
+        for (int j = 1; j <= p; ++j)
+            for (int i = 1; i <= p; ++i) {
+                const int c[3] = {i, j, k};
+                double D[ORA_MAXQ];
+                for (int n = 0; n < dim; ++n) {
+                    int lo[3] = {c[0], c[1], c[2]}, hi[3] = {c[0], c[1], c[2]};
+                    lo[n] -= 1;
+                    hi[n] += 1;
+                    const double *qc = Pin + ora_vol(p, dim, c[0], c[1], c[2], nq);
+                    const double *ql = Pin + ora_vol(p, dim, lo[0], lo[1], lo[2], nq);
+                    const double *qh = Pin + ora_vol(p, dim, hi[0], hi[1], hi[2], nq);
+                    double fleft[ORA_MAXQ], fright[ORA_MAXQ];
+                    ora_rusanov(ql, qc, n, nq, gamma, fleft);   /* face c - e_n/2 */
+                    ora_rusanov(qc, qh, n, nq, gamma, fright);  /* face c + e_n/2 */
+                    for (int q = 0; q < nq; ++q) {
+                        double d = fleft[q] - fright[q];
+                        D[q] = (n == 0) ? d : D[q] + d;
+                    }
+                }
+                const double *qc = Pin + ora_vol(p, dim, i, j, k, nq);
+                double *qo = Pout + ora_vol(p, dim, i, j, k, nq);
+                for (int q = 0; q < nq; ++q) qo[q] = qc[q] + r * D[q];
+            }
+}
+
+/*
+ * Batch entry point.  in/out: flat arrays holding every padded patch at
+ * offsets[t]; out gets the new interior of every patch (and, when periodic is
+ * non-zero, its self-wrapped face halo); lambda_out (may be NULL) gets the
+ * maximum wave speed of the new interior of every patch.  nthreads <= 0 uses
+ * the OpenMP default.  Returns 0, or -1 for arguments the oracle does not
+ * cover.
+ */
+int fvo_batch_update(const double *in, double *out, const int32_t *sizes,
+                     const int64_t *offsets, int32_t num_patches, int32_t dim,
+                     int32_t nq, double dt, double h, double gamma, int32_t periodic,
+                     double *lambda_out, int32_t nthreads)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    if (!(nq == 5 || (dim == 2 && nq == 4))) return -1;
+    if (num_patches < 0) return -1;
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+    for (int32_t t = 0; t < num_patches; ++t) {
+        int p = sizes[t];
+        const double *Pin = in + offsets[t];
+        double *Pout = out + offsets[t];
+        ora_patch_step(Pin, Pout, p, dim, nq, dt, h, gamma);
+        if (periodic) ora_wrap_faces(Pout, p, dim, nq);
+        if (lambda_out) lambda_out[t] = ora_patch_lambda(Pout, p, dim, nq, gamma);
+    }
+    (void)nthreads;
+    return 0;
+}
+
+/* Maximum wave speed of the interior of every patch of a state (used for the
+ * first time step size, before any update has produced a new solution). */
+int fvo_batch_lambda(const double *state, const int32_t *sizes, const int64_t *offsets,
+                     int32_t num_patches, int32_t dim, int32_t nq, double gamma,
+                     double *lambda_out)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    if (!(nq == 5 || (dim == 2 && nq == 4))) return -1;
+    for (int32_t t = 0; t < num_patches; ++t)
+        lambda_out[t] = ora_patch_lambda(state + offsets[t], sizes[t], dim, nq, gamma);
+    return 0;
+}
+
+/* Periodic self-wrap of the face halos of every patch of a state, in place. */
+int fvo_batch_wrap(double *state, const int32_t *sizes, const int64_t *offsets,
+                   int32_t num_patches, int32_t dim, int32_t nq)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    for (int32_t t = 0; t < num_patches; ++t)
+        ora_wrap_faces(state + offsets[t], sizes[t], dim, nq);
+    return 0;
+}
+
+/* Single-volume user terms, exposed so tests can evaluate F_n and lambda_n of
+ * a given state directly. */
+void fvo_flux(const double *q, int32_t n, int32_t nq, double gamma, double *f, double *lam)
+{
+    ora_flux(q, n, nq, gamma, f, lam);
+}
+
+/* Single-face Rusanov flux, exposed for tests. */
+void fvo_rusanov(const double *qL, const double *qR, int32_t n, int32_t nq, double gamma,
+                 double *fhat)
+{
+    ora_rusanov(qL, qR, n, nq, gamma, fhat);
+}
+
+/* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
+int32_t fvo_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

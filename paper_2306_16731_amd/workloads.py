@@ -1,0 +1,151 @@
+"""Seeded synthetic patch batches for the FV patch-update workloads.
+
+This module only draws input states; it contains none of the update's
+arithmetic, and both the GPU path and the CPU oracle consume what it returns.
+
+Layout of a batch (the layout the library's C ABI takes): one flat float64
+array; patch t starts at ``offsets[t]`` (in doubles) and holds its
+(p_t + 2)^d volumes in x-fastest order, each volume its N unknowns
+contiguously (array of structures), halo volumes at index 0 and p_t + 1 of
+every axis.
+
+State recipe (the paper fixes no initial data; these draws stand in for the
+patches an ExaHyPE traversal would hand the kernel):
+  * primitives drawn i.i.d. per volume (interior and halo alike):
+    rho ~ U[0.5, 1.5], u, v, w ~ U[-0.5, 0.5], p ~ U[0.5, 1.5];
+  * optionally a smooth Gaussian density pulse per patch,
+    rho += 0.1 exp(-|x - x_c|^2 / (2 sigma^2)), x_c the patch centre,
+    sigma = p h / 4, added before the conversion to conserved variables;
+  * conserved variables: (rho, rho u, rho v[, rho w], E) with
+    E = p / (gamma - 1) + rho |u|^2 / 2 (w is stored when N = 5, also in 2D).
+Draw order with ``numpy.random.Generator(PCG64(seed))``: the patch sizes
+(mixed batches only), then rho, u, v, w, p over all volumes of all patches in
+patch order.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = 1.4
+H_DEFAULT = 1.0 / 48.0
+CFL = 0.4
+
+
+@dataclass
+class Batch:
+    """A flat batch of halo-padded patches."""
+
+    data: np.ndarray      # float64 [total doubles]
+    sizes: np.ndarray     # int32 [T], interior volumes per axis
+    offsets: np.ndarray   # int64 [T], start of each patch in doubles
+    dim: int
+    nq: int
+
+    @property
+    def num_patches(self) -> int:
+        return int(self.sizes.shape[0])
+
+    @property
+    def uniform(self) -> bool:
+        return bool(self.num_patches == 0 or np.all(self.sizes == self.sizes[0]))
+
+    def patch_volumes(self) -> np.ndarray:
+        return (self.sizes.astype(np.int64) + 2) ** self.dim
+
+    def interior_volumes(self) -> int:
+        return int(np.sum(self.sizes.astype(np.int64) ** self.dim))
+
+    def patch(self, t: int) -> np.ndarray:
+        """View of patch t as an array [(p+2)]*dim reversed (k, j, i) x nq."""
+        p = int(self.sizes[t])
+        n = (p + 2) ** self.dim * self.nq
+        shape = (p + 2,) * self.dim + (self.nq,)
+        return self.data[self.offsets[t]:self.offsets[t] + n].reshape(shape)
+
+
+def contiguous_offsets(sizes: np.ndarray, dim: int, nq: int) -> np.ndarray:
+    vols = (np.asarray(sizes, dtype=np.int64) + 2) ** dim * nq
+    off = np.zeros(len(vols), dtype=np.int64)
+    if len(vols) > 1:
+        off[1:] = np.cumsum(vols)[:-1]
+    return off
+
+
+def _draw_primitives(rng: np.random.Generator, nvol: int):
+    rho = rng.uniform(0.5, 1.5, nvol)
+    u = rng.uniform(-0.5, 0.5, nvol)
+    v = rng.uniform(-0.5, 0.5, nvol)
+    w = rng.uniform(-0.5, 0.5, nvol)
+    p = rng.uniform(0.5, 1.5, nvol)
+    return rho, u, v, w, p
+
+
+def _pulse(sizes: np.ndarray, dim: int, h: float) -> np.ndarray:
+    """Gaussian density pulse, one per patch, centred on the patch centre."""
+    parts = []
+    for p in np.unique(sizes):
+        p = int(p)
+        idx = (np.arange(p + 2) - (p + 1) / 2.0) * h
+        grids = np.meshgrid(*([idx] * dim), indexing="ij")
+        r2 = sum(g * g for g in grids)
+        sigma = p * h / 4.0
+        parts.append((p, (0.1 * np.exp(-r2 / (2.0 * sigma * sigma))).reshape(-1)))
+    table = dict(parts)
+    return np.concatenate([table[int(p)] for p in sizes]) if len(sizes) else np.zeros(0)
+
+
+def conserved(rho, u, v, w, p, nq: int, gamma: float = GAMMA) -> np.ndarray:
+    """Stack primitive draws into conserved AoS volumes [nvol, nq]."""
+    ke = 0.5 * rho * (u * u + v * v + (w * w if nq == 5 else 0.0))
+    E = p / (gamma - 1.0) + ke
+    cols = [rho, rho * u, rho * v] + ([rho * w] if nq == 5 else []) + [E]
+    return np.stack(cols, axis=1)
+
+
+def make_batch(sizes, dim: int = 2, nq: int = 5, seed: int = 0, pulse: bool = False,
+               h: float = H_DEFAULT, gamma: float = GAMMA, rng: np.random.Generator | None = None) -> Batch:
+    """Contiguous batch of patches with the given interior sizes."""
+    sizes = np.asarray(sizes, dtype=np.int32)
+    rng = rng if rng is not None else np.random.Generator(np.random.PCG64(seed))
+    nvol = int(np.sum((sizes.astype(np.int64) + 2) ** dim))
+    rho, u, v, w, p = _draw_primitives(rng, nvol)
+    if pulse:
+        rho = rho + _pulse(sizes, dim, h)
+    data = conserved(rho, u, v, w, p, nq, gamma).reshape(-1).copy()
+    return Batch(data=data, sizes=sizes, offsets=contiguous_offsets(sizes, dim, nq), dim=dim, nq=nq)
+
+
+def make_uniform(num_patches: int, p: int, dim: int = 2, nq: int = 5, seed: int = 0, pulse: bool = False,
+                 h: float = H_DEFAULT, gamma: float = GAMMA) -> Batch:
+    return make_batch(np.full(num_patches, p, dtype=np.int32), dim, nq, seed, pulse, h, gamma)
+
+
+def make_mixed(num_patches: int, choices=(3, 5, 9, 17), dim: int = 2, nq: int = 5, seed: int = 0,
+               pulse: bool = False, h: float = H_DEFAULT, gamma: float = GAMMA) -> Batch:
+    """Patch sizes drawn uniformly from ``choices`` (drawn first), then the state."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = rng.choice(np.asarray(choices, dtype=np.int32), size=num_patches)
+    return make_batch(sizes, dim, nq, seed, pulse, h, gamma, rng=rng)
+
+
+# Named workloads.  Each entry: (builder kwargs, steps, periodic halo write).
+WORKLOADS = {
+    "c1_2d_p3_T16": dict(kind="uniform", num_patches=16, p=3, dim=2, steps=1, periodic=False, pulse=False),
+    "c2_2d_p16_T65536": dict(kind="uniform", num_patches=65536, p=16, dim=2, steps=10, periodic=True, pulse=True),
+    "c3_2d_mixed_T200000": dict(kind="mixed", num_patches=200000, choices=(3, 5, 9, 17), dim=2, steps=10,
+                                periodic=False, pulse=False),
+    "c4_3d_p8_T32768": dict(kind="uniform", num_patches=32768, p=8, dim=3, steps=10, periodic=False, pulse=False),
+}
+
+
+def build_workload(name: str, seed: int = 0, num_patches: int | None = None, nq: int = 5) -> tuple[Batch, dict]:
+    """Build a named workload (optionally with fewer patches for parity runs)."""
+    spec = dict(WORKLOADS[name])
+    T = num_patches if num_patches is not None else spec["num_patches"]
+    if spec["kind"] == "uniform":
+        b = make_uniform(T, spec["p"], spec["dim"], nq, seed, spec["pulse"])
+    else:
+        b = make_mixed(T, spec["choices"], spec["dim"], nq, seed, spec["pulse"])
+    return b, spec
