@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the FV patch update on one MI355X.
+
+Default workload: 65536 patches of 16 x 16 interior volumes (18 x 18 x 5
+doubles each, AoS per volume), 2D compressible Euler, Rusanov flux, FP64,
+seeded rho/u/v/w/p draws plus a Gaussian density pulse per patch, periodic
+face-halo write and the per-patch eigenvalue reduction, as one
+fv_patch_batch_update call per time step.  A "step" is one such call over the
+whole batch (one explicit Euler time step of every patch).
+
+Prints ONE JSON line with the metric (cell-updates/s over the timed steps,
+inputs resident in HBM), the roofline of the update kernel (algorithmic bytes
+per launch / average launch time, against 8 TB/s), and the CPU oracle timed on
+a bounded sample of the same workload on the host's cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_16731_amd", "csrc", "fv_update.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv_update_c2_2d_p16_T65536_traffic.md")
+
+
+def alg_bytes_per_patch(p: int, dim: int, nq: int, periodic: bool, with_lambda: bool) -> int:
+    """Bytes the method must move per patch: the face-halo-padded input (corner / edge
+    halo volumes excluded), the interior output, the periodic face-halo output, lambda."""
+    inner = p ** dim
+    faces = 2 * dim * p ** (dim - 1)
+    read = (inner + faces) * nq * 8
+    write = inner * nq * 8 + (faces * nq * 8 if periodic else 0)
+    return read + write + (8 if with_lambda else 0)
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_sha = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m_sha and m_b) or m_sha.group(1) != kernel_sha():
+        return None
+    return float(m_b.group(1))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-patches", type=int, default=65536)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the patch update is measured on a "
+              "single MI355X; sharding across GPUs is described in DESIGN.md, not run.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    fvpatch.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    name = "c2_2d_p16_T65536"
+    b, spec = wl.build_workload(name, seed=args.seed)
+    T, p, dim, nq = b.num_patches, int(b.sizes[0]), b.dim, b.nq
+    periodic = spec["periodic"]
+    flags = fvpatch.FV_HALO_PERIODIC if periodic else 0
+    h, gamma = wl.H_DEFAULT, wl.GAMMA
+
+    d_a = torch.from_numpy(b.data).to(dev)
+    d_b = d_a.clone()
+    lam = torch.empty(T, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # time step from the initial eigenvalue (outside the timed region)
+    fvpatch.fv_patch_batch_update(d_a, d_b, b.sizes, None, T, dim, nq, 1e-9, h, gamma, flags, lam, stream)
+    torch.cuda.synchronize()
+    dt = wl.CFL * h / (dim * float(lam.max().item()))
+    d_b.copy_(d_a)
+
+    def step(src, dst):
+        fvpatch.fv_patch_batch_update(src, dst, b.sizes, None, T, dim, nq, dt, h, gamma, flags, lam, stream)
+
+    for _ in range(args.warmup):
+        step(d_a, d_b)
+        d_a, d_b = d_b, d_a
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(d_a, d_b)
+        d_a, d_b = d_b, d_a
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    cells = T * p ** dim
+    value = cells * args.steps / (gpu_ms / 1e3)
+
+    per_launch = alg_bytes_per_patch(p, dim, nq, periodic, True) * T
+    achieved = per_launch / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                "kernel": "update_kernel<2,5>", "alg_bytes_per_launch": per_launch,
+                "alg_bytes_per_cell": round(per_launch / cells, 3)}
+
+    out = {
+        "metric": "cell-updates/s", "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": name, "patches": T, "p": p, "dim": dim, "unknowns": nq, "periodic_halo": periodic,
+                   "eigenvalue_reduction": True, "path": "fv_patch_batch_update", "dt": dt, "h": h},
+        "dof_updates_per_s": round(value * nq, 1),
+        "roofline": roofline,
+        "host_wall_s": round(wall, 4),
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        S = min(args.cpu_sample_patches, T)
+        steps_total = args.warmup + args.steps
+        sub = b.data[: S * int(b.offsets[1])]
+        threads = oracle.max_threads()
+        t0 = time.perf_counter()
+        ora_state, _ = oracle.run_steps(sub, b.sizes[:S], b.offsets[:S], dim, nq, [dt] * steps_total, h, gamma,
+                                        periodic, nthreads=threads)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(S * p ** dim * steps_total / cpu_s, 1), "unit": "cell-updates/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"first {S} of the {T} patches, {steps_total} steps, same dt, "
+                                         f"OpenMP over patches ({cpu_s:.2f} s wall)"}
+        # the timed GPU run advanced the same patches with the same dt: compare them
+        got = d_a[: S * int(b.offsets[1])].cpu().numpy()
+        g = got.reshape(-1, nq)
+        w = ora_state.reshape(-1, nq)
+        errs = np.max(np.abs(g - w), axis=0) / np.max(np.abs(w), axis=0)
+        out["parity_sample"] = {"patches": S, "steps": steps_total, "max_rel_err": float(np.max(errs)),
+                                "tolerance": 1e-12}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

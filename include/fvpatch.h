@@ -1,0 +1,130 @@
+/*
+ * fvpatch.h -- C ABI of the MI355X (gfx950) Finite Volume patch-update library.
+ *
+ * The library advances a batch of T small, halo-padded Cartesian patches by
+ * one explicit Euler time step of the Rusanov Finite Volume scheme for the
+ * compressible Euler equations, in IEEE FP64, and optionally returns every
+ * patch's maximum wave speed of the new solution for the CFL condition.
+ *
+ * What is computed (paper: "SYCL compute kernels for ExaHyPE",
+ * arXiv:2306.16731):
+ *   - the conservative update of a volume c (Sec. 2.2, the update formula
+ *     and Alg. 1), read as
+ *         Q_new(c) = Q(c) + (dt/h) ((D_x + D_y) + D_z),
+ *         D_n = Fhat_n(c - e_n/2) - Fhat_n(c + e_n/2);
+ *   - the Rusanov flux through a face (Eq. 2), read as
+ *         Fhat = 1/2 (F_n(Q_L) + F_n(Q_R)) - 1/2 max(l_n(Q_L), l_n(Q_R)) (Q_R - Q_L);
+ *   - the Euler user terms F_n and l_n = lambda_max,n = |u_n| + c (Sec. 2.2,
+ *     Sec. 5: B = S = delta = 0), ideal gas p = (gamma-1)(E - |m|^2/(2 rho)),
+ *     c = sqrt(gamma p / rho);
+ *   - the per-patch maximum eigenvalue of the new solution (end of Sec. 2.2):
+ *         lambda_t = max over interior c and axes n < d of l_n(Q_new(c)),
+ *     NaN-propagating.
+ * Only interior and face-halo volumes are read (the ranges of Alg. 1);
+ * corner (2D) and edge/corner (3D) halo volumes never enter the result.
+ *
+ * Data layout (the kernel's input is N (p+2)^d T doubles including the halo,
+ * Sec. 2.3): patch t of interior size p_t starts at double offset offsets[t]
+ * of the buffer; its (p_t+2)^d volumes are stored x fastest, then y, then z,
+ * each volume holding its N unknowns contiguously (array of structures):
+ *     index(t, i, j, k, q) = offsets[t] + ((k (p_t+2) + j) (p_t+2) + i) N + q,
+ *     i, j, k in [0, p_t + 1], halo volumes at 0 and p_t + 1.
+ * Unknowns: N = 5, Q = (rho, m_x, m_y, m_z, E), in 2D and 3D (in 2D m_z is
+ * a passive momentum: advected, no z flux, part of the kinetic energy); or
+ * N = 4, Q = (rho, m_x, m_y, E), in 2D (the paper's N = 2 + d).
+ *
+ * Output: the update writes the new interior volumes of every patch into the
+ * output buffer at the SAME offsets.  With FV_HALO_PERIODIC it also writes
+ * each patch's face halo as the self-wrap of its new interior (halo 0 takes
+ * interior p, halo p+1 takes interior 1, per axis; corners untouched), so the
+ * output can be fed straight back as the next step's input.  Other output
+ * volumes are not touched.  Input and output must not overlap (use two
+ * buffers and swap them between steps).
+ *
+ * Memory and ownership: patch and lambda buffers are DEVICE memory owned by
+ * the caller; `sizes` and `offsets` are HOST arrays owned by the caller and
+ * read during the call only.  The library owns only internal descriptor
+ * buffers, plans and servers, freed by their destroy calls.
+ *
+ * Streams: calls that take `stream` (a hipStream_t; NULL = the null stream)
+ * enqueue work on it and return without waiting for the device.  Results are
+ * valid once the stream has been synchronised.
+ *
+ * Errors: every call returns an fv_status.  All argument checks run on the
+ * host before any device work is enqueued; on error nothing is enqueued and
+ * fv_last_error() returns a human-readable detail (thread-local).  Device
+ * faults surface at the caller's next synchronisation, as HIP errors.
+ */
+#ifndef FVPATCH_H
+#define FVPATCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fv_status {
+    FV_OK = 0,
+    FV_ERR_INVALID_ARG = -1, /* null pointer, bad value, bad alignment, size out of range */
+    FV_ERR_UNSUPPORTED = -2, /* valid request this build does not implement (dim, N, p, device) */
+    FV_ERR_NO_DEVICE = -3,   /* no HIP device visible */
+    FV_ERR_LAUNCH = -4,      /* a HIP call failed while enqueueing work */
+    FV_ERR_OOM = -5,         /* device or pinned host allocation failed */
+    FV_ERR_BUDGET = -6,      /* serving: request exceeds the device-memory budget */
+    FV_ERR_OVERLAP = -7      /* buffers or patch ranges overlap */
+} fv_status;
+
+/* flags */
+#define FV_HALO_PERIODIC 0x2u /* also write the self-wrapped face halo of each output patch */
+
+/* Largest interior size per axis this build accepts, per dimension. */
+#define FV_MAX_P_2D 64
+#define FV_MAX_P_3D 24
+
+/*
+ * fv_patch_batch_update -- one explicit Euler step over a batch of patches
+ * (the plain per-batch launch).
+ *
+ *   patches_in   device, read-only: all input patches (layout above).
+ *   patches_out  device: receives the new interior (and the periodic face
+ *                halo) of every patch at the same offsets; must not overlap
+ *                patches_in over the batch's extent (FV_ERR_OVERLAP).
+ *   sizes        host [num_patches]: interior volumes per axis p_t,
+ *                1 <= p_t <= FV_MAX_P_2D (2D) / FV_MAX_P_3D (3D).
+ *   offsets      host [num_patches]: start of patch t in doubles (>= 0); the
+ *                patches' ranges must not overlap (FV_ERR_OVERLAP).  NULL
+ *                means contiguous patches, offsets[t] = t (p+2)^d N, and then
+ *                every sizes[t] must be equal.
+ *   num_patches  T >= 0; T == 0 is a no-op that returns FV_OK.
+ *   dim          2 or 3.
+ *   unknowns     N: 5 (2D, 3D) or 4 (2D).
+ *   dt, h        time step size and mesh width: finite and > 0.
+ *   gamma        ratio of specific heats: finite and > 1.
+ *   flags        0 or FV_HALO_PERIODIC.
+ *   lambda_out   device [num_patches] or NULL: per-patch max eigenvalue of
+ *                the new solution; NULL skips the reduction.
+ *   stream       hipStream_t or NULL.
+ * Pointers must be 8-byte aligned.  The call is re-entrant; calls on the same
+ * device share internal descriptor buffers guarded by events.
+ */
+fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
+                                const int32_t *sizes, const int64_t *offsets,
+                                int32_t num_patches, int32_t dim, int32_t unknowns,
+                                double dt, double h, double gamma, uint32_t flags,
+                                double *lambda_out, void *stream);
+
+/* Text for a status code (static storage). */
+const char *fv_status_string(fv_status status);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *fv_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t fv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVPATCH_H */

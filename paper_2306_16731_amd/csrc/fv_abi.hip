@@ -1,0 +1,293 @@
+// fv_abi.hip -- host side of the C ABI declared in include/fvpatch.h:
+// argument validation, status strings, per-device context, and the plain
+// per-batch launch of the patch-update kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fvpatch.h"
+#include "fv_internal.h"
+#include "fv_host.h"
+
+namespace fv {
+
+static thread_local std::string g_last_error;
+
+fv_status fail(fv_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int max_p(int dim) { return dim == 2 ? FV_MAX_P_2D : FV_MAX_P_3D; }
+
+int64_t patch_doubles(int p, int dim, int nq) {
+    int64_t w = p + 2;
+    return (dim == 2 ? w * w : w * w * w) * nq;
+}
+
+fv_status check_scalars(int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags) {
+    if (dim != 2 && dim != 3) return fail(FV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", dim);
+    if (!(nq == 5 || (dim == 2 && nq == 4))) {
+        if (nq == 4 || nq == 5) return fail(FV_ERR_UNSUPPORTED, "unknowns=%d is not supported in %dD", nq, dim);
+        return fail(FV_ERR_INVALID_ARG, "unknowns must be 5 (2D/3D) or 4 (2D) (got %d)", nq);
+    }
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (!std::isfinite(h) || !(h > 0.0)) return fail(FV_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (!std::isfinite(gamma) || !(gamma > 1.0)) return fail(FV_ERR_INVALID_ARG, "gamma must be finite and > 1");
+    if (flags & ~FV_HALO_PERIODIC) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~FV_HALO_PERIODIC);
+    return FV_OK;
+}
+
+static bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+static bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) {
+    return a0 < b1 && b0 < a1;
+}
+
+fv_status check_batch(const double *in, const double *out, const int32_t *sizes, const int64_t *offsets,
+                      int32_t num_patches, int32_t dim, int32_t nq, const double *lambda_out,
+                      BatchShape *shape) {
+    if (!in || !out || !sizes) return fail(FV_ERR_INVALID_ARG, "patches_in, patches_out and sizes must be non-null");
+    if (!aligned8(in) || !aligned8(out) || (lambda_out && !aligned8(lambda_out)))
+        return fail(FV_ERR_INVALID_ARG, "device pointers must be 8-byte aligned");
+    const int pmax = max_p(dim);
+    shape->uniform_p = sizes[0];
+    shape->contiguous = offsets == nullptr;
+    int64_t lo = INT64_MAX, hi = 0;
+    for (int32_t t = 0; t < num_patches; ++t) {
+        const int32_t p = sizes[t];
+        if (p < 1 || p > pmax) return fail(FV_ERR_INVALID_ARG, "sizes[%d]=%d outside [1, %d] for %dD", t, p, pmax, dim);
+        if (p != shape->uniform_p) shape->uniform_p = -1;
+    }
+    if (offsets == nullptr) {
+        if (shape->uniform_p < 0) return fail(FV_ERR_INVALID_ARG, "offsets == NULL requires equal sizes");
+        lo = 0;
+        hi = patch_doubles(shape->uniform_p, dim, nq) * (int64_t)num_patches;
+    } else {
+        bool sorted = true;
+        int64_t prev_end = -1;
+        for (int32_t t = 0; t < num_patches; ++t) {
+            const int64_t o = offsets[t];
+            if (o < 0) return fail(FV_ERR_INVALID_ARG, "offsets[%d]=%lld is negative", t, (long long)o);
+            const int64_t e = o + patch_doubles(sizes[t], dim, nq);
+            lo = std::min(lo, o);
+            hi = std::max(hi, e);
+            if (o < prev_end) sorted = false;
+            prev_end = std::max(prev_end, e);
+        }
+        if (!sorted) {
+            std::vector<std::pair<int64_t, int64_t>> r(num_patches);
+            for (int32_t t = 0; t < num_patches; ++t) r[t] = {offsets[t], offsets[t] + patch_doubles(sizes[t], dim, nq)};
+            std::sort(r.begin(), r.end());
+            for (int32_t t = 1; t < num_patches; ++t)
+                if (r[t].first < r[t - 1].second) return fail(FV_ERR_OVERLAP, "patch ranges overlap");
+        }
+    }
+    shape->lo = lo;
+    shape->hi = hi;
+    const uintptr_t in0 = reinterpret_cast<uintptr_t>(in + lo), in1 = reinterpret_cast<uintptr_t>(in + hi);
+    const uintptr_t o0 = reinterpret_cast<uintptr_t>(out + lo), o1 = reinterpret_cast<uintptr_t>(out + hi);
+    if (ranges_overlap(in0, in1, o0, o1)) return fail(FV_ERR_OVERLAP, "patches_in and patches_out overlap");
+    if (lambda_out) {
+        const uintptr_t l0 = reinterpret_cast<uintptr_t>(lambda_out), l1 = reinterpret_cast<uintptr_t>(lambda_out + num_patches);
+        if (ranges_overlap(l0, l1, o0, o1) || ranges_overlap(l0, l1, in0, in1))
+            return fail(FV_ERR_OVERLAP, "lambda_out overlaps the patch buffers");
+    }
+    return FV_OK;
+}
+
+// ---------------------------------------------------------------- device context
+struct DescSlot {
+    void *host = nullptr;    // pinned staging
+    void *dev = nullptr;     // device copy
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+struct DeviceContext {
+    int device = -1;
+    bool ok = false;
+    std::string arch;
+    std::mutex mu;
+    static constexpr int kSlots = 4;
+    DescSlot slots[kSlots];
+    int next = 0;
+};
+
+static std::mutex g_ctx_mu;
+static std::vector<DeviceContext *> g_ctx;
+
+fv_status current_context(DeviceContext **out) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(FV_ERR_NO_DEVICE, "no HIP device visible");
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FV_ERR_NO_DEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    if ((int)g_ctx.size() < n) g_ctx.resize(n, nullptr);
+    if (!g_ctx[dev]) {
+        auto *c = new DeviceContext();
+        c->device = dev;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            c->arch = prop.gcnArchName;
+            c->ok = c->arch.rfind("gfx950", 0) == 0;
+        }
+        g_ctx[dev] = c;
+    }
+    DeviceContext *c = g_ctx[dev];
+    if (!c->ok) return fail(FV_ERR_UNSUPPORTED, "device %d is '%s'; this library is built for gfx950 only", dev, c->arch.c_str());
+    *out = c;
+    return FV_OK;
+}
+
+// Take a descriptor slot with at least `bytes` of pinned and device memory,
+// waiting for the last launch that used it.
+fv_status acquire_slot(DeviceContext *c, size_t bytes, DescSlot **out) {
+    std::lock_guard<std::mutex> g(c->mu);
+    DescSlot &s = c->slots[c->next];
+    c->next = (c->next + 1) % DeviceContext::kSlots;
+    if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(FV_ERR_LAUNCH, "descriptor event wait failed");
+    if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+        return fail(FV_ERR_LAUNCH, "hipEventCreate failed");
+    if (s.cap < bytes) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        s.host = s.dev = nullptr;
+        s.cap = 0;
+        size_t cap = std::max<size_t>(bytes, 1 << 16);
+        if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) return fail(FV_ERR_OOM, "pinned allocation of %zu bytes failed", cap);
+        if (hipMalloc(&s.dev, cap) != hipSuccess) return fail(FV_ERR_OOM, "device allocation of %zu bytes failed", cap);
+        s.cap = cap;
+    }
+    *out = &s;
+    return FV_OK;
+}
+
+fv_status release_slot(DescSlot *s, hipStream_t stream) {
+    if (hipEventRecord(s->done, stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "hipEventRecord failed");
+    s->used = true;
+    return FV_OK;
+}
+
+// Plain per-batch launch; arguments already validated.
+fv_status plain_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets,
+                       int32_t T, int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags,
+                       double *lambda_out, hipStream_t stream, const BatchShape &shape) {
+    DeviceContext *ctx = nullptr;
+    fv_status st = current_context(&ctx);
+    if (st != FV_OK) return st;
+    UpdateLaunch L;
+    L.in = in;
+    L.out = out;
+    L.dim = dim;
+    L.nq = nq;
+    L.r = dt / h;
+    L.gamma = gamma;
+    L.flags = flags;
+    L.lambda_out = lambda_out;
+    if (shape.contiguous) {
+        L.num_items = T;
+        L.p = shape.uniform_p;
+        L.stride = patch_doubles(L.p, dim, nq);
+        hipError_t e = launch_update(L, stream);
+        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
+        return FV_OK;
+    }
+    // Group the patches by size (counting sort), upload (offset, id) lists.
+    const int pmax = max_p(dim);
+    std::vector<int32_t> count(pmax + 2, 0);
+    for (int32_t t = 0; t < T; ++t) count[sizes[t]]++;
+    std::vector<int32_t> start(pmax + 2, 0);
+    for (int p = 1; p <= pmax + 1; ++p) start[p] = start[p - 1] + count[p - 1];
+    const size_t bytes = (size_t)T * (sizeof(int64_t) + sizeof(int32_t));
+    DescSlot *slot = nullptr;
+    st = acquire_slot(ctx, bytes, &slot);
+    if (st != FV_OK) return st;
+    int64_t *hoff = static_cast<int64_t *>(slot->host);
+    int32_t *hid = reinterpret_cast<int32_t *>(hoff + T);
+    std::vector<int32_t> fill(start);
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t k = fill[sizes[t]]++;
+        hoff[k] = offsets[t];
+        hid[k] = t;
+    }
+    if (hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
+        (void)release_slot(slot, stream);
+        return fail(FV_ERR_LAUNCH, "descriptor upload failed");
+    }
+    const int64_t *doff = static_cast<const int64_t *>(slot->dev);
+    const int32_t *did = reinterpret_cast<const int32_t *>(doff + T);
+    for (int p = pmax; p >= 1; --p) {  // largest patches first
+        if (!count[p]) continue;
+        L.num_items = count[p];
+        L.p = p;
+        L.offsets = doff + start[p];
+        L.ids = did + start[p];
+        hipError_t e = launch_update(L, stream);
+        if (e != hipSuccess) {
+            (void)release_slot(slot, stream);
+            return fail(FV_ERR_LAUNCH, "kernel launch failed (p=%d): %s", p, hipGetErrorString(e));
+        }
+    }
+    return release_slot(slot, stream);
+}
+
+}  // namespace fv
+
+using namespace fv;
+
+extern "C" {
+
+fv_status fv_patch_batch_update(const double *patches_in, double *patches_out, const int32_t *sizes,
+                                const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t unknowns,
+                                double dt, double h, double gamma, uint32_t flags, double *lambda_out,
+                                void *stream) {
+    clear_error();
+    fv_status st = check_scalars(dim, unknowns, dt, h, gamma, flags);
+    if (st != FV_OK) return st;
+    if (num_patches < 0) return fail(FV_ERR_INVALID_ARG, "num_patches must be >= 0");
+    if (num_patches == 0) return FV_OK;
+    BatchShape shape;
+    st = check_batch(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, lambda_out, &shape);
+    if (st != FV_OK) return st;
+    return plain_update(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, dt, h, gamma, flags,
+                        lambda_out, static_cast<hipStream_t>(stream), shape);
+}
+
+const char *fv_status_string(fv_status s) {
+    switch (s) {
+        case FV_OK: return "ok";
+        case FV_ERR_INVALID_ARG: return "invalid argument";
+        case FV_ERR_UNSUPPORTED: return "unsupported";
+        case FV_ERR_NO_DEVICE: return "no device";
+        case FV_ERR_LAUNCH: return "launch failed";
+        case FV_ERR_OOM: return "out of memory";
+        case FV_ERR_BUDGET: return "over budget";
+        case FV_ERR_OVERLAP: return "overlapping buffers";
+    }
+    return "unknown status";
+}
+
+const char *fv_last_error(void) { return g_last_error.c_str(); }
+
+int32_t fv_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,34 @@
+// fv_host.h -- library-private host helpers shared by the ABI, plan and
+// serving code (validation, error reporting, per-device context).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fvpatch.h"
+
+namespace fv {
+
+struct BatchShape {
+    bool contiguous = false;  // offsets == NULL
+    int32_t uniform_p = -1;   // common interior size, -1 if mixed
+    int64_t lo = 0, hi = 0;   // extent of the batch in doubles
+};
+
+// Record an error detail for fv_last_error() and return `s`.
+fv_status fail(fv_status s, const char *fmt, ...);
+void clear_error();
+
+int max_p(int dim);
+int64_t patch_doubles(int p, int dim, int nq);
+
+fv_status check_scalars(int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags);
+fv_status check_batch(const double *in, const double *out, const int32_t *sizes, const int64_t *offsets,
+                      int32_t num_patches, int32_t dim, int32_t nq, const double *lambda_out, BatchShape *shape);
+
+struct DeviceContext;
+// Context of the current HIP device; FV_ERR_NO_DEVICE / FV_ERR_UNSUPPORTED
+// when there is none or it is not a gfx950.
+fv_status current_context(DeviceContext **out);
+
+}  // namespace fv

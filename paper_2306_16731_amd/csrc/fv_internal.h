@@ -1,0 +1,41 @@
+// fv_internal.h -- library-private declarations shared by the host ABI code and
+// the kernel launchers (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fv {
+
+// One launch of the patch-update kernel over `num_items` patches of one size.
+struct UpdateLaunch {
+    const double *in = nullptr;
+    double *out = nullptr;
+    const int64_t *offsets = nullptr;  // device [num_items] or null: item * stride
+    const int32_t *ids = nullptr;      // device [num_items] or null: lambda index = item
+    int32_t num_items = 0;
+    int32_t p = 0;                     // interior volumes per axis
+    int32_t dim = 2;
+    int32_t nq = 5;
+    int64_t stride = 0;                // doubles per patch when offsets == null
+    double r = 0.0;                    // dt / h
+    double gamma = 1.4;
+    uint32_t flags = 0;
+    double *lambda_out = nullptr;      // device [max id + 1] or null
+    int32_t block = 0;                 // threads per block, 0 = default choice
+};
+
+// Lanes one patch occupies (its cross-section plane including halo volumes).
+inline int plane_lanes(int p, int dim) { return dim == 2 ? (p + 2) : (p + 2) * (p + 2); }
+
+// Default block size: the multiple of 64 in [lanes, 1024] with the best lane
+// utilisation, smallest first among equals.
+int default_block(int p, int dim);
+
+// Dynamic LDS bytes a block of `block` threads needs.
+size_t update_lds_bytes(int dim, int nq, int block);
+
+// Enqueue one update launch; returns hipSuccess or the launch error.
+hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream);
+
+}  // namespace fv

@@ -1,0 +1,370 @@
+// fv_update.hip -- fused patch-update kernel for gfx950 (CDNA4, wave64).
+//
+// One explicit Euler step of the Rusanov Finite Volume scheme for the
+// compressible Euler equations over a batch of halo-padded patches, FP64:
+//   Q_new(c) = Q(c) + (dt/h) ((D_x + D_y) + D_z),
+//   D_n      = Fhat_n(c - e_n/2) - Fhat_n(c + e_n/2)                (Sec. 2.2, Alg. 1)
+//   Fhat     = 1/2 (F_n(Q_L) + F_n(Q_R)) - 1/2 max(l_n(Q_L), l_n(Q_R)) (Q_R - Q_L)  (Eq. 2)
+//   l_n      = |u_n| + c                                            (Sec. 2.2)
+// plus the per-patch maximum of l_n over the new interior (end of Sec. 2.2).
+//
+// Work mapping.  A patch's lanes cover its cross-section plane, halo volumes
+// included: (p+2) lanes along x in 2D, (p+2)^2 lanes over (x, y) in 3D.  Each
+// lane marches along the last axis (y in 2D, z in 3D) through the p+2 layers
+// of the patch.  At every layer a lane
+//   1. reads its volume (the next layer's read is already in flight),
+//   2. evaluates the user terms once: 1/rho, p, c, then F_n and l_n for the
+//      axes its volume's faces need,
+//   3. publishes (Q, F_n, l_n) of the in-plane axes in LDS and computes the
+//      in-plane face to its left from its neighbour's entry -- every face flux
+//      is formed exactly once and read back by the volume on its other side,
+//   4. forms the marching-axis face below it from the previous layer, kept in
+//      registers, and
+//   5. completes the volume of the previous layer, stores it, and folds its
+//      wave speeds into a running maximum.
+// Only interior and face-halo volumes are ever read; corner / edge halo
+// volumes are skipped.  Several patches share a block when they fit.
+//
+// Arithmetic.  The Euler terms are written with explicit fused multiply-adds
+// and contraction disabled, so every code path (in-plane or marching axis,
+// halo or interior lane) rounds identically: constant states are reproduced
+// bitwise, mirror images and x/y swaps give bitwise mirrored results.  The
+// kernel is HBM bound (no dense contraction, no MFMA).
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fv_internal.h"
+
+namespace fv {
+namespace {
+
+constexpr uint32_t kPeriodic = 0x2u;
+
+// NaN-propagating maximum: a NaN in either argument gives NaN.
+__device__ __forceinline__ double nanmax(double a, double b) {
+    return (a != a || a > b) ? a : b;
+}
+
+// Barrier for LDS traffic only: waits for this wave's LDS operations, not for
+// its outstanding global loads (the next layer's prefetch stays in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Per-volume quantities the user terms share across axes.
+template <int NQ>
+struct Prim {
+    double rinv;  // 1 / rho
+    double p;     // pressure
+    double c;     // speed of sound
+};
+
+#pragma clang fp contract(off)
+
+// Ideal-gas pressure and sound speed of a volume.
+template <int NQ>
+__device__ __forceinline__ Prim<NQ> primitives(const double (&q)[NQ], double gamma) {
+    Prim<NQ> a;
+    a.rinv = 1.0 / q[0];
+    double m2 = q[1] * q[1] + q[2] * q[2];
+    if constexpr (NQ == 5) m2 = m2 + q[3] * q[3];
+    double e = __builtin_fma(-0.5 * m2, a.rinv, q[NQ - 1]);  // E - |m|^2 / (2 rho)
+    a.p = (gamma - 1.0) * e;
+    a.c = __builtin_sqrt(gamma * a.p * a.rinv);
+    return a;
+}
+
+// F_n(Q) and l_n(Q) along axis n.
+template <int NQ>
+__device__ __forceinline__ void euler_flux(const double (&q)[NQ], const Prim<NQ> &a, int n,
+                                           double (&f)[NQ], double &lam) {
+    const double un = q[1 + n] * a.rinv;
+    f[0] = q[1 + n];
+#pragma unroll
+    for (int b = 0; b < NQ - 2; ++b)
+        f[1 + b] = (b == n) ? __builtin_fma(q[1 + b], un, a.p) : q[1 + b] * un;
+    f[NQ - 1] = (q[NQ - 1] + a.p) * un;
+    lam = __builtin_fabs(un) + a.c;
+}
+
+// Rusanov face flux from the left (L) and right (R) volume of a face.
+template <int NQ>
+__device__ __forceinline__ void rusanov(const double (&qL)[NQ], const double (&fL)[NQ], double lL,
+                                        const double (&qR)[NQ], const double (&fR)[NQ], double lR,
+                                        double (&fh)[NQ]) {
+    const double s = 0.5 * nanmax(lL, lR);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        fh[k] = __builtin_fma(-s, qR[k] - qL[k], 0.5 * (fL[k] + fR[k]));
+}
+
+// Largest wave speed of a volume over the axes n < D.
+template <int D, int NQ>
+__device__ __forceinline__ double volume_lambda(const double (&q)[NQ], double gamma) {
+    Prim<NQ> a = primitives<NQ>(q, gamma);
+    double l = 0.0;
+#pragma unroll
+    for (int n = 0; n < D; ++n) l = nanmax(l, __builtin_fabs(q[1 + n] * a.rinv) + a.c);
+    return l;
+}
+
+#pragma clang fp contract(on)
+
+template <int NQ>
+__device__ __forceinline__ void load_volume(const double *__restrict__ src, double (&q)[NQ]) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = src[k];
+}
+
+template <int NQ>
+__device__ __forceinline__ void store_volume(double *__restrict__ dst, const double (&q)[NQ]) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) dst[k] = q[k];
+}
+
+// LDS per lane (structure of arrays over the block's lanes, so consecutive
+// lanes hit consecutive 8-byte words):
+//   XQ[NQ], XF[D-1][NQ], XL[D-1]   the volume's state and in-plane user terms
+//   FH[D-1][NQ]                    the in-plane face flux to the lane's left
+template <int D, int NQ>
+struct Lds {
+    static constexpr int kXQ = 0;
+    static constexpr int kXF = NQ;
+    static constexpr int kXL = kXF + (D - 1) * NQ;
+    static constexpr int kFH = kXL + (D - 1);
+    static constexpr int kWords = kFH + (D - 1) * NQ;
+};
+
+template <int D, int NQ, int MAXB>
+__global__ void __launch_bounds__(MAXB)
+update_kernel(const double *__restrict__ in, double *__restrict__ out,
+              const int64_t *__restrict__ offsets, const int32_t *__restrict__ ids,
+              int32_t num_items, int32_t P, int64_t stride, double r, double gamma,
+              uint32_t flags, double *__restrict__ lambda_out) {
+    extern __shared__ double lds[];
+    using L = Lds<D, NQ>;
+    const int B = blockDim.x;
+    const int W = P + 2;
+    const int S = (D == 2) ? W : W * W;
+    const int ppb = B / S;
+    const int tid = threadIdx.x;
+    const int slot = tid / S;
+    const int l = tid - slot * S;
+    const int i = (D == 2) ? l : l % W;
+    const int j = (D == 2) ? 1 : l / W;
+    const int64_t item = (int64_t)blockIdx.x * ppb + slot;
+    const bool active = slot < ppb && item < num_items;
+
+    const bool xin = i >= 1 && i <= P;
+    const bool yin = j >= 1 && j <= P;
+    const bool pint = xin && yin;                 // plane-interior lane
+    const bool xhalo = !xin && yin;               // x face-halo lane
+    const bool yhalo = (D == 3) && xin && !yin;   // y face-halo lane (3D)
+    const bool used = active && (pint || xhalo || yhalo);
+
+    const int64_t off = active ? (offsets ? offsets[item] : item * stride) : 0;
+    const int64_t lane_off = (D == 2) ? (int64_t)i * NQ : ((int64_t)j * W + i) * NQ;
+    const int64_t layer = (int64_t)S * NQ;        // doubles between marching layers
+    const double *src = in + off + lane_off;
+    double *dst = out + off + lane_off;
+    const bool periodic = (flags & kPeriodic) != 0;
+
+    // Registers carried from one layer to the next (marching axis m = D-1).
+    double qprev[NQ], fmprev[NQ], lmprev = 0.0, fhprev[NQ], dinprev[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) { qprev[k] = fmprev[k] = fhprev[k] = dinprev[k] = 0.0; }
+    double lmax = 0.0;
+
+    double qnext[NQ];
+    if (used && pint) load_volume<NQ>(src, qnext);     // layer 0: only the plane interior
+
+    for (int k = 0; k < W; ++k) {
+        const bool inner = k >= 1 && k <= P;           // layer k is an interior layer
+        const bool live = used && (pint || inner);
+        double q[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q[c] = qnext[c];
+        // prefetch layer k + 1
+        if (k + 1 < W) {
+            const bool live1 = used && (pint || (k + 1 <= P));
+            if (live1) load_volume<NQ>(src + (k + 1) * layer, qnext);
+        }
+
+        Prim<NQ> a;
+        double fm[NQ], lm = 0.0;
+        if (live) {
+            a = primitives<NQ>(q, gamma);
+            // in-plane user terms, published for the neighbours
+            if (inner) {
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) lds[(L::kXQ + c) * B + tid] = q[c];
+#pragma unroll
+                for (int n = 0; n < D - 1; ++n) {
+                    const bool need = pint || (n == 0 ? xhalo : yhalo);
+                    if (need) {
+                        double f[NQ], lam;
+                        euler_flux<NQ>(q, a, n, f, lam);
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lds[(L::kXF + n * NQ + c) * B + tid] = f[c];
+                        lds[(L::kXL + n) * B + tid] = lam;
+                    }
+                }
+            }
+            if (pint) euler_flux<NQ>(q, a, D - 1, fm, lm);
+        }
+        lds_barrier();
+
+        // in-plane face to the lane's left (faces at coordinate - 1/2, for
+        // coordinates 1 .. p+1), formed once and published
+        if (active && inner) {
+#pragma unroll
+            for (int n = 0; n < D - 1; ++n) {
+                const int cn = (n == 0) ? i : j;
+                const bool other_in = (n == 0) ? yin : xin;
+                if (other_in && cn >= 1 && cn <= P + 1) {
+                    const int nb = tid - ((n == 0) ? 1 : W);
+                    double qL[NQ], fL[NQ], fR[NQ], lR, fh[NQ];
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) {
+                        qL[c] = lds[(L::kXQ + c) * B + nb];
+                        fL[c] = lds[(L::kXF + n * NQ + c) * B + nb];
+                        fR[c] = lds[(L::kXF + n * NQ + c) * B + tid];
+                    }
+                    const double lL = lds[(L::kXL + n) * B + nb];
+                    lR = lds[(L::kXL + n) * B + tid];
+                    rusanov<NQ>(qL, fL, lL, q, fR, lR, fh);
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) lds[(L::kFH + n * NQ + c) * B + tid] = fh[c];
+                }
+            }
+        }
+        lds_barrier();
+
+        if (active && pint) {
+            // in-plane differences of this layer's volume: D_x (+ D_y)
+            double din[NQ];
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) din[c] = 0.0;
+            if (inner) {
+#pragma unroll
+                for (int n = 0; n < D - 1; ++n) {
+                    const int nb = tid + ((n == 0) ? 1 : W);
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) {
+                        const double d = lds[(L::kFH + n * NQ + c) * B + tid] - lds[(L::kFH + n * NQ + c) * B + nb];
+                        din[c] = (n == 0) ? d : din[c] + d;
+                    }
+                }
+            }
+            // marching-axis face between layers k-1 and k
+            double fh[NQ];
+            if (k >= 1) rusanov<NQ>(qprev, fmprev, lmprev, q, fm, lm, fh);
+            // complete the volume of layer k-1
+            if (k >= 2) {
+                double qn[NQ];
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) {
+                    const double dsum = dinprev[c] + (fhprev[c] - fh[c]);
+                    qn[c] = __builtin_fma(r, dsum, qprev[c]);
+                }
+                const int kk = k - 1;
+                store_volume<NQ>(dst + kk * layer, qn);
+                if (periodic) {
+                    if (i == P) store_volume<NQ>(dst + kk * layer - (int64_t)P * NQ, qn);
+                    if (i == 1) store_volume<NQ>(dst + kk * layer + (int64_t)P * NQ, qn);
+                    if (D == 3) {
+                        if (j == P) store_volume<NQ>(dst + kk * layer - (int64_t)P * W * NQ, qn);
+                        if (j == 1) store_volume<NQ>(dst + kk * layer + (int64_t)P * W * NQ, qn);
+                    }
+                    if (kk == P) store_volume<NQ>(dst, qn);
+                    if (kk == 1) store_volume<NQ>(dst + (int64_t)(P + 1) * layer, qn);
+                }
+                if (lambda_out) lmax = nanmax(lmax, volume_lambda<D, NQ>(qn, gamma));
+            }
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                qprev[c] = q[c];
+                fmprev[c] = fm[c];
+                fhprev[c] = fh[c];
+                dinprev[c] = din[c];
+            }
+            lmprev = lm;
+        }
+    }
+
+    if (lambda_out) {
+        // per-patch maximum over the patch's lanes (NaN-propagating)
+        lds[tid] = lmax;
+        lds_barrier();
+        if (active && l == 0) {
+            double m = 0.0;
+            for (int t = 0; t < S; ++t) m = nanmax(m, lds[tid + t]);
+            lambda_out[ids ? ids[item] : item] = m;
+        }
+    }
+}
+
+template <int D, int NQ>
+hipError_t launch_typed(const UpdateLaunch &L, hipStream_t stream) {
+    const int S = plane_lanes(L.p, L.dim);
+    const int B = L.block > 0 ? L.block : default_block(L.p, L.dim);
+    if (B % 64 != 0 || B > 1024 || B < S) return hipErrorInvalidConfiguration;
+    const int ppb = B / S;
+    const int64_t blocks = ((int64_t)L.num_items + ppb - 1) / ppb;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const size_t lds = update_lds_bytes(L.dim, L.nq, B);
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return hipErrorInvalidDevice;
+    if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
+    if (lds > 64 * 1024) {
+        const void *fn = B <= 256 ? reinterpret_cast<const void *>(&update_kernel<D, NQ, 256>)
+                                  : reinterpret_cast<const void *>(&update_kernel<D, NQ, 1024>);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (B <= 256)
+        hipLaunchKernelGGL((update_kernel<D, NQ, 256>), dim3((unsigned)blocks), dim3(B), lds, stream,
+                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.gamma,
+                           L.flags, L.lambda_out);
+    else
+        hipLaunchKernelGGL((update_kernel<D, NQ, 1024>), dim3((unsigned)blocks), dim3(B), lds, stream,
+                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.gamma,
+                           L.flags, L.lambda_out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int default_block(int p, int dim) {
+    const int S = plane_lanes(p, dim);
+    int best = 0;
+    double best_u = -1.0;
+    for (int B = 64; B <= 1024; B += 64) {
+        if (B < S) continue;
+        if (update_lds_bytes(dim, 5, B) > 64 * 1024) break;
+        const double u = (double)((B / S) * S) / B;
+        if (u > best_u + 1e-9) { best_u = u; best = B; }
+    }
+    if (best == 0) best = ((S + 63) / 64) * 64;
+    return best;
+}
+
+size_t update_lds_bytes(int dim, int nq, int block) {
+    const int words = (dim == 2) ? (nq == 5 ? Lds<2, 5>::kWords : Lds<2, 4>::kWords) : Lds<3, 5>::kWords;
+    return sizeof(double) * (size_t)words * (size_t)block;
+}
+
+hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream) {
+    if (L.num_items <= 0) return hipSuccess;
+    if (L.dim == 2 && L.nq == 5) return launch_typed<2, 5>(L, stream);
+    if (L.dim == 2 && L.nq == 4) return launch_typed<2, 4>(L, stream);
+    if (L.dim == 3 && L.nq == 5) return launch_typed<3, 5>(L, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fv

@@ -1,0 +1,139 @@
+"""Python binding of the C ABI in include/fvpatch.h (ctypes; argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are passed as torch tensors on the GPU (float64, contiguous) or as raw
+integer device addresses; host descriptor arrays as numpy arrays or
+sequences.  The compute runs in the HIP library ``libfvpatch.so``; there is no
+other implementation behind these names -- if the library is missing, loading
+fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # torch first: its HIP runtime is then the one the library binds to
+    import torch
+except ImportError:  # pragma: no cover - torch is part of the supported environment
+    torch = None
+
+LIBRARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfvpatch.so")
+
+FV_OK = 0
+FV_ERR_INVALID_ARG = -1
+FV_ERR_UNSUPPORTED = -2
+FV_ERR_NO_DEVICE = -3
+FV_ERR_LAUNCH = -4
+FV_ERR_OOM = -5
+FV_ERR_BUDGET = -6
+FV_ERR_OVERLAP = -7
+FV_HALO_PERIODIC = 0x2
+FV_MAX_P_2D = 64
+FV_MAX_P_3D = 24
+
+# Every symbol the header declares (checked by the tests against include/fvpatch.h).
+EXPORTS = ["fv_patch_batch_update", "fv_status_string", "fv_last_error", "fv_version"]
+
+
+class FvError(RuntimeError):
+    """A non-zero fv_status returned by the library."""
+
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status_name(status)} ({status}): {detail}")
+        self.status = status
+        self.detail = detail
+
+
+_lib = None
+
+
+def load(path: str = LIBRARY):
+    """Load libfvpatch.so (built by ``python -m paper_2306_16731_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2306_16731_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, f64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
+    lib.fv_patch_batch_update.argtypes = [vp, vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp, vp]
+    lib.fv_patch_batch_update.restype = ctypes.c_int
+    lib.fv_status_string.argtypes = [ctypes.c_int]
+    lib.fv_status_string.restype = ctypes.c_char_p
+    lib.fv_last_error.argtypes = []
+    lib.fv_last_error.restype = ctypes.c_char_p
+    lib.fv_version.argtypes = []
+    lib.fv_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _dev_ptr(x):
+    """Device address of a tensor (checked: on GPU, float64/int, contiguous) or a raw int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if torch is not None and isinstance(x, torch.Tensor):
+        if not x.is_cuda:
+            raise ValueError("device buffer must be a GPU tensor")
+        if not x.is_contiguous():
+            raise ValueError("device buffer must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"expected a GPU tensor or an int address, got {type(x)!r}")
+
+
+def _host_array(x, dtype):
+    if x is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(x, dtype=dtype))
+    return a, a.ctypes.data
+
+
+def _stream_handle(stream):
+    if stream is None:
+        if torch is not None and torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def status_name(status: int) -> str:
+    return load().fv_status_string(int(status)).decode()
+
+
+def fv_status_string(status: int) -> str:
+    return load().fv_status_string(int(status)).decode()
+
+
+def fv_last_error() -> str:
+    return load().fv_last_error().decode()
+
+
+def fv_version() -> int:
+    return int(load().fv_version())
+
+
+def _check(status: int) -> int:
+    if status != FV_OK:
+        raise FvError(status, fv_last_error())
+    return status
+
+
+def fv_patch_batch_update(patches_in, patches_out, sizes, offsets, num_patches: int, dim: int, unknowns: int,
+                          dt: float, h: float, gamma: float = 1.4, flags: int = 0, lambda_out=None,
+                          stream=None, raise_on_error: bool = True) -> int:
+    """One explicit Euler step over a batch of patches; see include/fvpatch.h."""
+    lib = load()
+    sz, sz_p = _host_array(sizes, np.int32)
+    of, of_p = _host_array(offsets, np.int64)
+    st = lib.fv_patch_batch_update(_dev_ptr(patches_in), _dev_ptr(patches_out), sz_p, of_p, int(num_patches),
+                                   int(dim), int(unknowns), float(dt), float(h), float(gamma), int(flags),
+                                   _dev_ptr(lambda_out), _stream_handle(stream))
+    del sz, of
+    return _check(st) if raise_on_error else st

@@ -1,0 +1,130 @@
+"""The C-ABI library on the host (no GPU): it loads, exports every declared
+symbol, and rejects every invalid argument before touching a device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_16731_amd import build as fvbuild
+from paper_2306_16731_amd import fvpatch as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# Fake device addresses: validation never dereferences them.
+IN = 0x10000000
+OUT = 0x20000000
+LAM = 0x30000000
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if fvbuild.stale():
+        fvbuild.build()
+    F.load()
+
+
+def declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "fvpatch.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(fv_[a-z0-9_]+)\s*\(", hdr)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(F.LIBRARY)
+    names = declared_functions()
+    assert names, "no declarations found"
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/fvpatch.h but not exported"
+    assert sorted(F.EXPORTS) == names, "binding's EXPORTS list out of date with the header"
+
+
+def test_header_constants_match_binding():
+    hdr = open(os.path.join(ROOT, "include", "fvpatch.h")).read()
+    for name in ["FV_MAX_P_2D", "FV_MAX_P_3D"]:
+        assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name)
+    assert int(re.search(r"#define FV_HALO_PERIODIC (0x[0-9a-f]+)u", hdr).group(1), 16) == F.FV_HALO_PERIODIC
+
+
+def call(**kw):
+    args = dict(patches_in=IN, patches_out=OUT, sizes=[4] * 3, offsets=None, num_patches=3, dim=2, unknowns=5,
+                dt=1e-3, h=1 / 48, gamma=1.4, flags=0, lambda_out=LAM, stream=0)
+    args.update(kw)
+    return F.fv_patch_batch_update(raise_on_error=False, **args)
+
+
+def test_status_strings():
+    assert F.fv_status_string(F.FV_OK) == "ok"
+    assert F.fv_status_string(F.FV_ERR_OVERLAP) == "overlapping buffers"
+    assert F.fv_version() >= 100
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=1), F.FV_ERR_INVALID_ARG),
+    (dict(dim=4), F.FV_ERR_INVALID_ARG),
+    (dict(unknowns=3), F.FV_ERR_INVALID_ARG),
+    (dict(dim=3, unknowns=4), F.FV_ERR_UNSUPPORTED),
+    (dict(dt=0.0), F.FV_ERR_INVALID_ARG),
+    (dict(dt=-1e-3), F.FV_ERR_INVALID_ARG),
+    (dict(dt=float("nan")), F.FV_ERR_INVALID_ARG),
+    (dict(dt=float("inf")), F.FV_ERR_INVALID_ARG),
+    (dict(h=0.0), F.FV_ERR_INVALID_ARG),
+    (dict(h=float("nan")), F.FV_ERR_INVALID_ARG),
+    (dict(gamma=1.0), F.FV_ERR_INVALID_ARG),
+    (dict(gamma=float("nan")), F.FV_ERR_INVALID_ARG),
+    (dict(flags=0x4), F.FV_ERR_INVALID_ARG),
+    (dict(num_patches=-1), F.FV_ERR_INVALID_ARG),
+    (dict(patches_in=0), F.FV_ERR_INVALID_ARG),
+    (dict(patches_out=0), F.FV_ERR_INVALID_ARG),
+    (dict(sizes=None), F.FV_ERR_INVALID_ARG),
+    (dict(patches_in=IN + 4), F.FV_ERR_INVALID_ARG),
+    (dict(lambda_out=LAM + 2), F.FV_ERR_INVALID_ARG),
+    (dict(sizes=[0, 4, 4]), F.FV_ERR_INVALID_ARG),
+    (dict(sizes=[4, 65, 4]), F.FV_ERR_INVALID_ARG),
+    (dict(dim=3, sizes=[25, 4, 4]), F.FV_ERR_INVALID_ARG),
+    (dict(sizes=[4, 5, 4]), F.FV_ERR_INVALID_ARG),           # offsets NULL needs equal sizes
+    (dict(offsets=[0, -5, 200]), F.FV_ERR_INVALID_ARG),
+    (dict(offsets=[0, 100, 400]), F.FV_ERR_OVERLAP),         # patch 0 spans 180 doubles
+    (dict(offsets=[400, 0, 100]), F.FV_ERR_OVERLAP),         # unsorted and overlapping
+    (dict(patches_out=IN + 8 * 100), F.FV_ERR_OVERLAP),      # in and out overlap
+    (dict(patches_out=IN), F.FV_ERR_OVERLAP),
+    (dict(lambda_out=OUT + 8), F.FV_ERR_OVERLAP),
+])
+def test_invalid_arguments_rejected_before_device(kw, status):
+    st = call(**kw)
+    assert st == status, (st, F.fv_last_error())
+    assert F.fv_last_error() != ""
+
+
+def test_zero_patches_is_a_noop():
+    assert call(num_patches=0, sizes=None, patches_in=0, patches_out=0) == F.FV_OK
+    assert F.fv_last_error() == ""
+
+
+def test_valid_arguments_without_a_gpu_report_no_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except ImportError:
+        pass
+    assert call() == F.FV_ERR_NO_DEVICE
+    assert call(offsets=[0, 180, 360]) == F.FV_ERR_NO_DEVICE
+    assert call(offsets=[360, 0, 180]) == F.FV_ERR_NO_DEVICE      # unsorted, disjoint
+    assert call(lambda_out=None) == F.FV_ERR_NO_DEVICE
+
+
+def test_error_raises_with_detail():
+    with pytest.raises(F.FvError) as e:
+        F.fv_patch_batch_update(IN, OUT, [4], None, 1, 5, 5, 1e-3, 1 / 48)
+    assert e.value.status == F.FV_ERR_INVALID_ARG and "dim" in e.value.detail
+
+
+def test_binding_has_no_compute_of_its_own():
+    """The binding module holds no update arithmetic (it only marshals arguments)."""
+    src = open(os.path.join(ROOT, "paper_2306_16731_amd", "fvpatch.py")).read()
+    for token in ["sqrt", "gamma - 1", "0.5 *", "rusanov", "import oracle", "from oracle"]:
+        assert token not in src.lower(), token

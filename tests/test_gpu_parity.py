@@ -1,0 +1,221 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI (needs a gfx950 GPU).
+
+Tolerance: every unknown's max-norm error, relative to that unknown's max-norm
+over the batch, must be <= 1e-12, and so must the per-patch eigenvalues'.
+Both sides get the same seeded inputs and the same time-step sequence.  The
+expected error is ~1e-15 (the kernel fuses multiply-adds and uses 1/rho times
+m instead of m / rho; the oracle rounds every operation separately).
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_16731_amd import workloads as wl
+from tests import hip_path as hp
+from tests import invariants as inv
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _announce(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dt_sequence(batch, steps, periodic, h=wl.H_DEFAULT):
+    """dt_{n+1} = CFL h / (d max lambda_n) along the oracle's own trajectory."""
+    lam0 = oracle.batch_lambda(batch.data, batch.sizes, batch.offsets, batch.dim, batch.nq)
+    dts = [wl.CFL * h / (batch.dim * float(np.max(lam0)))]
+    state = batch.data.copy()
+    buf = state.copy()
+    for _ in range(steps - 1):
+        buf, lam = oracle.batch_update(state, batch.sizes, batch.offsets, batch.dim, batch.nq, dts[-1], h,
+                                       wl.GAMMA, periodic, out=buf)
+        state, buf = buf, state
+        dts.append(wl.CFL * h / (batch.dim * float(np.max(lam))))
+    return dts
+
+
+def compare_run(batch, steps, periodic, pass_offsets=True):
+    dts = dt_sequence(batch, steps, periodic)
+    want, want_lams = oracle.run_steps(batch.data, batch.sizes, batch.offsets, batch.dim, batch.nq, dts,
+                                       wl.H_DEFAULT, wl.GAMMA, periodic)
+    got, got_lams = hp.gpu_run_steps(batch.data, batch.sizes, batch.offsets, batch.dim, batch.nq, dts,
+                                     wl.H_DEFAULT, wl.GAMMA, periodic, pass_offsets=pass_offsets)
+    errs = hp.component_errors(got, want, batch.nq)
+    lerr = max(hp.lambda_error(g, w) for g, w in zip(got_lams, want_lams))
+    assert np.all(errs <= TOL), errs
+    assert lerr <= TOL, lerr
+    return errs, lerr
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_16731_amd import fvpatch
+    fvpatch.load()
+
+
+def test_c1_golden_and_oracle():
+    _announce("c1: 16 x 3^2, 2D, one step")
+    from tests.golden import make_golden as mg
+    b, dt, want, want_lam = mg.c1_case(0)
+    for pass_offsets in (True, False):
+        got, lam = hp.gpu_step(b.data, b.sizes, b.offsets, 2, 5, dt, wl.H_DEFAULT, wl.GAMMA, False,
+                               pass_offsets=pass_offsets)
+        assert np.all(hp.component_errors(got, want, 5) <= TOL)
+        assert hp.lambda_error(lam, want_lam) <= TOL
+
+
+@pytest.mark.parametrize("pass_offsets", [False, True])
+def test_c2_reduced_periodic_10_steps(pass_offsets):
+    _announce(f"c2 reduced: 300 x 16^2, 10 steps, periodic, offsets={pass_offsets}")
+    b, _ = wl.build_workload("c2_2d_p16_T65536", seed=1, num_patches=300)
+    compare_run(b, 10, True, pass_offsets)
+
+
+def test_c3_reduced_mixed_sizes():
+    _announce("c3 reduced: 1500 mixed {3,5,9,17}^2, 10 steps")
+    b, _ = wl.build_workload("c3_2d_mixed_T200000", seed=2, num_patches=1500)
+    compare_run(b, 10, False)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_c4_reduced_3d(periodic):
+    _announce(f"c4 reduced: 200 x 8^3, 10 steps, periodic={periodic}")
+    b, _ = wl.build_workload("c4_3d_p8_T32768", seed=3, num_patches=200)
+    compare_run(b, 10, periodic, pass_offsets=False)
+
+
+def test_two_d_n4():
+    _announce("2D N=4: 257 x 7^2, 5 steps")
+    b = wl.make_uniform(257, 7, dim=2, nq=4, seed=4, pulse=True)
+    compare_run(b, 5, True)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (2, 31), (2, 62), (2, 63), (2, 64), (3, 1), (3, 2), (3, 7),
+                                   (3, 14), (3, 15), (3, 24)])
+def test_sizes_edge(dim, p):
+    _announce(f"edge sizes: dim={dim} p={p}")
+    T = 5 if p > 20 else 37
+    b = wl.make_uniform(T, p, dim=dim, nq=5, seed=10 + p)
+    compare_run(b, 2, True, pass_offsets=False)
+    compare_run(b, 1, False, pass_offsets=True)
+
+
+def test_ragged_offsets_with_gaps_unsorted_and_odd():
+    """Patches at unsorted offsets with gaps, some starting at odd doubles (8- not 16-byte aligned)."""
+    _announce("ragged offsets")
+    rng = np.random.Generator(np.random.PCG64(77))
+    sizes = rng.choice(np.array([1, 3, 4, 9, 16, 17, 30], np.int32), size=211)
+    vols = (sizes.astype(np.int64) + 2) ** 2 * 5
+    gaps = rng.integers(0, 7, size=len(sizes))
+    starts = np.cumsum(np.concatenate([[3], (vols + gaps)[:-1]])).astype(np.int64)
+    perm = rng.permutation(len(sizes))
+    total = int(starts[-1] + vols[-1] + 5)
+    compact = wl.make_batch(sizes, 2, 5, seed=78)
+    data = rng.uniform(-1, 1, total)  # filler between patches: must stay untouched
+    for t in range(len(sizes)):
+        data[starts[t]:starts[t] + vols[t]] = compact.data[compact.offsets[t]:compact.offsets[t] + vols[t]]
+    s2, o2 = sizes[perm], starts[perm]
+    dts = [1.1e-3, 1.3e-3, 0.9e-3]
+    want, want_lams = oracle.run_steps(data, s2, o2, 2, 5, dts, wl.H_DEFAULT, wl.GAMMA, True)
+    got, got_lams = hp.gpu_run_steps(data, s2, o2, 2, 5, dts, wl.H_DEFAULT, wl.GAMMA, True)
+    mask = np.ones(total, bool)
+    for t in range(len(sizes)):
+        mask[starts[t]:starts[t] + vols[t]] = False
+    assert np.array_equal(got[mask], data[mask]), "bytes outside the patches were written"
+    inside = ~mask
+    assert np.all(hp.component_errors(got[inside], want[inside], 5) <= TOL)
+    assert max(hp.lambda_error(g, w) for g, w in zip(got_lams, want_lams)) <= TOL
+
+
+def test_single_patch_and_zero_patches():
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    b = wl.make_uniform(1, 16, seed=5)
+    compare_run(b, 3, True, pass_offsets=False)
+    d = torch.zeros(10, dtype=torch.float64, device="cuda")
+    assert fvpatch.fv_patch_batch_update(d, d, [], None, 0, 2, 5, 1e-3, 1 / 48) == 0
+
+
+def test_deterministic_bitwise():
+    b = wl.make_mixed(700, seed=6)
+    r1 = hp.gpu_step(b.data, b.sizes, b.offsets, 2, 5, 1.3e-3, wl.H_DEFAULT, wl.GAMMA, True)
+    r2 = hp.gpu_step(b.data, b.sizes, b.offsets, 2, 5, 1.3e-3, wl.H_DEFAULT, wl.GAMMA, True)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+
+
+def test_c2_full_size_sampled():
+    """Config 2 at its full size (65536 x 16^2, 10 steps, periodic) in the launch the benchmark
+    times; 96 sampled patches re-run by the oracle with the same dt sequence."""
+    _announce("c2 full size: 65536 x 16^2, 10 steps, sampled check")
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    b, spec = wl.build_workload("c2_2d_p16_T65536", seed=0)
+    T = b.num_patches
+    rng = np.random.Generator(np.random.PCG64(99))
+    sample = np.sort(rng.choice(T, size=96, replace=False))
+    sample = np.unique(np.concatenate([[0, T - 1], sample]))
+    stride = int(b.offsets[1])
+    sub = np.concatenate([b.data[t * stride:(t + 1) * stride] for t in sample])
+    sub_sizes = b.sizes[sample]
+    sub_off = np.arange(len(sample), dtype=np.int64) * stride
+    dts = [1.9e-3 * (1 + 0.01 * s) for s in range(10)]
+    want, want_lams = oracle.run_steps(sub, sub_sizes, sub_off, 2, 5, dts, wl.H_DEFAULT, wl.GAMMA, True)
+    a = hp.to_dev(b.data)
+    bb = a.clone()
+    lam = torch.empty(T, dtype=torch.float64, device="cuda")
+    for dt in dts:
+        fvpatch.fv_patch_batch_update(a, bb, b.sizes, None, T, 2, 5, dt, wl.H_DEFAULT, wl.GAMMA,
+                                      fvpatch.FV_HALO_PERIODIC, lam)
+        a, bb = bb, a
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(sample).to("cuda")
+    got = a.view(T, stride)[idx].cpu().numpy().reshape(-1)
+    got_lam = lam[idx].cpu().numpy()
+    assert np.all(hp.component_errors(got, want, 5) <= TOL)
+    assert hp.lambda_error(got_lam, want_lams[-1]) <= TOL
+    # every patch's state stays physical and finite
+    assert torch.isfinite(a).all().item() and torch.isfinite(lam).all().item()
+    del a, bb
+
+
+# --------------------------------------------------------------------- the invariant suite on the HIP path
+INV_CASES = [(2, 5), (2, 4), (3, 5)]
+
+
+@pytest.mark.parametrize("step", [hp.gpu_step, hp.gpu_step_contiguous], ids=["offsets", "contiguous"])
+@pytest.mark.parametrize("dim,nq", INV_CASES)
+def test_invariants_on_gpu(step, dim, nq):
+    _announce(f"invariants dim={dim} nq={nq} step={step.__name__}")
+    inv.check_constant_state(step, dim, nq)
+    inv.check_conservation(step, dim, nq)
+    inv.check_mirror(step, dim, nq)
+    inv.check_permutation(step, dim, nq)
+    inv.check_corner_independence(step, dim, nq)
+    inv.check_lambda_reduction(step, dim, nq)
+    inv.check_nan_propagates(step, dim, nq)
+
+
+def test_dimension_reduction_and_closed_form_on_gpu():
+    inv.check_dimension_reduction(hp.gpu_step)
+    inv.check_passive_scalar(hp.gpu_step)
+    inv.check_passive_scalar(hp.gpu_step, u0=0.44, p0=1.21, seed=11)
+
+
+def test_acoustic_convergence_on_gpu():
+    inv.check_acoustic_convergence(hp.gpu_step, 2, 5, (1, 1), sizes=(16, 32, 64))
+    # 3D: patches above 24^3 are out of range, so compare the error itself with the oracle's
+    for p in (8, 16, 24):
+        e_gpu = inv.acoustic_error(hp.gpu_step, p, 3, 5, (0, 0, 1))
+        e_ora = inv.acoustic_error(lambda *a: oracle.batch_update(*a), p, 3, 5, (0, 0, 1))
+        assert abs(e_gpu - e_ora) <= 1e-9 * e_ora, (p, e_gpu, e_ora)
