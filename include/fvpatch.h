@@ -114,6 +114,40 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
                                 double dt, double h, double gamma, uint32_t flags,
                                 double *lambda_out, void *stream);
 
+/*
+ * Launch parameters of the update kernel for one patch class (dim, unknowns,
+ * p).  The library picks defaults; the autotuner measures candidates and
+ * installs the fastest.  Settings are process-wide and apply to every later
+ * call (plain launches and plans built afterwards) on every device.
+ *
+ *   kernel    FV_KERNEL_AUTO, FV_KERNEL_BLOCK (plane-marching kernel, any
+ *             size), FV_KERNEL_WAVE (2D only: one padded patch row per
+ *             wavefront, p + 2 <= 64) or FV_KERNEL_TILE (2D only: whole
+ *             patches per block, one thread per interior volume, p*p <= 1024)
+ *   block     threads per block, a multiple of 64 (0 = default); the wave
+ *             kernel takes at most 256, the tile kernel at least p*p
+ *   prefetch  rows each lane keeps in flight in the wave kernel, 1..4
+ *             (0 = default)
+ */
+#define FV_KERNEL_AUTO 0
+#define FV_KERNEL_BLOCK 1
+#define FV_KERNEL_WAVE 2
+#define FV_KERNEL_TILE 3
+
+typedef struct fv_tuning {
+    int32_t kernel;
+    int32_t block;
+    int32_t prefetch;
+} fv_tuning;
+
+/* Install `tuning` for the class (NULL restores the defaults).  Returns
+ * FV_ERR_INVALID_ARG for values out of range, FV_ERR_UNSUPPORTED for a
+ * kernel that cannot run the class. */
+fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tuning *tuning);
+
+/* Current parameters of the class (the installed ones, else the defaults). */
+fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *tuning);
+
 /* Text for a status code (static storage). */
 const char *fv_status_string(fv_status status);
 

@@ -53,6 +53,7 @@ fv_status check_scalars(int32_t dim, int32_t nq, double dt, double h, double gam
 }
 
 static bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 static bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) {
     return a0 < b1 && b0 < a1;
@@ -187,6 +188,49 @@ fv_status release_slot(DescSlot *s, hipStream_t stream) {
     return FV_OK;
 }
 
+// ---------------------------------------------------------------- tuning table
+static std::mutex g_tune_mu;
+static fv_tuning g_tune[2][2][FV_MAX_P_2D + 1];  // [dim-2][nq-4][p], kernel = -1 when unset
+static bool g_tune_init = false;
+
+static fv_tuning *tune_slot(int dim, int nq, int p) {
+    if (!g_tune_init) {
+        for (auto &a : g_tune)
+            for (auto &b : a)
+                for (auto &c : b) c = fv_tuning{-1, 0, 0};
+        g_tune_init = true;
+    }
+    return &g_tune[dim - 2][nq - 4][p];
+}
+
+static int default_block_for(int kernel, int p, int dim) {
+    if (kernel == FV_KERNEL_WAVE) return 256;
+    if (kernel == FV_KERNEL_TILE) return tile2d_default_block(p);
+    return default_block(p, dim);
+}
+
+fv_tuning default_tuning(int dim, int nq, int p) {
+    (void)nq;
+    fv_tuning t{FV_KERNEL_AUTO, 0, 0};
+    t.kernel = (dim == 2 && wave2d_fits(p)) ? FV_KERNEL_WAVE : FV_KERNEL_BLOCK;
+    t.block = default_block_for(t.kernel, p, dim);
+    t.prefetch = t.kernel == FV_KERNEL_WAVE ? 4 : 1;
+    return t;
+}
+
+fv_tuning tuning_for(int dim, int nq, int p) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const fv_tuning *t = tune_slot(dim, nq, p);
+    return t->kernel < 0 ? default_tuning(dim, nq, p) : *t;
+}
+
+void apply_tuning(UpdateLaunch &L) {
+    const fv_tuning t = tuning_for(L.dim, L.nq, L.p);
+    L.kernel = t.kernel;
+    L.block = t.block;
+    L.prefetch = t.prefetch;
+}
+
 // Plain per-batch launch; arguments already validated.
 fv_status plain_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets,
                        int32_t T, int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags,
@@ -207,6 +251,8 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         L.num_items = T;
         L.p = shape.uniform_p;
         L.stride = patch_doubles(L.p, dim, nq);
+        L.vec2 = (L.stride % 2 == 0) && aligned16(in) && aligned16(out);
+        apply_tuning(L);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
         return FV_OK;
@@ -224,11 +270,14 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
     int64_t *hoff = static_cast<int64_t *>(slot->host);
     int32_t *hid = reinterpret_cast<int32_t *>(hoff + T);
     std::vector<int32_t> fill(start);
+    std::vector<char> odd(pmax + 2, 0);  // some patch of this size starts at an odd double
     for (int32_t t = 0; t < T; ++t) {
         const int32_t k = fill[sizes[t]]++;
         hoff[k] = offsets[t];
         hid[k] = t;
+        odd[sizes[t]] |= (char)(offsets[t] & 1);
     }
+    const bool bufs16 = aligned16(in) && aligned16(out);
     if (hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
         (void)release_slot(slot, stream);
         return fail(FV_ERR_LAUNCH, "descriptor upload failed");
@@ -241,6 +290,8 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         L.p = p;
         L.offsets = doff + start[p];
         L.ids = did + start[p];
+        L.vec2 = bufs16 && !odd[p] && patch_doubles(p, dim, nq) % 2 == 0;
+        apply_tuning(L);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) {
             (void)release_slot(slot, stream);
@@ -270,6 +321,67 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out, c
     if (st != FV_OK) return st;
     return plain_update(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, dt, h, gamma, flags,
                         lambda_out, static_cast<hipStream_t>(stream), shape);
+}
+
+static fv_status check_class(int32_t dim, int32_t nq, int32_t p) {
+    if (dim != 2 && dim != 3) return fail(FV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", dim);
+    if (!(nq == 5 || (dim == 2 && nq == 4))) return fail(FV_ERR_INVALID_ARG, "unsupported unknowns=%d for %dD", nq, dim);
+    if (p < 1 || p > max_p(dim)) return fail(FV_ERR_INVALID_ARG, "p=%d outside [1, %d]", p, max_p(dim));
+    return FV_OK;
+}
+
+fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tuning *t) {
+    clear_error();
+    fv_status st = check_class(dim, unknowns, p);
+    if (st != FV_OK) return st;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    fv_tuning *slot = tune_slot(dim, unknowns, p);
+    if (!t) {
+        *slot = fv_tuning{-1, 0, 0};
+        return FV_OK;
+    }
+    if (t->kernel < FV_KERNEL_AUTO || t->kernel > FV_KERNEL_TILE) return fail(FV_ERR_INVALID_ARG, "unknown kernel %d", t->kernel);
+    if (t->block < 0 || t->block > 1024 || t->block % 64 != 0) return fail(FV_ERR_INVALID_ARG, "block must be a multiple of 64 in [0, 1024]");
+    if (t->prefetch < 0 || t->prefetch > 4) return fail(FV_ERR_INVALID_ARG, "prefetch must be in [0, 4]");
+    fv_tuning v = *t;
+    const fv_tuning d = default_tuning(dim, unknowns, p);
+    if (v.kernel == FV_KERNEL_AUTO) v.kernel = d.kernel;
+    if (v.kernel == FV_KERNEL_WAVE && !(dim == 2 && wave2d_fits(p)))
+        return fail(FV_ERR_UNSUPPORTED, "the wave kernel needs 2D and p + 2 <= 64");
+    if (v.kernel == FV_KERNEL_TILE && !(dim == 2 && tile2d_fits(p)))
+        return fail(FV_ERR_UNSUPPORTED, "the tile kernel needs 2D and p*p <= 1024");
+    if (v.block == 0) v.block = v.kernel == d.kernel ? d.block : default_block_for(v.kernel, p, dim);
+    if (v.kernel == FV_KERNEL_WAVE && v.block > 256) return fail(FV_ERR_INVALID_ARG, "the wave kernel takes at most 256 threads");
+    if (v.kernel == FV_KERNEL_TILE) {
+        if (v.block < p * p) return fail(FV_ERR_INVALID_ARG, "the tile kernel needs at least p*p = %d threads", p * p);
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            tile2d_patches_per_block(p, unknowns, v.block, (size_t)lds_max) < 1)
+            return fail(FV_ERR_INVALID_ARG, "a tile of p=%d needs more LDS than the device offers", p);
+        (void)hipGetLastError();
+    }
+    if (v.kernel == FV_KERNEL_BLOCK) {
+        if (v.block < plane_lanes(p, dim)) return fail(FV_ERR_INVALID_ARG, "block %d smaller than the %d lanes of a patch", v.block, plane_lanes(p, dim));
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            update_lds_bytes(dim, unknowns, v.block) > (size_t)lds_max)
+            return fail(FV_ERR_INVALID_ARG, "block %d needs more LDS than the device offers", v.block);
+        (void)hipGetLastError();
+    }
+    if (v.prefetch == 0) v.prefetch = v.kernel == FV_KERNEL_WAVE ? 4 : 1;
+    *slot = v;
+    return FV_OK;
+}
+
+fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *t) {
+    clear_error();
+    fv_status st = check_class(dim, unknowns, p);
+    if (st != FV_OK) return st;
+    if (!t) return fail(FV_ERR_INVALID_ARG, "tuning must be non-null");
+    *t = tuning_for(dim, unknowns, p);
+    return FV_OK;
 }
 
 const char *fv_status_string(fv_status s) {

@@ -23,6 +23,9 @@ struct UpdateLaunch {
     uint32_t flags = 0;
     double *lambda_out = nullptr;      // device [max id + 1] or null
     int32_t block = 0;                 // threads per block, 0 = default choice
+    int32_t kernel = 0;                // FV_KERNEL_* of include/fvpatch.h, 0 = default choice
+    int32_t prefetch = 0;              // rows in flight per lane (2D wave kernel), 0 = default
+    bool vec2 = false;                 // every patch (and both buffers) 16-byte aligned: 16-byte loads
 };
 
 // Lanes one patch occupies (its cross-section plane including halo volumes).
@@ -37,5 +40,16 @@ size_t update_lds_bytes(int dim, int nq, int block);
 
 // Enqueue one update launch; returns hipSuccess or the launch error.
 hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream);
+
+// 2D kernel with each padded patch row inside one wavefront (p + 2 <= 64).
+bool wave2d_fits(int p);
+hipError_t launch_update2d(const UpdateLaunch &L, hipStream_t stream);
+
+// 2D kernel with whole patches per block, one thread per interior volume (p*p <= 1024).
+inline bool tile2d_fits(int p) { return p * p <= 1024; }
+int tile2d_default_block(int p);
+size_t tile2d_lds_bytes(int p, int nq, int G);
+int tile2d_patches_per_block(int p, int nq, int block, size_t lds_limit);
+hipError_t launch_update2d_tile(const UpdateLaunch &L, hipStream_t stream);
 
 }  // namespace fv

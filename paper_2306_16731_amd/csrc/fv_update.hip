@@ -35,16 +35,12 @@
 #include <stdint.h>
 
 #include "fv_internal.h"
+#include "fv_physics.h"
 
 namespace fv {
 namespace {
 
 constexpr uint32_t kPeriodic = 0x2u;
-
-// NaN-propagating maximum: a NaN in either argument gives NaN.
-__device__ __forceinline__ double nanmax(double a, double b) {
-    return (a != a || a > b) ? a : b;
-}
 
 // Barrier for LDS traffic only: waits for this wave's LDS operations, not for
 // its outstanding global loads (the next layer's prefetch stays in flight).
@@ -52,77 +48,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Per-volume quantities the user terms share across axes.
-template <int NQ>
-struct Prim {
-    double rinv;  // 1 / rho
-    double p;     // pressure
-    double c;     // speed of sound
-};
-
-#pragma clang fp contract(off)
-
-// Ideal-gas pressure and sound speed of a volume.
-template <int NQ>
-__device__ __forceinline__ Prim<NQ> primitives(const double (&q)[NQ], double gamma) {
-    Prim<NQ> a;
-    a.rinv = 1.0 / q[0];
-    double m2 = q[1] * q[1] + q[2] * q[2];
-    if constexpr (NQ == 5) m2 = m2 + q[3] * q[3];
-    double e = __builtin_fma(-0.5 * m2, a.rinv, q[NQ - 1]);  // E - |m|^2 / (2 rho)
-    a.p = (gamma - 1.0) * e;
-    a.c = __builtin_sqrt(gamma * a.p * a.rinv);
-    return a;
-}
-
-// F_n(Q) and l_n(Q) along axis n.
-template <int NQ>
-__device__ __forceinline__ void euler_flux(const double (&q)[NQ], const Prim<NQ> &a, int n,
-                                           double (&f)[NQ], double &lam) {
-    const double un = q[1 + n] * a.rinv;
-    f[0] = q[1 + n];
-#pragma unroll
-    for (int b = 0; b < NQ - 2; ++b)
-        f[1 + b] = (b == n) ? __builtin_fma(q[1 + b], un, a.p) : q[1 + b] * un;
-    f[NQ - 1] = (q[NQ - 1] + a.p) * un;
-    lam = __builtin_fabs(un) + a.c;
-}
-
-// Rusanov face flux from the left (L) and right (R) volume of a face.
-template <int NQ>
-__device__ __forceinline__ void rusanov(const double (&qL)[NQ], const double (&fL)[NQ], double lL,
-                                        const double (&qR)[NQ], const double (&fR)[NQ], double lR,
-                                        double (&fh)[NQ]) {
-    const double s = 0.5 * nanmax(lL, lR);
-#pragma unroll
-    for (int k = 0; k < NQ; ++k)
-        fh[k] = __builtin_fma(-s, qR[k] - qL[k], 0.5 * (fL[k] + fR[k]));
-}
-
-// Largest wave speed of a volume over the axes n < D.
-template <int D, int NQ>
-__device__ __forceinline__ double volume_lambda(const double (&q)[NQ], double gamma) {
-    Prim<NQ> a = primitives<NQ>(q, gamma);
-    double l = 0.0;
-#pragma unroll
-    for (int n = 0; n < D; ++n) l = nanmax(l, __builtin_fabs(q[1 + n] * a.rinv) + a.c);
-    return l;
-}
-
-#pragma clang fp contract(on)
-
-template <int NQ>
-__device__ __forceinline__ void load_volume(const double *__restrict__ src, double (&q)[NQ]) {
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) q[k] = src[k];
-}
-
-template <int NQ>
-__device__ __forceinline__ void store_volume(double *__restrict__ dst, const double (&q)[NQ]) {
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) dst[k] = q[k];
 }
 
 // LDS per lane (structure of arrays over the block's lanes, so consecutive
@@ -193,7 +118,7 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
             if (live1) load_volume<NQ>(src + (k + 1) * layer, qnext);
         }
 
-        Prim<NQ> a;
+        Prim a;
         double fm[NQ], lm = 0.0;
         if (live) {
             a = primitives<NQ>(q, gamma);
@@ -264,12 +189,10 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
             if (k >= 1) rusanov<NQ>(qprev, fmprev, lmprev, q, fm, lm, fh);
             // complete the volume of layer k-1
             if (k >= 2) {
-                double qn[NQ];
+                double qn[NQ], dsum[NQ];
 #pragma unroll
-                for (int c = 0; c < NQ; ++c) {
-                    const double dsum = dinprev[c] + (fhprev[c] - fh[c]);
-                    qn[c] = __builtin_fma(r, dsum, qprev[c]);
-                }
+                for (int c = 0; c < NQ; ++c) dsum[c] = dinprev[c] + (fhprev[c] - fh[c]);
+                advance<NQ>(qprev, dsum, r, qn);
                 const int kk = k - 1;
                 store_volume<NQ>(dst + kk * layer, qn);
                 if (periodic) {
@@ -361,6 +284,9 @@ size_t update_lds_bytes(int dim, int nq, int block) {
 
 hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream) {
     if (L.num_items <= 0) return hipSuccess;
+    if (L.dim == 2 && L.kernel == 2) return wave2d_fits(L.p) ? launch_update2d(L, stream) : hipErrorInvalidConfiguration;
+    if (L.dim == 2 && L.kernel == 3) return tile2d_fits(L.p) ? launch_update2d_tile(L, stream) : hipErrorInvalidConfiguration;
+    if (L.dim == 2 && L.kernel == 0 && wave2d_fits(L.p)) return launch_update2d(L, stream);
     if (L.dim == 2 && L.nq == 5) return launch_typed<2, 5>(L, stream);
     if (L.dim == 2 && L.nq == 4) return launch_typed<2, 4>(L, stream);
     if (L.dim == 3 && L.nq == 5) return launch_typed<3, 5>(L, stream);

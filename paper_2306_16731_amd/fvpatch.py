@@ -34,7 +34,19 @@ FV_MAX_P_2D = 64
 FV_MAX_P_3D = 24
 
 # Every symbol the header declares (checked by the tests against include/fvpatch.h).
-EXPORTS = ["fv_patch_batch_update", "fv_status_string", "fv_last_error", "fv_version"]
+EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_status_string", "fv_last_error",
+           "fv_version"]
+FV_KERNEL_AUTO = 0
+FV_KERNEL_BLOCK = 1
+FV_KERNEL_WAVE = 2
+FV_KERNEL_TILE = 3
+
+
+class fv_tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"kernel": self.kernel, "block": self.block, "prefetch": self.prefetch}
 
 
 class FvError(RuntimeError):
@@ -67,6 +79,10 @@ def load(path: str = LIBRARY):
     lib.fv_last_error.restype = ctypes.c_char_p
     lib.fv_version.argtypes = []
     lib.fv_version.restype = i32
+    lib.fv_set_tuning.argtypes = [i32, i32, i32, ctypes.POINTER(fv_tuning)]
+    lib.fv_set_tuning.restype = ctypes.c_int
+    lib.fv_get_tuning.argtypes = [i32, i32, i32, ctypes.POINTER(fv_tuning)]
+    lib.fv_get_tuning.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -137,3 +153,22 @@ def fv_patch_batch_update(patches_in, patches_out, sizes, offsets, num_patches: 
                                    _dev_ptr(lambda_out), _stream_handle(stream))
     del sz, of
     return _check(st) if raise_on_error else st
+
+
+def fv_set_tuning(dim: int, unknowns: int, p: int, tuning=None, raise_on_error: bool = True) -> int:
+    """Install launch parameters for a patch class (a dict or fv_tuning; None restores defaults)."""
+    lib = load()
+    if tuning is None:
+        st = lib.fv_set_tuning(int(dim), int(unknowns), int(p), None)
+    else:
+        t = tuning if isinstance(tuning, fv_tuning) else fv_tuning(**tuning)
+        st = lib.fv_set_tuning(int(dim), int(unknowns), int(p), ctypes.byref(t))
+    return _check(st) if raise_on_error else st
+
+
+def fv_get_tuning(dim: int, unknowns: int, p: int) -> dict:
+    """Launch parameters the library uses for a patch class."""
+    lib = load()
+    t = fv_tuning()
+    _check(lib.fv_get_tuning(int(dim), int(unknowns), int(p), ctypes.byref(t)))
+    return t.as_dict()

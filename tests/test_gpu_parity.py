@@ -219,3 +219,28 @@ def test_acoustic_convergence_on_gpu():
         e_gpu = inv.acoustic_error(hp.gpu_step, p, 3, 5, (0, 0, 1))
         e_ora = inv.acoustic_error(lambda *a: oracle.batch_update(*a), p, 3, 5, (0, 0, 1))
         assert abs(e_gpu - e_ora) <= 1e-9 * e_ora, (p, e_gpu, e_ora)
+
+
+# --------------------------------------------------------------------- every kernel variant the tuner may pick
+VARIANTS = [
+    (2, 16, dict(kernel=3, block=256)), (2, 16, dict(kernel=3, block=512)), (2, 16, dict(kernel=2, block=256, prefetch=1)),
+    (2, 16, dict(kernel=2, block=64, prefetch=4)), (2, 16, dict(kernel=1, block=128)), (2, 16, dict(kernel=1, block=320)),
+    (2, 3, dict(kernel=3, block=64)), (2, 3, dict(kernel=3, block=256)), (2, 5, dict(kernel=3, block=128)),
+    (2, 9, dict(kernel=3, block=128)), (2, 17, dict(kernel=3, block=320)), (2, 17, dict(kernel=3, block=640)),
+    (2, 32, dict(kernel=3, block=1024)), (2, 30, dict(kernel=2, block=128, prefetch=2)), (2, 17, dict(kernel=1, block=64)),
+    (3, 8, dict(kernel=1, block=128)), (3, 8, dict(kernel=1, block=512)),
+]
+
+
+@pytest.mark.parametrize("dim,p,tuning", VARIANTS, ids=[f"{d}d-p{p}-{t}" for d, p, t in VARIANTS])
+def test_kernel_variants(dim, p, tuning):
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"variant dim={dim} p={p} {tuning}")
+    try:
+        fvpatch.fv_set_tuning(dim, 5, p, tuning)
+        b = wl.make_uniform(23, p, dim=dim, nq=5, seed=40 + p)
+        compare_run(b, 2, True, pass_offsets=False)
+        compare_run(b, 1, False, pass_offsets=True)
+        inv.check_constant_state(hp.gpu_step, dim, 5, p=p, T=3)
+    finally:
+        fvpatch.fv_set_tuning(dim, 5, p, None)
