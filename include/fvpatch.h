@@ -128,6 +128,8 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
  *             kernel takes at most 256, the tile kernel at least p*p
  *   prefetch  rows each lane keeps in flight in the wave kernel, 1..4
  *             (0 = default)
+ *   rows      output rows the wave kernel stages in LDS per patch before
+ *             writing them in one burst, 1..16 (0 = default)
  */
 #define FV_KERNEL_AUTO 0
 #define FV_KERNEL_BLOCK 1
@@ -138,6 +140,7 @@ typedef struct fv_tuning {
     int32_t kernel;
     int32_t block;
     int32_t prefetch;
+    int32_t rows;
 } fv_tuning;
 
 /* Install `tuning` for the class (NULL restores the defaults).  Returns

@@ -197,7 +197,7 @@ static fv_tuning *tune_slot(int dim, int nq, int p) {
     if (!g_tune_init) {
         for (auto &a : g_tune)
             for (auto &b : a)
-                for (auto &c : b) c = fv_tuning{-1, 0, 0};
+                for (auto &c : b) c = fv_tuning{-1, 0, 0, 0};
         g_tune_init = true;
     }
     return &g_tune[dim - 2][nq - 4][p];
@@ -211,10 +211,11 @@ static int default_block_for(int kernel, int p, int dim) {
 
 fv_tuning default_tuning(int dim, int nq, int p) {
     (void)nq;
-    fv_tuning t{FV_KERNEL_AUTO, 0, 0};
+    fv_tuning t{FV_KERNEL_AUTO, 0, 0, 0};
     t.kernel = (dim == 2 && wave2d_fits(p)) ? FV_KERNEL_WAVE : FV_KERNEL_BLOCK;
     t.block = default_block_for(t.kernel, p, dim);
     t.prefetch = t.kernel == FV_KERNEL_WAVE ? 4 : 1;
+    t.rows = t.kernel == FV_KERNEL_WAVE ? 6 : 1;
     return t;
 }
 
@@ -229,6 +230,7 @@ void apply_tuning(UpdateLaunch &L) {
     L.kernel = t.kernel;
     L.block = t.block;
     L.prefetch = t.prefetch;
+    L.rows = t.rows;
 }
 
 // Plain per-batch launch; arguments already validated.
@@ -337,12 +339,13 @@ fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tunin
     std::lock_guard<std::mutex> g(g_tune_mu);
     fv_tuning *slot = tune_slot(dim, unknowns, p);
     if (!t) {
-        *slot = fv_tuning{-1, 0, 0};
+        *slot = fv_tuning{-1, 0, 0, 0};
         return FV_OK;
     }
     if (t->kernel < FV_KERNEL_AUTO || t->kernel > FV_KERNEL_TILE) return fail(FV_ERR_INVALID_ARG, "unknown kernel %d", t->kernel);
     if (t->block < 0 || t->block > 1024 || t->block % 64 != 0) return fail(FV_ERR_INVALID_ARG, "block must be a multiple of 64 in [0, 1024]");
     if (t->prefetch < 0 || t->prefetch > 4) return fail(FV_ERR_INVALID_ARG, "prefetch must be in [0, 4]");
+    if (t->rows < 0 || t->rows > 16) return fail(FV_ERR_INVALID_ARG, "rows must be in [0, 16]");
     fv_tuning v = *t;
     const fv_tuning d = default_tuning(dim, unknowns, p);
     if (v.kernel == FV_KERNEL_AUTO) v.kernel = d.kernel;
@@ -371,6 +374,15 @@ fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tunin
         (void)hipGetLastError();
     }
     if (v.prefetch == 0) v.prefetch = v.kernel == FV_KERNEL_WAVE ? 4 : 1;
+    if (v.rows == 0) v.rows = v.kernel == FV_KERNEL_WAVE ? 6 : 1;
+    if (v.kernel == FV_KERNEL_WAVE) {
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            wave2d_lds_bytes(p, unknowns, v.block, v.rows) > (size_t)lds_max)
+            return fail(FV_ERR_INVALID_ARG, "block %d with %d staged rows needs more LDS than the device offers", v.block, v.rows);
+        (void)hipGetLastError();
+    }
     *slot = v;
     return FV_OK;
 }

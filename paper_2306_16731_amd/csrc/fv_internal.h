@@ -26,6 +26,7 @@ struct UpdateLaunch {
     int32_t kernel = 0;                // FV_KERNEL_* of include/fvpatch.h, 0 = default choice
     int32_t prefetch = 0;              // rows in flight per lane (2D wave kernel), 0 = default
     bool vec2 = false;                 // every patch (and both buffers) 16-byte aligned: 16-byte loads
+    int32_t rows = 0;                  // output rows staged per flush (2D wave kernel), 0 = default
 };
 
 // Lanes one patch occupies (its cross-section plane including halo volumes).
@@ -43,6 +44,7 @@ hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream);
 
 // 2D kernel with each padded patch row inside one wavefront (p + 2 <= 64).
 bool wave2d_fits(int p);
+size_t wave2d_lds_bytes(int p, int nq, int block, int rows);
 hipError_t launch_update2d(const UpdateLaunch &L, hipStream_t stream);
 
 // 2D kernel with whole patches per block, one thread per interior volume (p*p <= 1024).

@@ -13,9 +13,14 @@
 //             D_x of each interior volume = its left face - the left face of
 //               the lane to its right (second DPP shift)
 //             y face between rows k-1 and k from registers
-//             complete row k-1: Q + (dt/h) (D_x + D_y), store, fold l into the
-//               patch maximum
+//             complete row k-1: Q + (dt/h) (D_x + D_y) into an LDS ring of R
+//               output rows per patch, fold l into the patch maximum
+//             every R rows: flush the ring as contiguous 16- (or 8-) byte
+//               chunks, R rows of a patch at a time
 //
+// Writing R consecutive rows of a patch in one burst keeps HBM write pages
+// whole; storing each lane's 40-byte volume as it completes leaves every
+// page to be reopened once per row and costs about a fifth of the write rate.
 // The waves of a block never synchronise with each other.  The per-patch
 // maximum is a segmented tree reduction over the patch's lanes at the end.
 #include <hip/hip_runtime.h>
@@ -29,6 +34,7 @@ namespace {
 
 constexpr uint32_t kPeriodic = 0x2u;
 constexpr int kDefaultPrefetch2d = 4;
+constexpr int kDefaultRows2d = 6;
 
 // Cross-lane moves of a double through the DPP wave shifts.  They are issued
 // in uniform control flow, so every source lane is enabled.
@@ -42,11 +48,71 @@ __device__ __forceinline__ double dpp_move(double x) {
 __device__ __forceinline__ double from_left(double x) { return dpp_move<0x138>(x); }   // wave_shr:1
 __device__ __forceinline__ double from_right(double x) { return dpp_move<0x130>(x); }  // wave_shl:1
 
-template <int NQ, int PF>
+// Exact quotient and remainder of small non-negative integers through a
+// float reciprocal and one correction step.
+__device__ __forceinline__ int small_div(int a, int b, float inv_b, int &rem) {
+    int q = (int)((float)a * inv_b);
+    int r = a - q * b;
+    if (r < 0) { q -= 1; r += b; }
+    else if (r >= b) { q += 1; r -= b; }
+    rem = r;
+    return q;
+}
+
+// Write rows [k0, k0 + nrows) of the wave's patches from the LDS ring.
+// Periodic output covers whole rows (the x-halo volumes hold their wrapped
+// copies), otherwise only the interior volumes of each row.
+template <int NQ, int VEC>
+__device__ __forceinline__ void flush_rows(double *__restrict__ out, const double *ring, const int64_t *bases,
+                                           int ppw, int R, int W, int P, int k0, int nrows, bool periodic,
+                                           int lane) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const int ROWD = W * NQ;
+    const int64_t row = ROWD;
+    if (periodic) {
+        // rows are contiguous in HBM and in the ring: nrows * ROWD doubles per patch
+        const int per = nrows * ROWD / VEC;
+        const float inv = 1.0f / (float)per;
+        for (int c = lane; c < ppw * per; c += 64) {
+            int rem;
+            const int sl = small_div(c, per, inv, rem);
+            const int64_t base = bases[sl];
+            if (base < 0) continue;
+            if constexpr (VEC == 2) {
+                const dv2 v = reinterpret_cast<const dv2 *>(ring + (size_t)sl * R * ROWD)[rem];
+                reinterpret_cast<dv2 *>(out + base + k0 * row)[rem] = v;
+            } else {
+                out[base + k0 * row + rem] = ring[(size_t)sl * R * ROWD + rem];
+            }
+        }
+    } else {
+        const int inner = P * NQ;  // interior doubles of a row
+        const int per = nrows * inner;
+        const float inv = 1.0f / (float)per;
+        const float inv_inner = 1.0f / (float)inner;
+        for (int c = lane; c < ppw * per; c += 64) {
+            int rem, d;
+            const int sl = small_div(c, per, inv, rem);
+            const int r = small_div(rem, inner, inv_inner, d);
+            const int64_t base = bases[sl];
+            if (base < 0) continue;
+            out[base + (k0 + r) * row + NQ + d] = ring[((size_t)sl * R + r) * ROWD + NQ + d];
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <int NQ, int PF, int VEC>
 __global__ void __launch_bounds__(256)
 update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                 const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int64_t stride, double r,
-                double gamma, uint32_t flags, double *__restrict__ lambda_out) {
+                double gamma, uint32_t flags, double *__restrict__ lambda_out, int32_t R) {
+    extern __shared__ double lds[];
     const int W = P + 2;
     const int ppw = 64 / W;
     const int lane = threadIdx.x & 63;
@@ -63,6 +129,14 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
     double *dst = out + off + (int64_t)i * NQ;
     const int64_t row = (int64_t)W * NQ;
     const bool periodic = (flags & kPeriodic) != 0;
+
+    // LDS: per wave, the ring of R output rows of each of its ppw patches, then their bases
+    const int ring_words = ppw * R * W * NQ;
+    double *ring = lds + (size_t)wave * (ring_words + ppw);
+    int64_t *bases = reinterpret_cast<int64_t *>(ring + ring_words);
+    if (i == 0 && slot < ppw) bases[slot] = active ? off : -1;
+    wave_lds_fence();
+    int k0 = 1;  // first output row held in the ring
 
     double qprev[NQ], fyprev[NQ], lyprev, fhprev[NQ], dxprev[NQ];
     rest_state<NQ>(qprev);
@@ -123,15 +197,27 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
             for (int c = 0; c < NQ; ++c) d[c] = dxprev[c] + (fhprev[c] - fh[c]);
             advance<NQ>(qprev, d, r, qn);
             const int kk = k - 1;
-            double *o = dst + kk * row;
-            store_volume<NQ>(o, qn);
+            double *srow = ring + ((size_t)slot * R + (kk - k0)) * row;
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) srow[i * NQ + c] = qn[c];
             if (periodic) {
-                if (i == P) store_volume<NQ>(o - (int64_t)P * NQ, qn);
-                if (i == 1) store_volume<NQ>(o + (int64_t)P * NQ, qn);
+                // x-halo copies go into the ring row; y-halo rows are stored directly
+                if (i == P)
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) srow[c] = qn[c];
+                if (i == 1)
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) srow[(P + 1) * NQ + c] = qn[c];
                 if (kk == P) store_volume<NQ>(dst, qn);
                 if (kk == 1) store_volume<NQ>(dst + (int64_t)(P + 1) * row, qn);
             }
             if (lambda_out) lmax = nanmax(lmax, volume_lambda<2, NQ>(qn, gamma));
+        }
+        if (k >= 2 && (k - k0 == R || k - 1 == P)) {
+            wave_lds_fence();
+            flush_rows<NQ, VEC>(out, ring, bases, ppw, R, W, P, k0, k - k0, periodic, lane);
+            wave_lds_fence();
+            k0 = k;
         }
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
@@ -155,17 +241,34 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
     }
 }
 
-template <int NQ, int PF>
+size_t wave2d_lds_bytes_(int p, int nq, int block, int R) {
+    const int W = p + 2, ppw = 64 / W;
+    return sizeof(double) * (size_t)(block / 64) * (size_t)(ppw * R * W * nq + ppw);
+}
+
+template <int NQ, int PF, int VEC>
 hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
     const int W = L.p + 2;
     const int ppw = 64 / W;
     const int B = L.block > 0 ? L.block : 256;
-    if (B % 64 != 0 || B > 256 || ppw < 1) return hipErrorInvalidConfiguration;
+    const int R = L.rows > 0 ? L.rows : kDefaultRows2d;
+    if (B % 64 != 0 || B > 256 || ppw < 1 || R < 1 || R > 16) return hipErrorInvalidConfiguration;
     const int per_block = (B / 64) * ppw;
     const int64_t blocks = ((int64_t)L.num_items + per_block - 1) / per_block;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((update2d_kernel<NQ, PF>), dim3((unsigned)blocks), dim3(B), 0, stream, L.in, L.out, L.offsets,
-                       L.ids, L.num_items, L.p, L.stride, L.r, L.gamma, L.flags, L.lambda_out);
+    const size_t lds = wave2d_lds_bytes_(L.p, NQ, B, R);
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return hipErrorInvalidDevice;
+    if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&update2d_kernel<NQ, PF, VEC>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((update2d_kernel<NQ, PF, VEC>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in, L.out,
+                       L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.gamma, L.flags, L.lambda_out, R);
     return hipGetLastError();
 }
 
@@ -173,20 +276,24 @@ hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
 
 bool wave2d_fits(int p) { return p + 2 <= 64; }
 
-template <int NQ>
+template <int NQ, int VEC>
 hipError_t launch2d_pf(const UpdateLaunch &L, hipStream_t stream) {
     switch (L.prefetch > 0 ? L.prefetch : kDefaultPrefetch2d) {
-        case 1: return launch2d<NQ, 1>(L, stream);
-        case 2: return launch2d<NQ, 2>(L, stream);
-        case 3: return launch2d<NQ, 3>(L, stream);
-        case 4: return launch2d<NQ, 4>(L, stream);
+        case 1: return launch2d<NQ, 1, VEC>(L, stream);
+        case 2: return launch2d<NQ, 2, VEC>(L, stream);
+        case 3: return launch2d<NQ, 3, VEC>(L, stream);
+        case 4: return launch2d<NQ, 4, VEC>(L, stream);
     }
     return hipErrorInvalidValue;
 }
 
+size_t wave2d_lds_bytes(int p, int nq, int block, int rows) { return wave2d_lds_bytes_(p, nq, block, rows); }
+
 hipError_t launch_update2d(const UpdateLaunch &L, hipStream_t stream) {
-    if (L.nq == 5) return launch2d_pf<5>(L, stream);
-    if (L.nq == 4) return launch2d_pf<4>(L, stream);
+    // 16-byte flush chunks need 16-byte aligned patches and an even row length
+    const bool v2 = L.vec2 && ((L.p + 2) * L.nq) % 2 == 0;
+    if (L.nq == 5) return v2 ? launch2d_pf<5, 2>(L, stream) : launch2d_pf<5, 1>(L, stream);
+    if (L.nq == 4) return v2 ? launch2d_pf<4, 2>(L, stream) : launch2d_pf<4, 1>(L, stream);
     return hipErrorInvalidValue;
 }
 

@@ -46,6 +46,109 @@ __host__ __device__ inline int tile_words(int P, int NQ) {
     return tile_q_words(P, NQ) + (NQ + 1) * tile_f_cells(P) + NQ * tile_h_faces(P);
 }
 
+// One axis phase of the tile kernel: publish the user terms along axis N of
+// every volume bordering an N face, form every N face once, and return
+// D_N = low face - high face of the calling thread's volume.
+template <int NQ>
+struct AxisTile {
+    double *QS, *FB, *FH;
+    const int64_t *POFF;
+    const double *Qg;
+    double *Fg, *Hg;
+    int P, G, W, QW, FC, HF, B, tid, i, j;
+    bool active;
+    int hg, hn, hv, nh, stride_h;
+    double gamma;
+
+    // user-term slot of volume (a, b): x layout (b-1)(P+2) + a for a in [0, P+1];
+    // y layout b P + (a-1) for b in [0, P+1]
+    template <int N>
+    __device__ __forceinline__ int slot(int a, int b) const { return N == 0 ? (b - 1) * W + a : b * P + (a - 1); }
+
+    template <int N>
+    __device__ __forceinline__ void phase(const double (&q)[NQ], const double (&f)[NQ], double l,
+                                          const double (&hf)[NQ], double hl, double (&d)[NQ]) {
+        if (active) {
+            const int v = slot<N>(i, j);
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) Fg[k * FC + v] = f[k];
+            Fg[NQ * FC + v] = l;
+        }
+        if (hg >= 0 && hn == N) {
+            double *F = FB + (size_t)hg * (NQ + 1) * FC;
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) F[k * FC + hv] = hf[k];
+            F[NQ * FC + hv] = hl;
+        }
+        // halo volumes beyond one per thread (only when 4 P G exceeds the block)
+        for (int hh = tid + B * stride_h; hh < nh * stride_h; hh += B * stride_h) {
+            const int hx = hh / stride_h;
+            const int xg = hx / (4 * P);
+            const int rem = hx - xg * 4 * P;
+            const int side = rem / P;
+            const int t = rem - side * P + 1;
+            if ((side < 2 ? 0 : 1) != N || POFF[xg] < 0) continue;
+            const int hi = side == 0 ? 0 : side == 1 ? P + 1 : t;
+            const int hj = side == 2 ? 0 : side == 3 ? P + 1 : t;
+            double hq[NQ], hf2[NQ], hl2;
+            const double *src = QS + (size_t)xg * QW + (hj * W + hi) * NQ;
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) hq[k] = src[k];
+            const Prim a = primitives<NQ>(hq, gamma);
+            euler_flux<NQ>(hq, a, N, hf2, hl2);
+            double *F = FB + (size_t)xg * (NQ + 1) * FC;
+            const int v = slot<N>(hi, hj);
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) F[k * FC + v] = hf2[k];
+            F[NQ * FC + v] = hl2;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+
+        // faces: each volume forms its low face; the last volume along N also its high face
+        //   x faces (i - 1/2, j): (j-1)(P+1) + (i-1);   y faces (i, j - 1/2): (j-1) P + (i-1)
+        const int flo = N == 0 ? (j - 1) * (P + 1) + (i - 1) : (j - 1) * P + (i - 1);
+        const int fhi = N == 0 ? flo + 1 : flo + P;
+        if (active) {
+            const int cn = N == 0 ? i : j;
+            const int vlo = N == 0 ? slot<0>(i - 1, j) : slot<1>(i, j - 1);
+            const int qlo = N == 0 ? (j * W + i - 1) * NQ : ((j - 1) * W + i) * NQ;
+            double qo[NQ], fo[NQ], fh[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                qo[k] = Qg[qlo + k];
+                fo[k] = Fg[k * FC + vlo];
+            }
+            rusanov<NQ>(qo, fo, Fg[NQ * FC + vlo], q, f, l, fh);
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) Hg[k * HF + flo] = fh[k];
+            if (cn == P) {
+                const int vhi = N == 0 ? slot<0>(i + 1, j) : slot<1>(i, j + 1);
+                const int qhi = N == 0 ? (j * W + i + 1) * NQ : ((j + 1) * W + i) * NQ;
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    qo[k] = Qg[qhi + k];
+                    fo[k] = Fg[k * FC + vhi];
+                }
+                rusanov<NQ>(q, f, l, qo, fo, Fg[NQ * FC + vhi], fh);
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) Hg[k * HF + fhi] = fh[k];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) d[k] = Hg[k * HF + flo] - Hg[k * HF + fhi];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) d[k] = 0.0;
+        }
+    }
+};
+
 template <int NQ, int VEC>
 __global__ void __launch_bounds__(1024)
 update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
@@ -79,7 +182,10 @@ update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, co
     // patch offsets even), VEC = 1 moves 8 bytes.
     {
         constexpr int kBatch = 4;
-        using vec_t = typename std::conditional<VEC == 2, double2, double>::type;
+        // native vector type: HIP's double2 is a union wrapper that keeps
+        // arrays of it out of registers
+        typedef double dvec2 __attribute__((ext_vector_type(2)));
+        using vec_t = typename std::conditional<VEC == 2, dvec2, double>::type;
         const int nv = QW / VEC;                          // vectors per patch (QW is even for VEC = 2)
         const int total = G * nv;
         const float inv_nv = 1.0f / (float)nv;
@@ -164,98 +270,11 @@ update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, co
     double dx[NQ], dy[NQ];
 
     // ---- the two axis phases
-#pragma unroll
-    for (int n = 0; n < 2; ++n) {
-        // publish the user terms of interior volumes along n
-        //   x layout: volume (i, j), i in [0, P+1], j in [1, P]  ->  (j-1) (P+2) + i
-        //   y layout: volume (i, j), i in [1, P], j in [0, P+1]  ->  j P + (i-1)
-        if (active) {
-            const int v = n == 0 ? (j - 1) * W + i : j * P + (i - 1);
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) Fg[k * FC + v] = n == 0 ? fx[k] : fy[k];
-            Fg[NQ * FC + v] = n == 0 ? lx : ly;
-        }
-        // face-halo volumes along n publish their terms
-        if (hg >= 0 && hn == n) {
-            double *F = FB + (size_t)hg * (NQ + 1) * FC;
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) F[k * FC + hv] = hfl[k];
-            F[NQ * FC + hv] = hl;
-        }
-        for (int hh = tid + B * stride_h; hh < nh * stride_h; hh += B * stride_h) {
-            // leftover halo volumes when 4P G > B / stride_h (never for the default blocks)
-            const int hx = hh / stride_h;
-            const int xg = hx / (4 * P);
-            const int rem = hx - xg * 4 * P;
-            const int side = rem / P;
-            const int t = rem - side * P + 1;
-            if ((side < 2 ? 0 : 1) != n || POFF[xg] < 0) continue;
-            const int hi = side == 0 ? 0 : side == 1 ? P + 1 : t;
-            const int hj = side == 2 ? 0 : side == 3 ? P + 1 : t;
-            double hq[NQ], hf2[NQ], hl2;
-            const double *src = QS + (size_t)xg * QW + (hj * W + hi) * NQ;
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) hq[k] = src[k];
-            const Prim a = primitives<NQ>(hq, gamma);
-            euler_flux<NQ>(hq, a, n, hf2, hl2);
-            double *F = FB + (size_t)xg * (NQ + 1) * FC;
-            const int v = n == 0 ? (hj - 1) * W + hi : hj * P + (hi - 1);
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) F[k * FC + v] = hf2[k];
-            F[NQ * FC + v] = hl2;
-        }
-        block_lds_barrier();
-
-        // faces along n: each volume forms the face on its low side; the last
-        // volume along n also forms the face on its high side
-        //   x faces: face (i - 1/2, j), index (j-1) (P+1) + (i-1);  y faces: (i, j - 1/2), index (j-1) P + (i-1)
-        if (active) {
-            const int cn = n == 0 ? i : j;
-            const int vself = n == 0 ? (j - 1) * W + i : j * P + (i - 1);
-            const int vlo = n == 0 ? vself - 1 : vself - P;
-            const int vhi = n == 0 ? vself + 1 : vself + P;
-            const int qlo = n == 0 ? (j * W + i - 1) * NQ : ((j - 1) * W + i) * NQ;
-            const int qhi = n == 0 ? (j * W + i + 1) * NQ : ((j + 1) * W + i) * NQ;
-            const int flo = n == 0 ? (j - 1) * (P + 1) + (i - 1) : (j - 1) * P + (i - 1);
-            const int fhi = n == 0 ? flo + 1 : flo + P;
-            const double *fs = n == 0 ? fx : fy;
-            const double ls = n == 0 ? lx : ly;
-            double qo[NQ], fo[NQ], fh[NQ];
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-                qo[k] = Qg[qlo + k];
-                fo[k] = Fg[k * FC + vlo];
-            }
-            double fself[NQ];
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) fself[k] = fs[k];
-            rusanov<NQ>(qo, fo, Fg[NQ * FC + vlo], q, fself, ls, fh);
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) Hg[k * HF + flo] = fh[k];
-            if (cn == P) {
-#pragma unroll
-                for (int k = 0; k < NQ; ++k) {
-                    qo[k] = Qg[qhi + k];
-                    fo[k] = Fg[k * FC + vhi];
-                }
-                rusanov<NQ>(q, fself, ls, qo, fo, Fg[NQ * FC + vhi], fh);
-#pragma unroll
-                for (int k = 0; k < NQ; ++k) Hg[k * HF + fhi] = fh[k];
-            }
-        }
-        block_lds_barrier();
-        if (active) {
-            const int flo = n == 0 ? (j - 1) * (P + 1) + (i - 1) : (j - 1) * P + (i - 1);
-            const int fhi = n == 0 ? flo + 1 : flo + P;
-#pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-                const double d = Hg[k * HF + flo] - Hg[k * HF + fhi];
-                if (n == 0) dx[k] = d;
-                else dy[k] = d;
-            }
-        }
-        if (n == 0) block_lds_barrier();  // x faces read before the y phase overwrites them
-    }
+    AxisTile<NQ> tile{QS, FB, FH, POFF, Qg, Fg, Hg, P, G, W, QW, FC, HF, B, tid, i, j, active,
+                      hg, hn, hv, nh, stride_h, gamma};
+    tile.template phase<0>(q, fx, lx, hfl, hl, dx);
+    block_lds_barrier();  // x faces read before the y phase overwrites them
+    tile.template phase<1>(q, fy, ly, hfl, hl, dy);
 
     // ---- update, store, eigenvalue of the new state
     double lam = 0.0;

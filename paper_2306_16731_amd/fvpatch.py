@@ -43,10 +43,11 @@ FV_KERNEL_TILE = 3
 
 
 class fv_tuning(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+    _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("rows", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"kernel": self.kernel, "block": self.block, "prefetch": self.prefetch}
+        return {"kernel": self.kernel, "block": self.block, "prefetch": self.prefetch, "rows": self.rows}
 
 
 class FvError(RuntimeError):

@@ -225,6 +225,9 @@ def test_acoustic_convergence_on_gpu():
 VARIANTS = [
     (2, 16, dict(kernel=3, block=256)), (2, 16, dict(kernel=3, block=512)), (2, 16, dict(kernel=2, block=256, prefetch=1)),
     (2, 16, dict(kernel=2, block=64, prefetch=4)), (2, 16, dict(kernel=1, block=128)), (2, 16, dict(kernel=1, block=320)),
+    (2, 16, dict(kernel=2, block=256, prefetch=4, rows=1)), (2, 16, dict(kernel=2, block=128, prefetch=2, rows=16)),
+    (2, 17, dict(kernel=2, block=256, prefetch=3, rows=5)), (2, 3, dict(kernel=2, block=64, prefetch=1, rows=3)),
+    (2, 62, dict(kernel=2, block=64, prefetch=2, rows=7)),
     (2, 3, dict(kernel=3, block=64)), (2, 3, dict(kernel=3, block=256)), (2, 5, dict(kernel=3, block=128)),
     (2, 9, dict(kernel=3, block=128)), (2, 17, dict(kernel=3, block=320)), (2, 17, dict(kernel=3, block=640)),
     (2, 32, dict(kernel=3, block=1024)), (2, 30, dict(kernel=2, block=128, prefetch=2)), (2, 17, dict(kernel=1, block=64)),
