@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_16731_amd", "csrc", "fv_update.hip")
+# sources of the kernel the roofline reports (the 2D wave kernel and its physics)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_16731_amd", "csrc", f) for f in ("fv_update2d.hip", "fv_physics.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv_update_c2_2d_p16_T65536_traffic.md")
 
 
@@ -44,7 +45,10 @@ def alg_bytes_per_patch(p: int, dim: int, nq: int, periodic: bool, with_lambda: 
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -64,10 +68,15 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed steps first (about 40 ms: the GPU's clocks and TLBs settle)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-patches", type=int, default=65536)
+    ap.add_argument("--cpu-sample-patches", type=int, default=4096,
+                    help="patches the CPU oracle advances through all warmup + timed steps")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run 4 update launches and one 849,346,560-byte device copy, for rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE runs (the copy's reading is the counters' scale), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,6 +106,14 @@ def main() -> int:
     d_b = d_a.clone()
     lam = torch.empty(T, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.traffic_probe:
+        for _ in range(4):
+            fvpatch.fv_patch_batch_update(d_a, d_b, b.sizes, None, T, dim, nq, 1.6e-3, h, gamma, flags, lam, stream)
+        d_b.copy_(d_a)  # plain copy of known size: d_a.numel() * 8 bytes read and written
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": d_a.numel() * 8, "kernel_sources_sha": kernel_sha()}))
+        return 0
 
     # time step from the initial eigenvalue (outside the timed region)
     fvpatch.fv_patch_batch_update(d_a, d_b, b.sizes, None, T, dim, nq, 1e-9, h, gamma, flags, lam, stream)
@@ -134,7 +151,7 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
-                "kernel": "update_kernel<2,5>", "alg_bytes_per_launch": per_launch,
+                "kernel": "update2d_kernel (2D wave kernel, N=5)", "alg_bytes_per_launch": per_launch,
                 "alg_bytes_per_cell": round(per_launch / cells, 3)}
 
     out = {
@@ -146,6 +163,7 @@ def main() -> int:
         "dof_updates_per_s": round(value * nq, 1),
         "roofline": roofline,
         "host_wall_s": round(wall, 4),
+        "tuning": fvpatch.fv_get_tuning(dim, nq, p),
     }
 
     if not args.no_cpu_baseline:
