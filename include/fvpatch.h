@@ -151,6 +151,66 @@ fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tunin
 /* Current parameters of the class (the installed ones, else the defaults). */
 fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *tuning);
 
+/*
+ * ---- Batching form: plans --------------------------------------------------
+ *
+ * A plan fixes a batch composition (sizes, offsets) once: it sorts the
+ * patches by size, largest first, cuts every size class into wave tasks with
+ * the launch parameters the tuning table holds for it, and uploads that work
+ * list.  Each step is then ONE fused launch over all 2D classes with
+ * p + 2 <= 64 (persistent: as many waves as fit the device walk the task
+ * list), plus one launch per remaining class (3D, or 2D p > 62).  The plan
+ * also captures k steps, with the time step formed on the device from each
+ * step's eigenvalues, into one hipGraph that replays without host round
+ * trips.  This is the paper's task fusion of T patch updates into one kernel
+ * (Sec. 2.1) with the precompiled task graph it proposes (Sec. 6, Sec. 8).
+ * Plans are single-owner objects; they keep their own device memory.
+ */
+typedef struct fv_plan fv_plan;
+
+#define FV_PLAN_NO_PERSIST 0x100u /* plan flag: one wave per task instead of a persistent grid */
+
+typedef struct fv_plan_stats {
+    int32_t num_patches;
+    int32_t num_tasks;          /* wave tasks of the fused launch */
+    int32_t num_class_launches; /* classes launched on their own each step */
+    int32_t prefetch;           /* row prefetch of the fused launch (0 = default) */
+    int32_t lds_per_wave_bytes; /* LDS a wave of the fused launch uses */
+    int32_t persistent;         /* 1: persistent grid */
+    int32_t captured_steps;     /* steps in the captured graph, 0 if none */
+} fv_plan_stats;
+
+/* Build a plan for the composition (sizes, offsets as for
+ * fv_patch_batch_update; offsets NULL = contiguous, equal sizes).  flags:
+ * FV_HALO_PERIODIC and/or FV_PLAN_NO_PERSIST.  Tuning installed later does
+ * not change an existing plan. */
+fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *offsets, int32_t num_patches,
+                         int32_t dim, int32_t unknowns, uint32_t flags);
+
+/* One step of every patch of the plan: like fv_patch_batch_update on the
+ * plan's composition.  Asynchronous on `stream`. */
+fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patches_out, double dt, double h,
+                          double gamma, double *lambda_out, void *stream);
+
+/* Capture `steps` steps into a graph: step k reads buf_a (k even) or buf_b
+ * (k odd) and writes the other (the result of an even number of steps is in
+ * buf_a).  Step 0 uses dt_dev[0], which the caller writes before each replay;
+ * after step k the eigenvalues in lambda_out (device [num_patches]) fix
+ * dt_dev[k+1] = cfl h / (dim max lambda) on the device (NaN-propagating).
+ * dt_dev: device [steps + 1].  `stream` must be a non-null stream; the capture
+ * enqueues nothing.  Replaces a previous capture of the plan. */
+fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, double *buf_b, double h, double gamma,
+                                double cfl, double *lambda_out, double *dt_dev, void *stream);
+
+/* Launch the captured graph on `stream`. */
+fv_status fv_plan_replay(fv_plan *plan, void *stream);
+
+/* Shape of the plan's work list. */
+fv_status fv_plan_info(const fv_plan *plan, fv_plan_stats *info);
+
+/* Wait for the device, then free the plan (NULL is a no-op). */
+fv_status fv_plan_destroy(fv_plan *plan);
+
 /* Text for a status code (static storage). */
 const char *fv_status_string(fv_status status);
 

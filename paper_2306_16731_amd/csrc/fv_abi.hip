@@ -59,12 +59,9 @@ static bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b
     return a0 < b1 && b0 < a1;
 }
 
-fv_status check_batch(const double *in, const double *out, const int32_t *sizes, const int64_t *offsets,
-                      int32_t num_patches, int32_t dim, int32_t nq, const double *lambda_out,
-                      BatchShape *shape) {
-    if (!in || !out || !sizes) return fail(FV_ERR_INVALID_ARG, "patches_in, patches_out and sizes must be non-null");
-    if (!aligned8(in) || !aligned8(out) || (lambda_out && !aligned8(lambda_out)))
-        return fail(FV_ERR_INVALID_ARG, "device pointers must be 8-byte aligned");
+fv_status check_layout(const int32_t *sizes, const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t nq,
+                       BatchShape *shape) {
+    if (!sizes) return fail(FV_ERR_INVALID_ARG, "sizes must be non-null");
     const int pmax = max_p(dim);
     shape->uniform_p = sizes[0];
     shape->contiguous = offsets == nullptr;
@@ -100,6 +97,14 @@ fv_status check_batch(const double *in, const double *out, const int32_t *sizes,
     }
     shape->lo = lo;
     shape->hi = hi;
+    return FV_OK;
+}
+
+fv_status check_buffers(const double *in, const double *out, const double *lambda_out, int32_t num_patches,
+                        int64_t lo, int64_t hi) {
+    if (!in || !out) return fail(FV_ERR_INVALID_ARG, "patches_in and patches_out must be non-null");
+    if (!aligned8(in) || !aligned8(out) || (lambda_out && !aligned8(lambda_out)))
+        return fail(FV_ERR_INVALID_ARG, "device pointers must be 8-byte aligned");
     const uintptr_t in0 = reinterpret_cast<uintptr_t>(in + lo), in1 = reinterpret_cast<uintptr_t>(in + hi);
     const uintptr_t o0 = reinterpret_cast<uintptr_t>(out + lo), o1 = reinterpret_cast<uintptr_t>(out + hi);
     if (ranges_overlap(in0, in1, o0, o1)) return fail(FV_ERR_OVERLAP, "patches_in and patches_out overlap");
@@ -109,6 +114,17 @@ fv_status check_batch(const double *in, const double *out, const int32_t *sizes,
             return fail(FV_ERR_OVERLAP, "lambda_out overlaps the patch buffers");
     }
     return FV_OK;
+}
+
+fv_status check_batch(const double *in, const double *out, const int32_t *sizes, const int64_t *offsets,
+                      int32_t num_patches, int32_t dim, int32_t nq, const double *lambda_out,
+                      BatchShape *shape) {
+    if (!in || !out || !sizes) return fail(FV_ERR_INVALID_ARG, "patches_in, patches_out and sizes must be non-null");
+    if (!aligned8(in) || !aligned8(out) || (lambda_out && !aligned8(lambda_out)))
+        return fail(FV_ERR_INVALID_ARG, "device pointers must be 8-byte aligned");
+    fv_status st = check_layout(sizes, offsets, num_patches, dim, nq, shape);
+    if (st != FV_OK) return st;
+    return check_buffers(in, out, lambda_out, num_patches, shape->lo, shape->hi);
 }
 
 // ---------------------------------------------------------------- device context

@@ -25,6 +25,18 @@ int64_t patch_doubles(int p, int dim, int nq);
 fv_status check_scalars(int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags);
 fv_status check_batch(const double *in, const double *out, const int32_t *sizes, const int64_t *offsets,
                       int32_t num_patches, int32_t dim, int32_t nq, const double *lambda_out, BatchShape *shape);
+// sizes / offsets only: ranges, bounds, overlaps between patches
+fv_status check_layout(const int32_t *sizes, const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t nq,
+                       BatchShape *shape);
+// device buffers over the extent [lo, hi) of a validated layout
+fv_status check_buffers(const double *in, const double *out, const double *lambda_out, int32_t num_patches,
+                        int64_t lo, int64_t hi);
+
+struct UpdateLaunch;
+// Launch parameters installed for a patch class (or the defaults), and their
+// application to a launch.
+fv_tuning tuning_for(int dim, int nq, int p);
+void apply_tuning(UpdateLaunch &L);
 
 struct DeviceContext;
 // Context of the current HIP device; FV_ERR_NO_DEVICE / FV_ERR_UNSUPPORTED

@@ -19,6 +19,7 @@ struct UpdateLaunch {
     int32_t nq = 5;
     int64_t stride = 0;                // doubles per patch when offsets == null
     double r = 0.0;                    // dt / h
+    const double *r_dev = nullptr;     // device dt / h (overrides r when set: device-side time step)
     double gamma = 1.4;
     uint32_t flags = 0;
     double *lambda_out = nullptr;      // device [max id + 1] or null
@@ -27,6 +28,36 @@ struct UpdateLaunch {
     int32_t prefetch = 0;              // rows in flight per lane (2D wave kernel), 0 = default
     bool vec2 = false;                 // every patch (and both buffers) 16-byte aligned: 16-byte loads
     int32_t rows = 0;                  // output rows staged per flush (2D wave kernel), 0 = default
+};
+
+// One wave's work in a task-list launch: `count` (<= 64 / (p + 2)) patches of
+// size p, at entries first .. first + count - 1 of the offsets / ids lists;
+// `rows` output rows are staged per flush.
+struct WaveTask {
+    int32_t p;
+    int32_t rows;
+    int32_t first;
+    int32_t count;
+};
+
+// One task-list launch of the 2D wave kernel over mixed patch sizes.
+struct TaskLaunch {
+    const double *in = nullptr;
+    double *out = nullptr;
+    const int64_t *offsets = nullptr;  // device, sorted into tasks
+    const int32_t *ids = nullptr;      // device, lambda index of each entry
+    const WaveTask *tasks = nullptr;   // device [num_tasks]
+    int32_t num_tasks = 0;
+    int32_t nq = 5;
+    int32_t ring_words = 0;            // LDS doubles per wave (max over the tasks' sizes)
+    int32_t prefetch = 0;
+    bool vec2 = false;
+    bool persistent = true;            // grid of resident waves looping over the tasks
+    double r = 0.0;
+    const double *r_dev = nullptr;
+    double gamma = 1.4;
+    uint32_t flags = 0;
+    double *lambda_out = nullptr;
 };
 
 // Lanes one patch occupies (its cross-section plane including halo volumes).
@@ -45,7 +76,9 @@ hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream);
 // 2D kernel with each padded patch row inside one wavefront (p + 2 <= 64).
 bool wave2d_fits(int p);
 size_t wave2d_lds_bytes(int p, int nq, int block, int rows);
+int wave2d_ring_words(int p, int nq, int rows);
 hipError_t launch_update2d(const UpdateLaunch &L, hipStream_t stream);
+hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream);
 
 // 2D kernel with whole patches per block, one thread per interior volume (p*p <= 1024).
 inline bool tile2d_fits(int p) { return p * p <= 1024; }
@@ -53,5 +86,11 @@ int tile2d_default_block(int p);
 size_t tile2d_lds_bytes(int p, int nq, int G);
 int tile2d_patches_per_block(int p, int nq, int block, size_t lds_limit);
 hipError_t launch_update2d_tile(const UpdateLaunch &L, hipStream_t stream);
+
+// dt_next = cfl h / (dim max lambda) and r_next = dt_next / h, on the device.
+hipError_t launch_next_dt(const double *lambda, int32_t n, double cfl, double h, int32_t dim, double *dt_out,
+                          double *r_out, hipStream_t stream);
+// r = dt / h on the device.
+hipError_t launch_ratio(const double *dt, double h, double *r_out, hipStream_t stream);
 
 }  // namespace fv

@@ -1,0 +1,330 @@
+// fv_plan.hip -- batching form: a fixed batch composition turned once into a
+// device work list, then one fused launch per step over all patch sizes, and
+// k steps with a device-side time step captured in one hipGraph.
+//
+// The paper bundles T patch updates into one kernel call (task fusion, Sec.
+// 2.1) and proposes, without being able to run it, to precompile the fixed
+// task graph so the GPU resolves the dependencies (Sec. 6, Sec. 8).  Here the
+// plan sorts the patches by size (largest first), cuts each size class into
+// wave tasks (floor(64 / (p+2)) patches per task) with the launch parameters
+// the tuning table holds for that class, and runs all classes in ONE launch of
+// the 2D wave kernel whose waves walk the task list (persistent: as many
+// waves as fit on the device).  Classes the wave kernel cannot take (3D, or
+// 2D p > 62) are launched per class inside the same step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "fvpatch.h"
+#include "fv_host.h"
+#include "fv_internal.h"
+
+struct fv_plan {
+    int device = -1;
+    int32_t dim = 2, nq = 5, num_patches = 0;
+    uint32_t flags = 0;
+    bool persistent = true;
+    int64_t lo = 0, hi = 0;  // extent in doubles
+    // device descriptors: offsets / ids sorted into tasks and groups, the task list
+    int64_t *d_offsets = nullptr;
+    int32_t *d_ids = nullptr;
+    fv::WaveTask *d_tasks = nullptr;
+    int32_t num_tasks = 0;
+    int32_t ring_words = 0;
+    int32_t prefetch = 0;
+    bool even_offsets = true;  // every wave-task patch starts at an even double and has even rows
+    struct Group {
+        int32_t p, first, count;
+    };
+    std::vector<Group> groups;  // classes launched per class (3D, 2D p > 62)
+    // captured multi-step run
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t steps = 0;
+    double *d_r = nullptr;  // dt / h per captured step
+};
+
+namespace fv {
+namespace {
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+[[maybe_unused]] bool overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) { return a0 < b1 && b0 < a1; }
+
+fv_status plan_buffers(const fv_plan *pl, const double *in, const double *out, const double *lambda_out) {
+    return check_buffers(in, out, lambda_out, pl->num_patches, pl->lo, pl->hi);
+}
+
+fv_status check_device(const fv_plan *pl) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FV_ERR_NO_DEVICE, "hipGetDevice failed");
+    if (dev != pl->device) return fail(FV_ERR_INVALID_ARG, "plan was created on device %d, current is %d", pl->device, dev);
+    return FV_OK;
+}
+
+// Enqueue one step of the plan: the fused task launch and the per-class launches.
+fv_status enqueue_step(const fv_plan *pl, const double *in, double *out, double r, const double *r_dev, double gamma,
+                       double *lambda_out, hipStream_t stream) {
+    if (pl->num_tasks > 0) {
+        TaskLaunch T;
+        T.in = in;
+        T.out = out;
+        T.offsets = pl->d_offsets;
+        T.ids = pl->d_ids;
+        T.tasks = pl->d_tasks;
+        T.num_tasks = pl->num_tasks;
+        T.nq = pl->nq;
+        T.ring_words = pl->ring_words;
+        T.prefetch = pl->prefetch;
+        T.vec2 = pl->even_offsets && aligned16(in) && aligned16(out);
+        T.persistent = pl->persistent;
+        T.r = r;
+        T.r_dev = r_dev;
+        T.gamma = gamma;
+        T.flags = pl->flags;
+        T.lambda_out = lambda_out;
+        hipError_t e = launch_update2d_tasks(T, stream);
+        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "fused launch failed: %s", hipGetErrorString(e));
+    }
+    for (const auto &g : pl->groups) {
+        UpdateLaunch L;
+        L.in = in;
+        L.out = out;
+        L.offsets = pl->d_offsets + g.first;
+        L.ids = pl->d_ids + g.first;
+        L.num_items = g.count;
+        L.p = g.p;
+        L.dim = pl->dim;
+        L.nq = pl->nq;
+        L.r = r;
+        L.r_dev = r_dev;
+        L.gamma = gamma;
+        L.flags = pl->flags;
+        L.lambda_out = lambda_out;
+        apply_tuning(L);
+        if (L.dim == 2 && L.kernel == FV_KERNEL_WAVE) L.kernel = FV_KERNEL_BLOCK;  // wave-eligible sizes are in the task list
+        hipError_t e = launch_update(L, stream);
+        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "class launch (p=%d) failed: %s", g.p, hipGetErrorString(e));
+    }
+    return FV_OK;
+}
+
+void release_graph(fv_plan *pl) {
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->d_r) (void)hipFree(pl->d_r);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+    pl->d_r = nullptr;
+    pl->steps = 0;
+}
+
+void release(fv_plan *pl) {
+    release_graph(pl);
+    if (pl->d_offsets) (void)hipFree(pl->d_offsets);
+    if (pl->d_ids) (void)hipFree(pl->d_ids);
+    if (pl->d_tasks) (void)hipFree(pl->d_tasks);
+    delete pl;
+}
+
+}  // namespace
+}  // namespace fv
+
+using namespace fv;
+
+extern "C" {
+
+fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *offsets, int32_t num_patches,
+                         int32_t dim, int32_t unknowns, uint32_t flags) {
+    clear_error();
+    if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
+    *plan = nullptr;
+    fv_status st = check_scalars(dim, unknowns, 1.0, 1.0, 2.0, flags & FV_HALO_PERIODIC);
+    if (st != FV_OK) return st;
+    if (flags & ~(FV_HALO_PERIODIC | FV_PLAN_NO_PERSIST)) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if (num_patches < 1) return fail(FV_ERR_INVALID_ARG, "a plan needs at least one patch");
+    BatchShape shape;
+    st = check_layout(sizes, offsets, num_patches, dim, unknowns, &shape);
+    if (st != FV_OK) return st;
+    DeviceContext *ctx = nullptr;
+    st = current_context(&ctx);
+    if (st != FV_OK) return st;
+
+    auto *pl = new fv_plan();
+    hipGetDevice(&pl->device);
+    pl->dim = dim;
+    pl->nq = unknowns;
+    pl->flags = flags & FV_HALO_PERIODIC;
+    pl->persistent = !(flags & FV_PLAN_NO_PERSIST);
+    pl->num_patches = num_patches;
+    pl->lo = shape.lo;
+    pl->hi = shape.hi;
+
+    // counting sort by size, largest first
+    const int pmax = max_p(dim);
+    std::vector<int32_t> count(pmax + 1, 0);
+    for (int32_t t = 0; t < num_patches; ++t) count[sizes[t]]++;
+    std::vector<int64_t> hoff(num_patches);
+    std::vector<int32_t> hid(num_patches);
+    std::vector<WaveTask> tasks;
+    int32_t cursor = 0;
+    int32_t best_cells = -1;
+    std::vector<int32_t> start(pmax + 1, 0);
+    for (int p = pmax; p >= 1; --p) {
+        start[p] = cursor;
+        cursor += count[p];
+    }
+    {
+        std::vector<int32_t> fill(start);
+        for (int32_t t = 0; t < num_patches; ++t) {
+            const int32_t k = fill[sizes[t]]++;
+            hoff[k] = offsets ? offsets[t] : (int64_t)t * patch_doubles(sizes[t], dim, unknowns);
+            hid[k] = t;
+        }
+    }
+    for (int p = pmax; p >= 1; --p) {
+        if (!count[p]) continue;
+        if (dim == 2 && wave2d_fits(p)) {
+            const fv_tuning tu = tuning_for(dim, unknowns, p);
+            const int rows = tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6;
+            const int ppw = 64 / (p + 2);
+            for (int32_t f = 0; f < count[p]; f += ppw)
+                tasks.push_back(WaveTask{p, rows, start[p] + f, std::min<int32_t>(ppw, count[p] - f)});
+            pl->ring_words = std::max(pl->ring_words, wave2d_ring_words(p, unknowns, rows));
+            const int64_t cells = (int64_t)count[p] * p * p;
+            if (cells > best_cells) {
+                best_cells = (int32_t)std::min<int64_t>(cells, INT32_MAX);
+                pl->prefetch = tu.kernel == FV_KERNEL_WAVE ? tu.prefetch : 0;
+            }
+            if (((p + 2) * unknowns) % 2) pl->even_offsets = false;
+            for (int32_t k = start[p]; k < start[p] + count[p]; ++k)
+                if (hoff[k] & 1) pl->even_offsets = false;
+        } else {
+            pl->groups.push_back(fv_plan::Group{p, start[p], count[p]});
+        }
+    }
+    pl->num_tasks = (int32_t)tasks.size();
+
+    // device copies of the work list
+    bool ok = hipMalloc(&pl->d_offsets, sizeof(int64_t) * num_patches) == hipSuccess &&
+              hipMalloc(&pl->d_ids, sizeof(int32_t) * num_patches) == hipSuccess &&
+              (tasks.empty() || hipMalloc(&pl->d_tasks, sizeof(WaveTask) * tasks.size()) == hipSuccess);
+    if (!ok) {
+        release(pl);
+        return fail(FV_ERR_OOM, "device allocation of the work list failed");
+    }
+    ok = hipMemcpy(pl->d_offsets, hoff.data(), sizeof(int64_t) * num_patches, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(pl->d_ids, hid.data(), sizeof(int32_t) * num_patches, hipMemcpyHostToDevice) == hipSuccess &&
+         (tasks.empty() ||
+          hipMemcpy(pl->d_tasks, tasks.data(), sizeof(WaveTask) * tasks.size(), hipMemcpyHostToDevice) == hipSuccess);
+    if (!ok) {
+        release(pl);
+        return fail(FV_ERR_LAUNCH, "upload of the work list failed");
+    }
+    *plan = pl;
+    return FV_OK;
+}
+
+fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patches_out, double dt, double h,
+                          double gamma, double *lambda_out, void *stream) {
+    clear_error();
+    if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
+    fv_status st = check_scalars(plan->dim, plan->nq, dt, h, gamma, 0);
+    if (st != FV_OK) return st;
+    if ((st = check_device(plan)) != FV_OK) return st;
+    if ((st = plan_buffers(plan, patches_in, patches_out, lambda_out)) != FV_OK) return st;
+    return enqueue_step(plan, patches_in, patches_out, dt / h, nullptr, gamma, lambda_out,
+                        static_cast<hipStream_t>(stream));
+}
+
+fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, double *buf_b, double h, double gamma,
+                                double cfl, double *lambda_out, double *dt_dev, void *stream) {
+    clear_error();
+    if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
+    if (steps < 1 || steps > 100000) return fail(FV_ERR_INVALID_ARG, "steps must be in [1, 100000]");
+    fv_status st = check_scalars(plan->dim, plan->nq, 1.0, h, gamma, 0);
+    if (st != FV_OK) return st;
+    if (!std::isfinite(cfl) || !(cfl > 0.0)) return fail(FV_ERR_INVALID_ARG, "cfl must be finite and > 0");
+    if (!lambda_out || !dt_dev) return fail(FV_ERR_INVALID_ARG, "lambda_out and dt_dev are required");
+    if (!aligned8(dt_dev)) return fail(FV_ERR_INVALID_ARG, "dt_dev must be 8-byte aligned");
+    if (!stream) return fail(FV_ERR_INVALID_ARG, "capture needs a non-null stream");
+    if ((st = check_device(plan)) != FV_OK) return st;
+    if ((st = plan_buffers(plan, buf_a, buf_b, lambda_out)) != FV_OK) return st;
+    {
+        const uintptr_t d0 = reinterpret_cast<uintptr_t>(dt_dev), d1 = reinterpret_cast<uintptr_t>(dt_dev + steps + 1);
+        const uintptr_t l0 = reinterpret_cast<uintptr_t>(lambda_out), l1 = reinterpret_cast<uintptr_t>(lambda_out + plan->num_patches);
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(buf_a + plan->lo), a1 = reinterpret_cast<uintptr_t>(buf_a + plan->hi);
+        const uintptr_t b0 = reinterpret_cast<uintptr_t>(buf_b + plan->lo), b1 = reinterpret_cast<uintptr_t>(buf_b + plan->hi);
+        if (overlap(d0, d1, l0, l1) || overlap(d0, d1, a0, a1) || overlap(d0, d1, b0, b1))
+            return fail(FV_ERR_OVERLAP, "dt_dev overlaps another buffer");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    release_graph(plan);
+    if (hipMalloc(&plan->d_r, sizeof(double) * (steps + 1)) != hipSuccess) return fail(FV_ERR_OOM, "device allocation failed");
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        release_graph(plan);
+        return fail(FV_ERR_LAUNCH, "hipStreamBeginCapture failed");
+    }
+    fv_status cap = FV_OK;
+    if (launch_ratio(dt_dev, h, plan->d_r, s) != hipSuccess) cap = fail(FV_ERR_LAUNCH, "capture of the first step size failed");
+    for (int32_t k = 0; k < steps && cap == FV_OK; ++k) {
+        const double *src = (k % 2 == 0) ? buf_a : buf_b;
+        double *dst = (k % 2 == 0) ? buf_b : buf_a;
+        cap = enqueue_step(plan, src, dst, 0.0, plan->d_r + k, gamma, lambda_out, s);
+        if (cap == FV_OK && launch_next_dt(lambda_out, plan->num_patches, cfl, h, plan->dim, dt_dev + k + 1,
+                                           plan->d_r + k + 1, s) != hipSuccess)
+            cap = fail(FV_ERR_LAUNCH, "capture of the step-size kernel failed");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (cap != FV_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        release_graph(plan);
+        return cap != FV_OK ? cap : fail(FV_ERR_LAUNCH, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    }
+    plan->graph = g;
+    if (hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        release_graph(plan);
+        return fail(FV_ERR_LAUNCH, "hipGraphInstantiate failed");
+    }
+    plan->steps = steps;
+    return FV_OK;
+}
+
+fv_status fv_plan_replay(fv_plan *plan, void *stream) {
+    clear_error();
+    if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
+    if (!plan->exec) return fail(FV_ERR_INVALID_ARG, "no captured steps: call fv_plan_capture_steps first");
+    fv_status st = check_device(plan);
+    if (st != FV_OK) return st;
+    if (hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(FV_ERR_LAUNCH, "hipGraphLaunch failed");
+    return FV_OK;
+}
+
+fv_status fv_plan_info(const fv_plan *plan, fv_plan_stats *info) {
+    clear_error();
+    if (!plan || !info) return fail(FV_ERR_INVALID_ARG, "plan and info must be non-null");
+    info->num_patches = plan->num_patches;
+    info->num_tasks = plan->num_tasks;
+    info->num_class_launches = (int32_t)plan->groups.size();
+    info->prefetch = plan->prefetch;
+    info->lds_per_wave_bytes = (int32_t)(plan->ring_words * sizeof(double));
+    info->persistent = plan->persistent ? 1 : 0;
+    info->captured_steps = plan->steps;
+    return FV_OK;
+}
+
+fv_status fv_plan_destroy(fv_plan *plan) {
+    clear_error();
+    if (!plan) return FV_OK;
+    (void)hipDeviceSynchronize();  // no replay or launch of this plan may still be running
+    release(plan);
+    return FV_OK;
+}
+
+}  // extern "C"

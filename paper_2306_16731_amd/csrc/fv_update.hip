@@ -67,9 +67,10 @@ template <int D, int NQ, int MAXB>
 __global__ void __launch_bounds__(MAXB)
 update_kernel(const double *__restrict__ in, double *__restrict__ out,
               const int64_t *__restrict__ offsets, const int32_t *__restrict__ ids,
-              int32_t num_items, int32_t P, int64_t stride, double r, double gamma,
-              uint32_t flags, double *__restrict__ lambda_out) {
+              int32_t num_items, int32_t P, int64_t stride, double r_host, const double *__restrict__ r_dev,
+              double gamma, uint32_t flags, double *__restrict__ lambda_out) {
     extern __shared__ double lds[];
+    const double r = r_dev ? *r_dev : r_host;
     using L = Lds<D, NQ>;
     const int B = blockDim.x;
     const int W = P + 2;
@@ -252,11 +253,11 @@ hipError_t launch_typed(const UpdateLaunch &L, hipStream_t stream) {
     }
     if (B <= 256)
         hipLaunchKernelGGL((update_kernel<D, NQ, 256>), dim3((unsigned)blocks), dim3(B), lds, stream,
-                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.gamma,
+                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma,
                            L.flags, L.lambda_out);
     else
         hipLaunchKernelGGL((update_kernel<D, NQ, 1024>), dim3((unsigned)blocks), dim3(B), lds, stream,
-                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.gamma,
+                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma,
                            L.flags, L.lambda_out);
     return hipGetLastError();
 }

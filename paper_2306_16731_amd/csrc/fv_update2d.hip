@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fv_internal.h"
 #include "fv_physics.h"
 
@@ -107,19 +109,22 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// One wave advances patches item0 .. item0 + ppw - 1 (those below num_items)
+// of size P.  Patch `item` starts at offsets[item] (or item * stride) and its
+// eigenvalue goes to lambda_out[ids[item]] (or [item]).  `ring` is the wave's
+// LDS region: R output rows of each patch, then the patch bases.
 template <int NQ, int PF, int VEC>
-__global__ void __launch_bounds__(256)
-update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
-                const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int64_t stride, double r,
-                double gamma, uint32_t flags, double *__restrict__ lambda_out, int32_t R) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void wave_update(const double *__restrict__ in, double *__restrict__ out,
+                                            const int64_t *__restrict__ offsets, const int32_t *__restrict__ ids,
+                                            int64_t item0, int64_t num_items, int P, int64_t stride, double r,
+                                            double gamma, uint32_t flags, double *__restrict__ lambda_out, int R,
+                                            double *ring) {
     const int W = P + 2;
     const int ppw = 64 / W;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int slot = lane / W;
     const int i = lane - slot * W;
-    const int64_t item = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw + slot;
+    const int64_t item = item0 + slot;
     const bool active = slot < ppw && item < num_items;
     const bool xin = i >= 1 && i <= P;
     const bool writer = active && xin;
@@ -130,10 +135,10 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
     const int64_t row = (int64_t)W * NQ;
     const bool periodic = (flags & kPeriodic) != 0;
 
-    // LDS: per wave, the ring of R output rows of each of its ppw patches, then their bases
+    // LDS: the ring of R output rows of each of the wave's ppw patches, then their bases
     const int ring_words = ppw * R * W * NQ;
-    double *ring = lds + (size_t)wave * (ring_words + ppw);
     int64_t *bases = reinterpret_cast<int64_t *>(ring + ring_words);
+    wave_lds_fence();  // a previous patch group of this wave may still be reading the ring
     if (i == 0 && slot < ppw) bases[slot] = active ? off : -1;
     wave_lds_fence();
     int k0 = 1;  // first output row held in the ring
@@ -241,6 +246,47 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
     }
 }
 
+
+// Uniform launch: every wave takes the next ppw patches of one size.
+template <int NQ, int PF, int VEC>
+__global__ void __launch_bounds__(256)
+update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
+                const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int64_t stride, double r,
+                const double *__restrict__ r_dev, double gamma, uint32_t flags, double *__restrict__ lambda_out,
+                int32_t R) {
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x >> 6;
+    const int ppw = 64 / (P + 2);
+    const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
+    const double rr = r_dev ? *r_dev : r;
+    wave_update<NQ, PF, VEC>(in, out, offsets, ids, item0, num_items, P, stride, rr, gamma, flags, lambda_out, R,
+                             lds + (size_t)wave * (ppw * R * (P + 2) * NQ + ppw));
+}
+
+// Task-list launch over mixed patch sizes: task t holds `count` patches of
+// size `p` at offsets[first ..] (ids[first ..]).  Each wave takes tasks
+// gw, gw + nw, ... (nw = waves in the grid), so a grid smaller than the task
+// list is persistent; tasks sorted largest first balance the tail.
+template <int NQ, int PF, int VEC>
+__global__ void __launch_bounds__(256)
+update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
+                      const int32_t *__restrict__ ids, const WaveTask *__restrict__ tasks, int32_t num_tasks,
+                      double r, const double *__restrict__ r_dev, double gamma, uint32_t flags,
+                      double *__restrict__ lambda_out, int32_t ring_words) {
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * waves + wave;
+    const int64_t nw = (int64_t)gridDim.x * waves;
+    const double rr = r_dev ? *r_dev : r;
+    double *ring = lds + (size_t)wave * ring_words;
+    for (int64_t t = gw; t < num_tasks; t += nw) {
+        const WaveTask tk = tasks[t];
+        wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma,
+                                 flags, lambda_out, tk.rows, ring);
+    }
+}
+
 size_t wave2d_lds_bytes_(int p, int nq, int block, int R) {
     const int W = p + 2, ppw = 64 / W;
     return sizeof(double) * (size_t)(block / 64) * (size_t)(ppw * R * W * nq + ppw);
@@ -268,7 +314,35 @@ hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((update2d_kernel<NQ, PF, VEC>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in, L.out,
-                       L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.gamma, L.flags, L.lambda_out, R);
+                       L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma, L.flags, L.lambda_out, R);
+    return hipGetLastError();
+}
+
+template <int NQ, int PF, int VEC>
+hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
+    const int B = 256;
+    const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)T.ring_words;
+    int dev = 0, lds_max = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return hipErrorInvalidDevice;
+    if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
+    const void *fn = reinterpret_cast<const void *>(&update2d_tasks_kernel<NQ, PF, VEC>);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int64_t blocks = ((int64_t)T.num_tasks + B / 64 - 1) / (B / 64);
+    if (T.persistent) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, B, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+        blocks = std::min<int64_t>(blocks, (int64_t)per_cu * cus);
+    }
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL((update2d_tasks_kernel<NQ, PF, VEC>), dim3((unsigned)blocks), dim3(B), lds, stream, T.in, T.out,
+                       T.offsets, T.ids, T.tasks, T.num_tasks, T.r, T.r_dev, T.gamma, T.flags, T.lambda_out,
+                       T.ring_words);
     return hipGetLastError();
 }
 
@@ -288,6 +362,29 @@ hipError_t launch2d_pf(const UpdateLaunch &L, hipStream_t stream) {
 }
 
 size_t wave2d_lds_bytes(int p, int nq, int block, int rows) { return wave2d_lds_bytes_(p, nq, block, rows); }
+
+int wave2d_ring_words(int p, int nq, int rows) {
+    const int W = p + 2, ppw = 64 / W;
+    return ppw * rows * W * nq + ppw;
+}
+
+template <int NQ, int VEC>
+static hipError_t tasks_pf(const TaskLaunch &T, hipStream_t stream) {
+    switch (T.prefetch > 0 ? T.prefetch : kDefaultPrefetch2d) {
+        case 1: return launch2d_tasks<NQ, 1, VEC>(T, stream);
+        case 2: return launch2d_tasks<NQ, 2, VEC>(T, stream);
+        case 3: return launch2d_tasks<NQ, 3, VEC>(T, stream);
+        case 4: return launch2d_tasks<NQ, 4, VEC>(T, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream) {
+    if (T.num_tasks <= 0) return hipSuccess;
+    if (T.nq == 5) return T.vec2 ? tasks_pf<5, 2>(T, stream) : tasks_pf<5, 1>(T, stream);
+    if (T.nq == 4) return T.vec2 ? tasks_pf<4, 2>(T, stream) : tasks_pf<4, 1>(T, stream);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_update2d(const UpdateLaunch &L, hipStream_t stream) {
     // 16-byte flush chunks need 16-byte aligned patches and an even row length

@@ -153,8 +153,10 @@ template <int NQ, int VEC>
 __global__ void __launch_bounds__(1024)
 update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                      const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int32_t G, int64_t stride,
-                     double r, double gamma, uint32_t flags, double *__restrict__ lambda_out) {
+                     double r_host, const double *__restrict__ r_dev, double gamma, uint32_t flags,
+                     double *__restrict__ lambda_out) {
     extern __shared__ double lds[];
+    const double r = r_dev ? *r_dev : r_host;
     const int B = blockDim.x;
     const int tid = threadIdx.x;
     const int C = P * P;
@@ -366,7 +368,7 @@ hipError_t launch_update2d_tile(const UpdateLaunch &L, hipStream_t stream) {
     }
 #define FV_TILE_LAUNCH(NQV, VV)                                                                                   \
     hipLaunchKernelGGL((update2d_tile_kernel<NQV, VV>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in, L.out, \
-                       L.offsets, L.ids, L.num_items, p, G, L.stride, L.r, L.gamma, L.flags, L.lambda_out)
+                       L.offsets, L.ids, L.num_items, p, G, L.stride, L.r, L.r_dev, L.gamma, L.flags, L.lambda_out)
     if (L.nq == 5) {
         if (vec2) FV_TILE_LAUNCH(5, 2);
         else FV_TILE_LAUNCH(5, 1);

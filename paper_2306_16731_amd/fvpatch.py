@@ -34,8 +34,10 @@ FV_MAX_P_2D = 64
 FV_MAX_P_3D = 24
 
 # Every symbol the header declares (checked by the tests against include/fvpatch.h).
-EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_status_string", "fv_last_error",
-           "fv_version"]
+EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_create", "fv_plan_execute",
+           "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_status_string",
+           "fv_last_error", "fv_version"]
+FV_PLAN_NO_PERSIST = 0x100
 FV_KERNEL_AUTO = 0
 FV_KERNEL_BLOCK = 1
 FV_KERNEL_WAVE = 2
@@ -57,6 +59,14 @@ class FvError(RuntimeError):
         super().__init__(f"{status_name(status)} ({status}): {detail}")
         self.status = status
         self.detail = detail
+
+
+class fv_plan_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("num_patches", "num_tasks", "num_class_launches", "prefetch",
+                                                "lds_per_wave_bytes", "persistent", "captured_steps")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 _lib = None
@@ -84,6 +94,19 @@ def load(path: str = LIBRARY):
     lib.fv_set_tuning.restype = ctypes.c_int
     lib.fv_get_tuning.argtypes = [i32, i32, i32, ctypes.POINTER(fv_tuning)]
     lib.fv_get_tuning.restype = ctypes.c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.fv_plan_create.argtypes = [pp, vp, vp, i32, i32, i32, u32]
+    lib.fv_plan_create.restype = ctypes.c_int
+    lib.fv_plan_execute.argtypes = [vp, vp, vp, f64, f64, f64, vp, vp]
+    lib.fv_plan_execute.restype = ctypes.c_int
+    lib.fv_plan_capture_steps.argtypes = [vp, i32, vp, vp, f64, f64, f64, vp, vp, vp]
+    lib.fv_plan_capture_steps.restype = ctypes.c_int
+    lib.fv_plan_replay.argtypes = [vp, vp]
+    lib.fv_plan_replay.restype = ctypes.c_int
+    lib.fv_plan_info.argtypes = [vp, ctypes.POINTER(fv_plan_stats)]
+    lib.fv_plan_info.restype = ctypes.c_int
+    lib.fv_plan_destroy.argtypes = [vp]
+    lib.fv_plan_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -173,3 +196,48 @@ def fv_get_tuning(dim: int, unknowns: int, p: int) -> dict:
     t = fv_tuning()
     _check(lib.fv_get_tuning(int(dim), int(unknowns), int(p), ctypes.byref(t)))
     return t.as_dict()
+
+
+# ---------------------------------------------------------------- plans (batching form)
+def fv_plan_create(sizes, offsets, num_patches: int, dim: int, unknowns: int, flags: int = 0,
+                   raise_on_error: bool = True):
+    """Build a plan; returns its handle (an int), or (status, None) when raise_on_error is False."""
+    lib = load()
+    h = ctypes.c_void_p()
+    sz, sz_p = _host_array(sizes, np.int32)
+    of, of_p = _host_array(offsets, np.int64)
+    st = lib.fv_plan_create(ctypes.byref(h), sz_p, of_p, int(num_patches), int(dim), int(unknowns), int(flags))
+    del sz, of
+    if raise_on_error:
+        _check(st)
+        return h.value
+    return st, h.value
+
+
+def fv_plan_execute(plan, patches_in, patches_out, dt: float, h: float, gamma: float = 1.4, lambda_out=None,
+                    stream=None, raise_on_error: bool = True) -> int:
+    st = load().fv_plan_execute(plan, _dev_ptr(patches_in), _dev_ptr(patches_out), float(dt), float(h), float(gamma),
+                                _dev_ptr(lambda_out), _stream_handle(stream))
+    return _check(st) if raise_on_error else st
+
+
+def fv_plan_capture_steps(plan, steps: int, buf_a, buf_b, h: float, gamma: float, cfl: float, lambda_out, dt_dev,
+                          stream=None, raise_on_error: bool = True) -> int:
+    st = load().fv_plan_capture_steps(plan, int(steps), _dev_ptr(buf_a), _dev_ptr(buf_b), float(h), float(gamma),
+                                      float(cfl), _dev_ptr(lambda_out), _dev_ptr(dt_dev), _stream_handle(stream))
+    return _check(st) if raise_on_error else st
+
+
+def fv_plan_replay(plan, stream=None, raise_on_error: bool = True) -> int:
+    st = load().fv_plan_replay(plan, _stream_handle(stream))
+    return _check(st) if raise_on_error else st
+
+
+def fv_plan_info(plan) -> dict:
+    info = fv_plan_stats()
+    _check(load().fv_plan_info(plan, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def fv_plan_destroy(plan) -> int:
+    return _check(load().fv_plan_destroy(plan))

@@ -128,3 +128,28 @@ def test_binding_has_no_compute_of_its_own():
     src = open(os.path.join(ROOT, "paper_2306_16731_amd", "fvpatch.py")).read()
     for token in ["sqrt", "gamma - 1", "0.5 *", "rusanov", "import oracle", "from oracle"]:
         assert token not in src.lower(), token
+
+
+def test_plan_validation_before_device():
+    """Plan creation rejects bad compositions before any device work."""
+    bad = [
+        (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=5, unknowns=5), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=None, num_patches=0, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 5], offsets=None, num_patches=2, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=[0, 10], num_patches=2, dim=2, unknowns=5), F.FV_ERR_OVERLAP),
+        (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5, flags=0x4), F.FV_ERR_INVALID_ARG),
+    ]
+    for kw, status in bad:
+        st, h = F.fv_plan_create(raise_on_error=False, **kw)
+        assert st == status and not h, (kw, st, F.fv_last_error())
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    st, h = F.fv_plan_create([4, 4], None, 2, 2, 5, raise_on_error=False)
+    assert st == F.FV_ERR_NO_DEVICE and not h
+    assert F.fv_plan_destroy(None) == F.FV_OK
+    assert F.load().fv_plan_replay(None, None) == F.FV_ERR_INVALID_ARG
+    assert F.load().fv_plan_execute(None, IN, OUT, 1e-3, 1 / 48, 1.4, None, None) == F.FV_ERR_INVALID_ARG

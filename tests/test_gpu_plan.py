@@ -1,0 +1,186 @@
+"""Batching form (plans) vs the CPU oracle through the C ABI (needs a gfx950 GPU).
+
+A plan runs every size class of a mixed batch in one fused launch (persistent
+or one wave per task), per-class launches for 3D and 2D p > 62, and captures k
+steps with a device-side time step in a hipGraph.  Tolerance as for the plain
+launch: 1e-12 per-unknown relative max-norm, and the same for lambda and for the
+device-formed time steps.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_16731_amd import workloads as wl
+from tests import hip_path as hp
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _announce(msg):
+    print(f"[gpu-plan] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_16731_amd import fvpatch
+    fvpatch.load()
+
+
+def oracle_dts(batch, steps, periodic, dt0, h=wl.H_DEFAULT, cfl=wl.CFL):
+    """The step sizes the oracle's own eigenvalues give, starting from dt0."""
+    state = batch.data.copy()
+    dts = [dt0]
+    for _ in range(steps):
+        state, lam = oracle.batch_update(state, batch.sizes, batch.offsets, batch.dim, batch.nq, dts[-1], h,
+                                         wl.GAMMA, periodic)
+        dts.append(cfl * h / (batch.dim * float(np.max(lam))))
+    return dts
+
+
+def run_plan(batch, dts, periodic, flags=0):
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    plan = fvpatch.fv_plan_create(batch.sizes, batch.offsets, batch.num_patches, batch.dim, batch.nq,
+                                  flags | (fvpatch.FV_HALO_PERIODIC if periodic else 0))
+    try:
+        info = fvpatch.fv_plan_info(plan)
+        a = hp.to_dev(batch.data)
+        b = a.clone()
+        lam = torch.empty((len(dts), batch.num_patches), dtype=torch.float64, device="cuda")
+        for s, dt in enumerate(dts):
+            fvpatch.fv_plan_execute(plan, a, b, dt, wl.H_DEFAULT, wl.GAMMA, lam[s])
+            a, b = b, a
+        torch.cuda.synchronize()
+        return a.cpu().numpy(), list(lam.cpu().numpy()), info
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+
+
+def check_against_oracle(batch, dts, periodic, got, got_lams):
+    want, want_lams = oracle.run_steps(batch.data, batch.sizes, batch.offsets, batch.dim, batch.nq, dts,
+                                       wl.H_DEFAULT, wl.GAMMA, periodic)
+    errs = hp.component_errors(got, want, batch.nq)
+    assert np.all(errs <= TOL), errs
+    assert max(hp.lambda_error(g, w) for g, w in zip(got_lams, want_lams)) <= TOL
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_plan_mixed_sizes(persistent):
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"plan: 3000 mixed {{3,5,9,17}}^2, 6 steps, persistent={persistent}")
+    b, _ = wl.build_workload("c3_2d_mixed_T200000", seed=21, num_patches=3000)
+    dts = oracle_dts(b, 5, False, 1.5e-3)
+    got, lams, info = run_plan(b, dts, False, 0 if persistent else fvpatch.FV_PLAN_NO_PERSIST)
+    assert info["num_class_launches"] == 0 and info["num_tasks"] > 0 and info["persistent"] == int(persistent)
+    check_against_oracle(b, dts, False, got, lams)
+
+
+def test_plan_mixed_with_large_class_odd_offsets_periodic():
+    """Sizes the wave kernel cannot take (p = 63, 64) run as class launches in the same step;
+    patches start at odd doubles (8- not 16-byte aligned), with gaps."""
+    _announce("plan: mixed with p in {1, 7, 16, 63, 64}, odd offsets, periodic")
+    rng = np.random.Generator(np.random.PCG64(31))
+    sizes = rng.choice(np.array([1, 7, 16, 63, 64], np.int32), size=150)
+    compact = wl.make_batch(sizes, 2, 5, seed=32)
+    vols = (sizes.astype(np.int64) + 2) ** 2 * 5
+    starts = np.cumsum(np.concatenate([[1], (vols + 3)[:-1]])).astype(np.int64)
+    data = np.zeros(int(starts[-1] + vols[-1] + 1))
+    for t in range(len(sizes)):
+        data[starts[t]:starts[t] + vols[t]] = compact.data[compact.offsets[t]:compact.offsets[t] + vols[t]]
+    batch = wl.Batch(data=data, sizes=sizes, offsets=starts, dim=2, nq=5)
+    dts = [1.1e-3, 0.9e-3, 1.2e-3]
+    got, lams, info = run_plan(batch, dts, True)
+    assert info["num_class_launches"] == 2
+    mask = np.zeros(len(data), bool)
+    for t in range(len(sizes)):
+        mask[starts[t]:starts[t] + vols[t]] = True
+    assert np.array_equal(got[~mask], data[~mask])
+    want, want_lams = oracle.run_steps(data, sizes, starts, 2, 5, dts, wl.H_DEFAULT, wl.GAMMA, True)
+    assert np.all(hp.component_errors(got[mask], want[mask], 5) <= TOL)
+    assert max(hp.lambda_error(g, w) for g, w in zip(lams, want_lams)) <= TOL
+
+
+def test_plan_3d():
+    _announce("plan: 300 x 8^3, 4 steps")
+    b, _ = wl.build_workload("c4_3d_p8_T32768", seed=22, num_patches=300)
+    dts = oracle_dts(b, 3, False, 1.2e-3)
+    got, lams, info = run_plan(b, dts, False)
+    assert info["num_tasks"] == 0 and info["num_class_launches"] == 1
+    check_against_oracle(b, dts, False, got, lams)
+
+
+@pytest.mark.parametrize("name,T,periodic", [("c3_2d_mixed_T200000", 2500, False), ("c4_3d_p8_T32768", 200, False),
+                                             ("c2_2d_p16_T65536", 600, True)])
+def test_graph_replay_with_device_dt(name, T, periodic):
+    """k steps captured in one graph; step sizes formed on the device from each step's
+    eigenvalues.  Replayed twice with eager work and synchronisations in between;
+    every replay is checked against the oracle run with the device's step sizes,
+    and those step sizes against the ones the oracle's own eigenvalues give."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"graph: {name} T={T}, 5 steps x 2 replays")
+    b, _ = wl.build_workload(name, seed=23, num_patches=T)
+    steps = 5
+    plan = fvpatch.fv_plan_create(b.sizes, b.offsets, b.num_patches, b.dim, b.nq,
+                                  fvpatch.FV_HALO_PERIODIC if periodic else 0)
+    try:
+        bufa = hp.to_dev(b.data)
+        bufb = bufa.clone()
+        lam = torch.empty(b.num_patches, dtype=torch.float64, device="cuda")
+        dt_dev = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+        s = torch.cuda.Stream()
+        fvpatch.fv_plan_capture_steps(plan, steps, bufa, bufb, wl.H_DEFAULT, wl.GAMMA, wl.CFL, lam, dt_dev, s)
+        assert fvpatch.fv_plan_info(plan)["captured_steps"] == steps
+        state = b.data.copy()
+        dt0 = 1.4e-3
+        for rep in range(2):
+            dt_dev[0] = dt0
+            torch.cuda.synchronize()
+            fvpatch.fv_plan_replay(plan, s)
+            s.synchronize()
+            got = (bufb if steps % 2 else bufa).cpu().numpy()
+            dts = dt_dev.cpu().numpy()
+            # eager work between replays (torch kernels, a copy, a sync)
+            scratch = torch.ones(1 << 20, device="cuda").cumsum(0)
+            torch.cuda.synchronize()
+            del scratch
+            want, want_lams = oracle.run_steps(state, b.sizes, b.offsets, b.dim, b.nq, list(dts[:steps]),
+                                               wl.H_DEFAULT, wl.GAMMA, periodic)
+            assert np.all(hp.component_errors(got, want, b.nq) <= TOL), rep
+            assert hp.lambda_error(lam.cpu().numpy(), want_lams[-1]) <= TOL
+            ref_dts = [dts[0]] + [wl.CFL * wl.H_DEFAULT / (b.dim * float(np.max(l))) for l in want_lams]
+            np.testing.assert_allclose(dts, ref_dts, rtol=TOL, atol=0)
+            # the next replay starts from this result: bring it back into buffer a
+            if steps % 2:
+                bufa.copy_(bufb)
+            torch.cuda.synchronize()
+            state = want
+            dt0 = float(dts[-1])
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+
+
+def test_plan_replay_without_capture_is_an_error():
+    from paper_2306_16731_amd import fvpatch
+    b = wl.make_uniform(4, 5, seed=3)
+    plan = fvpatch.fv_plan_create(b.sizes, None, 4, 2, 5)
+    try:
+        assert fvpatch.fv_plan_replay(plan, None, raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG
+        import torch
+        d = hp.to_dev(b.data)
+        assert fvpatch.fv_plan_execute(plan, d, d, 1e-3, wl.H_DEFAULT, raise_on_error=False) == fvpatch.FV_ERR_OVERLAP
+        assert fvpatch.fv_plan_capture_steps(plan, 2, d, d.clone(), wl.H_DEFAULT, wl.GAMMA, wl.CFL,
+                                             torch.empty(4, dtype=torch.float64, device="cuda"),
+                                             torch.empty(3, dtype=torch.float64, device="cuda"), None,
+                                             raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG  # null stream
+    finally:
+        fvpatch.fv_plan_destroy(plan)
