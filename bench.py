@@ -74,6 +74,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patches", type=int, default=4096,
                     help="patches the CPU oracle advances through all warmup + timed steps")
+    ap.add_argument("--form", choices=["plain", "batching", "serving"], default="plain",
+                    help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
+                         "plans and captured graphs (one line each).  serving: the request loop (config 5)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
+    ap.add_argument("--tuning-table", default=None, help="install this autotuner table instead of tuning now")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run 4 update launches and one 849,346,560-byte device copy, for rocprofv3 --pmc "
                          "FETCH_SIZE / WRITE_SIZE runs (the copy's reading is the counters' scale), then exit")
@@ -94,6 +99,11 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.form == "batching":
+        return bench_batching(args)
+    if args.form == "serving":
+        from paper_2306_16731_amd import serving
+        return serving.bench_main(args)
     dev = torch.device("cuda:0")
     name = "c2_2d_p16_T65536"
     b, spec = wl.build_workload(name, seed=args.seed)
@@ -188,6 +198,103 @@ def main() -> int:
         out["parity_sample"] = {"patches": S, "steps": steps_total, "max_rel_err": float(np.max(errs)),
                                 "tolerance": 1e-12}
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def _timed(fn, steps: int) -> float:
+    """Seconds for `steps` calls of fn, bracketed by device synchronisation."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def bench_batching(args) -> int:
+    """Configs 3 (200000 mixed 2D patches) and 4 (32768 x 8^3): plain per-batch launches vs a plan's fused
+    launch vs the captured 10-step graph.  Wall time between device synchronisations (the plain path's host
+    work counts: it is what the plan removes)."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import autotune, fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    h, gamma, steps = wl.H_DEFAULT, wl.GAMMA, 10
+    t_tune = time.perf_counter()
+    if args.tuning_table:
+        autotune.load(args.tuning_table)
+        tuned = {"table": os.path.basename(args.tuning_table)}
+    else:
+        tuned = autotune.tune_classes([(2, 5, p) for p in (3, 5, 9, 17)] + [(3, 5, 8)])
+    t_tune = time.perf_counter() - t_tune
+    for name in ("c3_2d_mixed_T200000", "c4_3d_p8_T32768"):
+        b, spec = wl.build_workload(name, seed=args.seed)
+        T, dim, nq = b.num_patches, b.dim, b.nq
+        periodic = spec["periodic"]
+        flags = fvpatch.FV_HALO_PERIODIC if periodic else 0
+        cells = b.interior_volumes()
+        a = torch.from_numpy(b.data).to("cuda")
+        c = a.clone()
+        lam = torch.empty(T, dtype=torch.float64, device="cuda")
+        dt = 1.0e-3
+        bufs = [a, c]
+
+        def plain():
+            fvpatch.fv_patch_batch_update(bufs[0], bufs[1], b.sizes, b.offsets, T, dim, nq, dt, h, gamma, flags, lam)
+            bufs.reverse()
+
+        for _ in range(args.warmup // 10 + 3):
+            plain()
+        results = {"plain": _timed(plain, steps) / steps}
+        plan_choice = autotune.tune_plan(b, periodic) if dim == 2 else {"persistent": True}
+        pflags = flags | (0 if plan_choice["persistent"] else fvpatch.FV_PLAN_NO_PERSIST)
+        plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags)
+        try:
+            info = fvpatch.fv_plan_info(plan)
+
+            def fused():
+                fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam)
+                bufs.reverse()
+
+            for _ in range(args.warmup // 10 + 3):
+                fused()
+            results["plan"] = _timed(fused, steps) / steps
+            dt_dev = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+            stream = torch.cuda.Stream()
+            fvpatch.fv_plan_capture_steps(plan, steps, a, c, h, gamma, wl.CFL, lam, dt_dev, stream)
+
+            def replay():
+                dt_dev[0] = dt
+                fvpatch.fv_plan_replay(plan, stream)
+                stream.synchronize()
+
+            for _ in range(3):
+                replay()
+            results["graph"] = _timed(replay, 5) / (5 * steps)
+            dts = dt_dev.cpu().numpy()
+        finally:
+            fvpatch.fv_plan_destroy(plan)
+        per_patch = [alg_bytes_per_patch(int(p), dim, nq, periodic, True) for p in b.sizes]
+        alg = float(np.sum(per_patch))
+        for form, sec in results.items():
+            line = {"metric": "cell-updates/s", "value": round(cells / sec, 1), "unit": "cell-updates/s",
+                    "form": form, "ms_per_step": round(sec * 1e3, 4), "alg_GBs": round(alg / sec / 1e9, 1),
+                    "hbm_frac": round(alg / sec / 1e9 / HBM_PEAK_GBS, 4),
+                    "speedup_vs_plain": round(results["plain"] / sec, 3), "dtype": "f64", "data": "synthetic",
+                    "config": {"workload": name, "patches": T, "dim": dim, "steps": steps, "cells_per_step": cells,
+                               "periodic_halo": periodic},
+                    "plan": info if form != "plain" else None,
+                    "plan_work_split": plan_choice if form != "plain" else None,
+                    "timing": "wall time between device synchronisations, host work included"}
+            if form == "graph":
+                line["device_dt"] = [float(x) for x in dts[:3]]
+            print(json.dumps(line), flush=True)
+        del a, c, lam
+        torch.cuda.empty_cache()
+    print(json.dumps({"autotune_seconds": round(t_tune, 2), "tuning": tuned}), flush=True)
     return 0
 
 

@@ -197,8 +197,9 @@ fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patch
  * buf_a).  Step 0 uses dt_dev[0], which the caller writes before each replay;
  * after step k the eigenvalues in lambda_out (device [num_patches]) fix
  * dt_dev[k+1] = cfl h / (dim max lambda) on the device (NaN-propagating).
- * dt_dev: device [steps + 1].  `stream` must be a non-null stream; the capture
- * enqueues nothing.  Replaces a previous capture of the plan. */
+ * dt_dev: device [steps + 1].  `stream` must be a non-null stream; before
+ * capturing, the call clears two internal words on `stream` and waits for it.
+ * Replaces a previous capture of the plan. */
 fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, double *buf_b, double h, double gamma,
                                 double cfl, double *lambda_out, double *dt_dev, void *stream);
 

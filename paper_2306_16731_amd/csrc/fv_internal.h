@@ -88,8 +88,10 @@ int tile2d_patches_per_block(int p, int nq, int block, size_t lds_limit);
 hipError_t launch_update2d_tile(const UpdateLaunch &L, hipStream_t stream);
 
 // dt_next = cfl h / (dim max lambda) and r_next = dt_next / h, on the device.
+// `slot` (max bits) and `done` (block counter) must be zero before the first launch; each launch
+// leaves them zero.
 hipError_t launch_next_dt(const double *lambda, int32_t n, double cfl, double h, int32_t dim, double *dt_out,
-                          double *r_out, hipStream_t stream);
+                          double *r_out, unsigned long long *slot, unsigned int *done, hipStream_t stream);
 // r = dt / h on the device.
 hipError_t launch_ratio(const double *dt, double h, double *r_out, hipStream_t stream);
 

@@ -46,6 +46,7 @@ struct fv_plan {
     hipGraphExec_t exec = nullptr;
     int32_t steps = 0;
     double *d_r = nullptr;  // dt / h per captured step
+    unsigned long long *d_slot = nullptr;  // max-eigenvalue bits and block counter of the step-size reduction
 };
 
 namespace fv {
@@ -117,6 +118,8 @@ void release_graph(fv_plan *pl) {
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     if (pl->d_r) (void)hipFree(pl->d_r);
+    if (pl->d_slot) (void)hipFree(pl->d_slot);
+    pl->d_slot = nullptr;
     pl->exec = nullptr;
     pl->graph = nullptr;
     pl->d_r = nullptr;
@@ -264,7 +267,17 @@ fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, dou
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     release_graph(plan);
-    if (hipMalloc(&plan->d_r, sizeof(double) * (steps + 1)) != hipSuccess) return fail(FV_ERR_OOM, "device allocation failed");
+    if (hipMalloc(&plan->d_r, sizeof(double) * (steps + 1)) != hipSuccess ||
+        hipMalloc(&plan->d_slot, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        release_graph(plan);
+        return fail(FV_ERR_OOM, "device allocation failed");
+    }
+    // zeroed once, outside the graph; every step-size launch leaves them zero
+    if (hipMemsetAsync(plan->d_slot, 0, 2 * sizeof(unsigned long long), s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        release_graph(plan);
+        return fail(FV_ERR_LAUNCH, "clearing the reduction slot failed");
+    }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
         release_graph(plan);
         return fail(FV_ERR_LAUNCH, "hipStreamBeginCapture failed");
@@ -276,7 +289,8 @@ fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, dou
         double *dst = (k % 2 == 0) ? buf_b : buf_a;
         cap = enqueue_step(plan, src, dst, 0.0, plan->d_r + k, gamma, lambda_out, s);
         if (cap == FV_OK && launch_next_dt(lambda_out, plan->num_patches, cfl, h, plan->dim, dt_dev + k + 1,
-                                           plan->d_r + k + 1, s) != hipSuccess)
+                                           plan->d_r + k + 1, plan->d_slot,
+                                           reinterpret_cast<unsigned int *>(plan->d_slot + 1), s) != hipSuccess)
             cap = fail(FV_ERR_LAUNCH, "capture of the step-size kernel failed");
     }
     hipGraph_t g = nullptr;
