@@ -212,6 +212,88 @@ fv_status fv_plan_info(const fv_plan *plan, fv_plan_stats *info);
 /* Wait for the device, then free the plan (NULL is a no-op). */
 fv_status fv_plan_destroy(fv_plan *plan);
 
+/*
+ * ---- Serving form: a request loop over device-resident patch state --------
+ *
+ * A mesh traversal hands the kernel batches of patches as it goes (task
+ * fusion of enclave tasks, Sec. 2.1).  The server keeps every registered
+ * mesh's patch state resident in HBM -- two state slots per patch, each patch
+ * ping-ponging on its own -- so no patch data crosses PCIe after registration
+ * (the recycled device memory of Sec. 4 "Data transfer", without the copies).
+ * A batch names a contiguous range of a mesh's patches and a time step.
+ * Batches are admitted in arrival order while the resident bytes plus the
+ * bytes of the batches in flight fit `budget_bytes` and fewer than
+ * `max_inflight` are running; otherwise they wait (none is dropped).  Each
+ * batch's latency runs from its arrival to the moment the loop sees its
+ * completion event.  Servers are single-owner objects with their own stream.
+ */
+typedef struct fv_server fv_server;
+
+#define FV_SERVE_FUSED 0 /* one fused launch per batch (task list, largest patches first) */
+#define FV_SERVE_PLAIN 1 /* each batch through the plain per-batch path (one launch per size class) */
+
+typedef struct fv_server_config {
+    int64_t budget_bytes; /* HBM budget for resident state plus in-flight batches */
+    int32_t dim;          /* 2 or 3 */
+    int32_t unknowns;     /* as for fv_patch_batch_update */
+    double h;             /* mesh width */
+    double gamma;         /* ratio of specific heats */
+    uint32_t flags;       /* 0 or FV_HALO_PERIODIC */
+    int32_t mode;         /* FV_SERVE_FUSED or FV_SERVE_PLAIN */
+    int32_t max_inflight; /* batches running at once (0 = 8), at most 1024 */
+    int32_t reserved;
+} fv_server_config;
+
+typedef struct fv_serve_request {
+    int64_t arrival_ns; /* fv_server_run_trace: offset from the start of the run */
+    int32_t mesh;
+    int32_t first;      /* patch range [first, first + count) of the mesh */
+    int32_t count;
+    int32_t reserved;
+    double dt;
+} fv_serve_request;
+
+typedef struct fv_server_stats {
+    int64_t submitted, completed, queued, inflight, peak_queued, peak_inflight;
+    int64_t cells_updated;  /* interior volumes updated by completed batches */
+    int64_t resident_bytes, budget_bytes;
+    double p50_ms, p99_ms, max_ms, mean_ms; /* arrival-to-completion latency of completed batches */
+    double cell_updates_per_s;               /* completed cells / (last completion - first arrival) */
+} fv_server_stats;
+
+fv_status fv_server_create(fv_server **server, const fv_server_config *cfg);
+
+/* Register a mesh: num_patches patches of the given sizes, stored contiguously
+ * in host_state (layout as for fv_patch_batch_update with offsets NULL but
+ * sizes free to differ); uploads it into both slots.  FV_ERR_BUDGET if its two
+ * slots do not fit the budget. */
+fv_status fv_server_add_mesh(fv_server *server, const int32_t *sizes, int32_t num_patches, const double *host_state,
+                             int32_t *mesh_id);
+
+/* Queue a batch (arrival_ns <= 0: now, on the server's steady clock in ns). */
+fv_status fv_server_submit(fv_server *server, int32_t mesh_id, int32_t first, int32_t count, double dt,
+                           int64_t arrival_ns, int64_t *ticket);
+
+/* Retire finished batches and admit queued ones; never blocks. */
+fv_status fv_server_poll(fv_server *server, fv_server_stats *stats);
+
+/* Run every queued batch to completion. */
+fv_status fv_server_drain(fv_server *server, fv_server_stats *stats);
+
+/* Replay a trace in the loop: request k is submitted when
+ * reqs[k].arrival_ns has elapsed since the call started (arrivals
+ * non-decreasing), the loop polling in between; then drains. */
+fv_status fv_server_run_trace(fv_server *server, const fv_serve_request *reqs, int64_t n, fv_server_stats *stats);
+
+/* Drain, then copy the mesh's current state into host_state (layout of
+ * fv_server_add_mesh). */
+fv_status fv_server_read_mesh(fv_server *server, int32_t mesh_id, double *host_state);
+
+fv_status fv_server_stats_get(fv_server *server, fv_server_stats *stats);
+
+/* Wait for the server's stream, then free everything it holds (NULL: no-op). */
+fv_status fv_server_destroy(fv_server *server);
+
 /* Text for a status code (static storage). */
 const char *fv_status_string(fv_status status);
 

@@ -249,10 +249,14 @@ void apply_tuning(UpdateLaunch &L) {
     L.rows = t.rows;
 }
 
-// Plain per-batch launch; arguments already validated.
+// Plain per-batch launch; arguments already validated.  out_offsets (host,
+// optional) places patch t's output at out + out_offsets[t] instead of at its
+// input offset (used by the serving loop, whose patches ping-pong between two
+// slots individually).
 fv_status plain_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets,
                        int32_t T, int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags,
-                       double *lambda_out, hipStream_t stream, const BatchShape &shape) {
+                       double *lambda_out, hipStream_t stream, const BatchShape &shape,
+                       const int64_t *out_offsets) {
     DeviceContext *ctx = nullptr;
     fv_status st = current_context(&ctx);
     if (st != FV_OK) return st;
@@ -265,7 +269,7 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
     L.gamma = gamma;
     L.flags = flags;
     L.lambda_out = lambda_out;
-    if (shape.contiguous) {
+    if (shape.contiguous && !out_offsets) {
         L.num_items = T;
         L.p = shape.uniform_p;
         L.stride = patch_doubles(L.p, dim, nq);
@@ -281,19 +285,26 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
     for (int32_t t = 0; t < T; ++t) count[sizes[t]]++;
     std::vector<int32_t> start(pmax + 2, 0);
     for (int p = 1; p <= pmax + 1; ++p) start[p] = start[p - 1] + count[p - 1];
-    const size_t bytes = (size_t)T * (sizeof(int64_t) + sizeof(int32_t));
+    const int64_t nout = out_offsets ? T : 0;
+    const size_t bytes = (size_t)T * (sizeof(int64_t) + sizeof(int32_t)) + (size_t)nout * sizeof(int64_t);
     DescSlot *slot = nullptr;
     st = acquire_slot(ctx, bytes, &slot);
     if (st != FV_OK) return st;
     int64_t *hoff = static_cast<int64_t *>(slot->host);
-    int32_t *hid = reinterpret_cast<int32_t *>(hoff + T);
+    int64_t *hout = hoff + T;
+    int32_t *hid = reinterpret_cast<int32_t *>(hout + nout);
     std::vector<int32_t> fill(start);
     std::vector<char> odd(pmax + 2, 0);  // some patch of this size starts at an odd double
     for (int32_t t = 0; t < T; ++t) {
         const int32_t k = fill[sizes[t]]++;
-        hoff[k] = offsets[t];
+        const int64_t o = offsets ? offsets[t] : (int64_t)t * patch_doubles(sizes[t], dim, nq);
+        hoff[k] = o;
         hid[k] = t;
-        odd[sizes[t]] |= (char)(offsets[t] & 1);
+        odd[sizes[t]] |= (char)(o & 1);
+        if (out_offsets) {
+            hout[k] = out_offsets[t];
+            odd[sizes[t]] |= (char)(out_offsets[t] & 1);
+        }
     }
     const bool bufs16 = aligned16(in) && aligned16(out);
     if (hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
@@ -301,12 +312,14 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         return fail(FV_ERR_LAUNCH, "descriptor upload failed");
     }
     const int64_t *doff = static_cast<const int64_t *>(slot->dev);
-    const int32_t *did = reinterpret_cast<const int32_t *>(doff + T);
+    const int64_t *dout = out_offsets ? doff + T : nullptr;
+    const int32_t *did = reinterpret_cast<const int32_t *>(doff + T + nout);
     for (int p = pmax; p >= 1; --p) {  // largest patches first
         if (!count[p]) continue;
         L.num_items = count[p];
         L.p = p;
         L.offsets = doff + start[p];
+        L.out_offsets = dout ? dout + start[p] : nullptr;
         L.ids = did + start[p];
         L.vec2 = bufs16 && !odd[p] && patch_doubles(p, dim, nq) % 2 == 0;
         apply_tuning(L);
@@ -338,7 +351,7 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out, c
     st = check_batch(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, lambda_out, &shape);
     if (st != FV_OK) return st;
     return plain_update(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, dt, h, gamma, flags,
-                        lambda_out, static_cast<hipStream_t>(stream), shape);
+                        lambda_out, static_cast<hipStream_t>(stream), shape, nullptr);
 }
 
 static fv_status check_class(int32_t dim, int32_t nq, int32_t p) {

@@ -38,6 +38,12 @@ struct UpdateLaunch;
 fv_tuning tuning_for(int dim, int nq, int p);
 void apply_tuning(UpdateLaunch &L);
 
+// Plain per-batch launch on validated arguments (out_offsets: optional host
+// array of output offsets; NULL = output at the input offsets).
+fv_status plain_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets, int32_t T,
+                       int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags, double *lambda_out,
+                       hipStream_t stream, const BatchShape &shape, const int64_t *out_offsets);
+
 struct DeviceContext;
 // Context of the current HIP device; FV_ERR_NO_DEVICE / FV_ERR_UNSUPPORTED
 // when there is none or it is not a gfx950.

@@ -12,6 +12,7 @@ struct UpdateLaunch {
     const double *in = nullptr;
     double *out = nullptr;
     const int64_t *offsets = nullptr;  // device [num_items] or null: item * stride
+    const int64_t *out_offsets = nullptr;  // device [num_items] or null: output at the input offsets
     const int32_t *ids = nullptr;      // device [num_items] or null: lambda index = item
     int32_t num_items = 0;
     int32_t p = 0;                     // interior volumes per axis
@@ -45,6 +46,7 @@ struct TaskLaunch {
     const double *in = nullptr;
     double *out = nullptr;
     const int64_t *offsets = nullptr;  // device, sorted into tasks
+    const int64_t *out_offsets = nullptr;  // device, output offsets in the same order (null: same as input)
     const int32_t *ids = nullptr;      // device, lambda index of each entry
     const WaveTask *tasks = nullptr;   // device [num_tasks]
     int32_t num_tasks = 0;

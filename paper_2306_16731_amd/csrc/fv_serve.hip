@@ -1,0 +1,542 @@
+// fv_serve.hip -- serving form: a request loop over device-resident patch state.
+//
+// A traversal of an adaptive mesh hands the kernel batches of patches as it
+// goes (task fusion of enclave tasks, Sec. 2.1); the paper's measurements are
+// dominated by moving those patches host <-> device and by allocating device
+// memory per kernel call, which it replaces by recycled ("managed") device
+// memory (Sec. 4, "Data transfer").  Here the patch state never leaves the
+// device: every registered mesh keeps two state slots per patch in HBM, each
+// patch ping-pongs between them on its own (a per-patch parity), and a batch
+// names a range of a mesh's patches.  Batches are admitted in arrival order
+// while the resident state plus the batches in flight fit an HBM byte budget
+// (otherwise they wait; none is dropped), launched on the server's stream,
+// and retired when their completion event has fired, which records the
+// arrival-to-completion latency.
+//
+// Two launch modes: FV_SERVE_FUSED builds the batch's task list (largest
+// patches first) in pinned staging memory and runs the whole batch in one
+// fused launch; FV_SERVE_PLAIN runs each batch through the plain per-batch
+// path (validation, grouping by size, one launch per size class).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <vector>
+
+#include "fvpatch.h"
+#include "fv_host.h"
+#include "fv_internal.h"
+
+namespace {
+
+using clock_type = std::chrono::steady_clock;
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(clock_type::now().time_since_epoch()).count();
+}
+
+struct Mesh {
+    std::vector<int32_t> sizes;
+    std::vector<int64_t> off;   // offset of each patch inside one slot (doubles)
+    std::vector<uint8_t> cur;   // slot holding each patch's current state
+    int64_t slot_doubles = 0;
+    double *buf = nullptr;      // two slots: [0, slot_doubles) and [slot_doubles, 2 slot_doubles)
+};
+
+struct Request {
+    int64_t ticket = 0;
+    int32_t mesh = 0, first = 0, count = 0;
+    double dt = 0.0;
+    int64_t arrival_ns = 0;
+};
+
+// Pinned + device staging of one in-flight batch (recycled, never freed while the server lives).
+struct Staging {
+    void *host = nullptr;
+    void *dev = nullptr;
+    size_t cap = 0;
+    double *lambda = nullptr;  // device [cap_patches]
+    int32_t cap_patches = 0;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+};
+
+struct Inflight {
+    Request req;
+    int staging = -1;
+    int64_t bytes = 0;
+    int64_t cells = 0;
+    hipEvent_t done = nullptr;  // event recorded after the batch's launches
+};
+
+}  // namespace
+
+struct fv_server {
+    fv_server_config cfg{};
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int64_t resident_bytes = 0;
+    int64_t inflight_bytes = 0;
+    std::vector<Mesh> meshes;
+    std::deque<Request> queue;
+    std::deque<Inflight> inflight;
+    std::vector<Staging> staging;
+    std::vector<hipEvent_t> spare_events;
+    std::vector<double> latency_ms;
+    int64_t next_ticket = 1;
+    int64_t submitted = 0, completed = 0, cells_updated = 0, peak_queue = 0, peak_inflight = 0;
+    int64_t first_arrival_ns = -1, last_completion_ns = -1;
+};
+
+namespace fv {
+namespace {
+
+int64_t batch_bytes(const Request &r) {
+    // descriptors (in and out offsets, ids, tasks) + lambda of the batch
+    return (int64_t)r.count * (8 + 8 + 4 + 16 + 8);
+}
+
+fv_status ensure_staging(fv_server *s, Staging &st, int32_t count) {
+    const size_t need = (size_t)count * (8 + 8 + 4 + sizeof(WaveTask)) + 16;
+    if (st.cap >= need && st.cap_patches >= count) return FV_OK;
+    if (st.busy) return fail(FV_ERR_LAUNCH, "staging buffer in use");
+    if (st.host) (void)hipHostFree(st.host);
+    if (st.dev) (void)hipFree(st.dev);
+    if (st.lambda) (void)hipFree(st.lambda);
+    st.host = st.dev = nullptr;
+    st.lambda = nullptr;
+    st.cap = 0;
+    st.cap_patches = 0;
+    const int32_t cp = std::max<int32_t>(count, 4096);
+    const size_t cap = (size_t)cp * (8 + 8 + 4 + sizeof(WaveTask)) + 16;  // + padding before the task list
+    if (hipHostMalloc(&st.host, cap, hipHostMallocDefault) != hipSuccess || hipMalloc(&st.dev, cap) != hipSuccess ||
+        hipMalloc(&st.lambda, sizeof(double) * cp) != hipSuccess)
+        return fail(FV_ERR_OOM, "staging allocation failed");
+    st.cap = cap;
+    st.cap_patches = cp;
+    (void)s;
+    return FV_OK;
+}
+
+// Launch one batch (fused mode): task list of the wave kernel for 2D p <= 62,
+// per-class launches otherwise.  Descriptors go through the staging buffer.
+fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
+    const int dim = s->cfg.dim, nq = s->cfg.unknowns;
+    const int pmax = max_p(dim);
+    const int32_t n = r.count;
+    int64_t *hin = static_cast<int64_t *>(st.host);
+    int64_t *hout = hin + n;
+    int32_t *hid = reinterpret_cast<int32_t *>(hout + n);
+    WaveTask *htask = reinterpret_cast<WaveTask *>(hid + n + (n & 1));
+    // counting sort by size, largest first
+    int32_t count[FV_MAX_P_2D + 1] = {0};
+    for (int32_t k = 0; k < n; ++k) count[m.sizes[r.first + k]]++;
+    int32_t start[FV_MAX_P_2D + 2] = {0};
+    int32_t cursor = 0;
+    for (int p = pmax; p >= 1; --p) {
+        start[p] = cursor;
+        cursor += count[p];
+    }
+    int32_t fill[FV_MAX_P_2D + 2];
+    std::memcpy(fill, start, sizeof(fill));
+    bool even = true;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t t = r.first + k;
+        const int32_t j = fill[m.sizes[t]]++;
+        const int64_t base_in = m.cur[t] ? m.slot_doubles : 0;
+        const int64_t base_out = m.cur[t] ? 0 : m.slot_doubles;
+        hin[j] = base_in + m.off[t];
+        hout[j] = base_out + m.off[t];
+        hid[j] = k;
+        if ((hin[j] | hout[j]) & 1) even = false;
+    }
+    int32_t ntask = 0, ring_words = 0, prefetch = 0;
+    int64_t best_cells = -1;
+    struct Cls { int p, first, count; };
+    std::vector<Cls> classes;
+    for (int p = pmax; p >= 1; --p) {
+        if (!count[p]) continue;
+        if (dim == 2 && wave2d_fits(p)) {
+            const fv_tuning tu = tuning_for(dim, nq, p);
+            const int rows = tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6;
+            const int ppw = 64 / (p + 2);
+            for (int32_t f = 0; f < count[p]; f += ppw)
+                htask[ntask++] = WaveTask{p, rows, start[p] + f, std::min<int32_t>(ppw, count[p] - f)};
+            ring_words = std::max(ring_words, wave2d_ring_words(p, nq, rows));
+            if ((int64_t)count[p] * p * p > best_cells) {
+                best_cells = (int64_t)count[p] * p * p;
+                prefetch = tu.kernel == FV_KERNEL_WAVE ? tu.prefetch : 0;
+            }
+            if (((p + 2) * nq) % 2) even = false;
+        } else {
+            classes.push_back(Cls{p, start[p], count[p]});
+        }
+    }
+    const size_t bytes = (size_t)(reinterpret_cast<char *>(htask + ntask) - static_cast<char *>(st.host));
+    if (hipMemcpyAsync(st.dev, st.host, bytes, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        return fail(FV_ERR_LAUNCH, "descriptor upload failed");
+    const int64_t *din = static_cast<const int64_t *>(st.dev);
+    const int64_t *dout = din + n;
+    const int32_t *did = reinterpret_cast<const int32_t *>(dout + n);
+    const WaveTask *dtask = reinterpret_cast<const WaveTask *>(did + n + (n & 1));
+    const double r_host = r.dt / s->cfg.h;
+    if (ntask > 0) {
+        TaskLaunch T;
+        T.in = m.buf;
+        T.out = m.buf;
+        T.offsets = din;
+        T.out_offsets = dout;
+        T.ids = did;
+        T.tasks = dtask;
+        T.num_tasks = ntask;
+        T.nq = nq;
+        T.ring_words = ring_words;
+        T.prefetch = prefetch;
+        T.vec2 = even && ((reinterpret_cast<uintptr_t>(m.buf) & 15u) == 0);
+        T.persistent = false;
+        T.r = r_host;
+        T.gamma = s->cfg.gamma;
+        T.flags = s->cfg.flags;
+        T.lambda_out = st.lambda;
+        hipError_t e = launch_update2d_tasks(T, s->stream);
+        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "fused launch failed: %s", hipGetErrorString(e));
+    }
+    for (const auto &c : classes) {
+        UpdateLaunch L;
+        L.in = m.buf;
+        L.out = m.buf;
+        L.offsets = din + c.first;
+        L.out_offsets = dout + c.first;
+        L.ids = did + c.first;
+        L.num_items = c.count;
+        L.p = c.p;
+        L.dim = dim;
+        L.nq = nq;
+        L.r = r_host;
+        L.gamma = s->cfg.gamma;
+        L.flags = s->cfg.flags;
+        L.lambda_out = st.lambda;
+        apply_tuning(L);
+        if (L.kernel == FV_KERNEL_WAVE) L.kernel = FV_KERNEL_BLOCK;
+        if (L.kernel == FV_KERNEL_TILE) L.vec2 = false;
+        hipError_t e = launch_update(L, s->stream);
+        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "class launch failed: %s", hipGetErrorString(e));
+    }
+    return FV_OK;
+}
+
+// Launch one batch through the plain per-batch path.
+fv_status launch_plain(fv_server *s, Mesh &m, const Request &r, Staging &st) {
+    const int32_t n = r.count;
+    std::vector<int64_t> in_off(n), out_off(n);
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t t = r.first + k;
+        in_off[k] = (m.cur[t] ? m.slot_doubles : 0) + m.off[t];
+        out_off[k] = (m.cur[t] ? 0 : m.slot_doubles) + m.off[t];
+    }
+    BatchShape shape;
+    fv_status stt = check_layout(m.sizes.data() + r.first, in_off.data(), n, s->cfg.dim, s->cfg.unknowns, &shape);
+    if (stt != FV_OK) return stt;
+    return plain_update(m.buf, m.buf, m.sizes.data() + r.first, in_off.data(), n, s->cfg.dim, s->cfg.unknowns, r.dt,
+                        s->cfg.h, s->cfg.gamma, s->cfg.flags, st.lambda, s->stream, shape, out_off.data());
+}
+
+hipEvent_t take_event(fv_server *s) {
+    if (!s->spare_events.empty()) {
+        hipEvent_t e = s->spare_events.back();
+        s->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Retire completed batches (in order); record their latency.
+void retire(fv_server *s, bool wait) {
+    while (!s->inflight.empty()) {
+        Inflight &f = s->inflight.front();
+        if (wait) {
+            if (hipEventSynchronize(f.done) != hipSuccess) break;
+        } else if (hipEventQuery(f.done) != hipSuccess) {
+            break;
+        }
+        const int64_t t = now_ns();
+        s->latency_ms.push_back((double)(t - f.req.arrival_ns) * 1e-6);
+        s->completed++;
+        s->cells_updated += f.cells;
+        s->last_completion_ns = t;
+        s->inflight_bytes -= f.bytes;
+        s->staging[f.staging].busy = false;
+        s->spare_events.push_back(f.done);
+        s->inflight.pop_front();
+    }
+}
+
+// Admit queued batches while the budget and the in-flight limit allow.
+fv_status admit(fv_server *s) {
+    while (!s->queue.empty()) {
+        const Request &r = s->queue.front();
+        const int64_t b = batch_bytes(r);
+        if ((int64_t)s->inflight.size() >= s->cfg.max_inflight) break;
+        if (s->resident_bytes + s->inflight_bytes + b > s->cfg.budget_bytes) {
+            if (s->inflight.empty())
+                return fail(FV_ERR_BUDGET, "batch of %d patches does not fit the budget even alone", r.count);
+            break;
+        }
+        int si = -1;
+        for (int k = 0; k < (int)s->staging.size(); ++k)
+            if (!s->staging[k].busy) {
+                si = k;
+                break;
+            }
+        if (si < 0) break;
+        Staging &st = s->staging[si];
+        fv_status e = ensure_staging(s, st, r.count);
+        if (e != FV_OK) return e;
+        Mesh &m = s->meshes[r.mesh];
+        e = (s->cfg.mode == FV_SERVE_PLAIN) ? launch_plain(s, m, r, st) : launch_fused(s, m, r, st);
+        if (e != FV_OK) return e;
+        Inflight f;
+        f.req = r;
+        f.staging = si;
+        f.bytes = b;
+        f.done = take_event(s);
+        if (!f.done || hipEventRecord(f.done, s->stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "event record failed");
+        for (int32_t k = 0; k < r.count; ++k) {
+            const int32_t t = r.first + k;
+            m.cur[t] ^= 1u;
+            f.cells += (int64_t)std::pow(m.sizes[t], s->cfg.dim);
+        }
+        st.busy = true;
+        s->inflight_bytes += b;
+        s->inflight.push_back(f);
+        s->peak_inflight = std::max<int64_t>(s->peak_inflight, (int64_t)s->inflight.size());
+        s->queue.pop_front();
+    }
+    return FV_OK;
+}
+
+double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+}
+
+void fill_stats(const fv_server *s, fv_server_stats *out) {
+    if (!out) return;
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->queued = (int64_t)s->queue.size();
+    out->inflight = (int64_t)s->inflight.size();
+    out->peak_queued = s->peak_queue;
+    out->peak_inflight = s->peak_inflight;
+    out->cells_updated = s->cells_updated;
+    out->resident_bytes = s->resident_bytes;
+    out->budget_bytes = s->cfg.budget_bytes;
+    out->p50_ms = percentile(s->latency_ms, 0.50);
+    out->p99_ms = percentile(s->latency_ms, 0.99);
+    out->max_ms = s->latency_ms.empty() ? 0.0 : *std::max_element(s->latency_ms.begin(), s->latency_ms.end());
+    double sum = 0.0;
+    for (double x : s->latency_ms) sum += x;
+    out->mean_ms = s->latency_ms.empty() ? 0.0 : sum / (double)s->latency_ms.size();
+    if (s->first_arrival_ns >= 0 && s->last_completion_ns > s->first_arrival_ns)
+        out->cell_updates_per_s = (double)s->cells_updated / ((double)(s->last_completion_ns - s->first_arrival_ns) * 1e-9);
+}
+
+fv_status check_server(fv_server *s) {
+    if (!s) return fail(FV_ERR_INVALID_ARG, "server must be non-null");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
+        return fail(FV_ERR_INVALID_ARG, "server was created on device %d, current is %d", s->device, dev);
+    return FV_OK;
+}
+
+}  // namespace
+}  // namespace fv
+
+using namespace fv;
+
+extern "C" {
+
+fv_status fv_server_create(fv_server **server, const fv_server_config *cfg) {
+    clear_error();
+    if (!server || !cfg) return fail(FV_ERR_INVALID_ARG, "server and cfg must be non-null");
+    *server = nullptr;
+    fv_status st = check_scalars(cfg->dim, cfg->unknowns, 1.0, cfg->h, cfg->gamma, cfg->flags);
+    if (st != FV_OK) return st;
+    if (cfg->budget_bytes <= 0) return fail(FV_ERR_INVALID_ARG, "budget_bytes must be > 0");
+    if (cfg->mode != FV_SERVE_FUSED && cfg->mode != FV_SERVE_PLAIN) return fail(FV_ERR_INVALID_ARG, "unknown mode %d", cfg->mode);
+    if (cfg->max_inflight < 0 || cfg->max_inflight > 1024) return fail(FV_ERR_INVALID_ARG, "max_inflight must be in [0, 1024]");
+    DeviceContext *ctx = nullptr;
+    if ((st = current_context(&ctx)) != FV_OK) return st;
+    auto *s = new fv_server();
+    s->cfg = *cfg;
+    if (s->cfg.max_inflight == 0) s->cfg.max_inflight = 8;
+    hipGetDevice(&s->device);
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return fail(FV_ERR_LAUNCH, "stream creation failed");
+    }
+    s->staging.resize(s->cfg.max_inflight);
+    *server = s;
+    return FV_OK;
+}
+
+fv_status fv_server_add_mesh(fv_server *s, const int32_t *sizes, int32_t num_patches, const double *host_state,
+                             int32_t *mesh_id) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (!sizes || !host_state || !mesh_id || num_patches < 1)
+        return fail(FV_ERR_INVALID_ARG, "sizes, host_state, mesh_id and num_patches >= 1 are required");
+    Mesh m;
+    m.sizes.assign(sizes, sizes + num_patches);
+    m.off.resize(num_patches);
+    m.cur.assign(num_patches, 0);
+    int64_t o = 0;
+    const int pmax = max_p(s->cfg.dim);
+    for (int32_t t = 0; t < num_patches; ++t) {
+        if (sizes[t] < 1 || sizes[t] > pmax) return fail(FV_ERR_INVALID_ARG, "sizes[%d]=%d outside [1, %d]", t, sizes[t], pmax);
+        m.off[t] = o;
+        o += patch_doubles(sizes[t], s->cfg.dim, s->cfg.unknowns);
+    }
+    m.slot_doubles = o + (o & 1);  // keep the second slot 16-byte aligned
+    const int64_t bytes = 2 * m.slot_doubles * (int64_t)sizeof(double);
+    if (s->resident_bytes + s->inflight_bytes + bytes > s->cfg.budget_bytes)
+        return fail(FV_ERR_BUDGET, "mesh of %lld bytes does not fit the budget (%lld resident of %lld)", (long long)bytes,
+                    (long long)s->resident_bytes, (long long)s->cfg.budget_bytes);
+    if (hipMalloc(&m.buf, bytes) != hipSuccess) return fail(FV_ERR_OOM, "device allocation of %lld bytes failed", (long long)bytes);
+    // both slots start from the given state (halo volumes included)
+    if (hipMemcpy(m.buf, host_state, o * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m.buf + m.slot_doubles, host_state, o * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(m.buf);
+        return fail(FV_ERR_LAUNCH, "upload of the mesh failed");
+    }
+    s->resident_bytes += bytes;
+    s->meshes.push_back(std::move(m));
+    *mesh_id = (int32_t)s->meshes.size() - 1;
+    return FV_OK;
+}
+
+fv_status fv_server_submit(fv_server *s, int32_t mesh_id, int32_t first, int32_t count, double dt, int64_t arrival_ns,
+                           int64_t *ticket) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (mesh_id < 0 || mesh_id >= (int32_t)s->meshes.size()) return fail(FV_ERR_INVALID_ARG, "unknown mesh %d", mesh_id);
+    const Mesh &m = s->meshes[mesh_id];
+    if (count < 1 || first < 0 || (int64_t)first + count > (int64_t)m.sizes.size())
+        return fail(FV_ERR_INVALID_ARG, "range [%d, %d) outside the mesh of %zu patches", first, first + count, m.sizes.size());
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV_ERR_INVALID_ARG, "dt must be finite and > 0");
+    Request r;
+    r.ticket = s->next_ticket++;
+    r.mesh = mesh_id;
+    r.first = first;
+    r.count = count;
+    r.dt = dt;
+    r.arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+    if (s->first_arrival_ns < 0 || r.arrival_ns < s->first_arrival_ns) s->first_arrival_ns = r.arrival_ns;
+    s->queue.push_back(r);
+    s->submitted++;
+    s->peak_queue = std::max<int64_t>(s->peak_queue, (int64_t)s->queue.size());
+    if (ticket) *ticket = r.ticket;
+    return FV_OK;
+}
+
+fv_status fv_server_poll(fv_server *s, fv_server_stats *stats) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    retire(s, false);
+    st = admit(s);
+    fill_stats(s, stats);
+    return st;
+}
+
+fv_status fv_server_drain(fv_server *s, fv_server_stats *stats) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    while (!s->queue.empty() || !s->inflight.empty()) {
+        if ((st = admit(s)) != FV_OK) return st;  // FV_ERR_BUDGET if a batch can never fit
+        retire(s, true);
+    }
+    fill_stats(s, stats);
+    return FV_OK;
+}
+
+fv_status fv_server_run_trace(fv_server *s, const fv_serve_request *reqs, int64_t n, fv_server_stats *stats) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (!reqs || n < 0) return fail(FV_ERR_INVALID_ARG, "reqs must be non-null");
+    for (int64_t k = 1; k < n; ++k)
+        if (reqs[k].arrival_ns < reqs[k - 1].arrival_ns) return fail(FV_ERR_INVALID_ARG, "arrivals must be non-decreasing");
+    const int64_t t0 = now_ns();
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t due = t0 + reqs[k].arrival_ns;
+        while (now_ns() < due) {
+            retire(s, false);
+            if ((st = admit(s)) != FV_OK) return st;
+        }
+        st = fv_server_submit(s, reqs[k].mesh, reqs[k].first, reqs[k].count, reqs[k].dt, due, nullptr);
+        if (st != FV_OK) return st;
+        retire(s, false);
+        if ((st = admit(s)) != FV_OK) return st;
+    }
+    return fv_server_drain(s, stats);
+}
+
+fv_status fv_server_read_mesh(fv_server *s, int32_t mesh_id, double *host_state) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (mesh_id < 0 || mesh_id >= (int32_t)s->meshes.size() || !host_state) return fail(FV_ERR_INVALID_ARG, "bad mesh or buffer");
+    if ((st = fv_server_drain(s, nullptr)) != FV_OK) return st;
+    const Mesh &m = s->meshes[mesh_id];
+    for (size_t t = 0; t < m.sizes.size(); ++t) {
+        const int64_t n = patch_doubles(m.sizes[t], s->cfg.dim, s->cfg.unknowns);
+        const double *src = m.buf + (m.cur[t] ? m.slot_doubles : 0) + m.off[t];
+        if (hipMemcpyAsync(host_state + m.off[t], src, n * sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+            return fail(FV_ERR_LAUNCH, "read-back failed");
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "read-back failed");
+    return FV_OK;
+}
+
+fv_status fv_server_stats_get(fv_server *s, fv_server_stats *stats) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (!stats) return fail(FV_ERR_INVALID_ARG, "stats must be non-null");
+    fill_stats(s, stats);
+    return FV_OK;
+}
+
+fv_status fv_server_destroy(fv_server *s) {
+    clear_error();
+    if (!s) return FV_OK;
+    (void)hipStreamSynchronize(s->stream);
+    for (auto &f : s->inflight) (void)hipEventDestroy(f.done);
+    for (auto e : s->spare_events) (void)hipEventDestroy(e);
+    for (auto &st : s->staging) {
+        if (st.host) (void)hipHostFree(st.host);
+        if (st.dev) (void)hipFree(st.dev);
+        if (st.lambda) (void)hipFree(st.lambda);
+    }
+    for (auto &m : s->meshes)
+        if (m.buf) (void)hipFree(m.buf);
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+    return FV_OK;
+}
+
+}  // extern "C"

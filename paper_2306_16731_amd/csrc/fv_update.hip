@@ -66,7 +66,8 @@ struct Lds {
 template <int D, int NQ, int MAXB>
 __global__ void __launch_bounds__(MAXB)
 update_kernel(const double *__restrict__ in, double *__restrict__ out,
-              const int64_t *__restrict__ offsets, const int32_t *__restrict__ ids,
+              const int64_t *__restrict__ offsets, const int64_t *__restrict__ out_offsets,
+              const int32_t *__restrict__ ids,
               int32_t num_items, int32_t P, int64_t stride, double r_host, const double *__restrict__ r_dev,
               double gamma, uint32_t flags, double *__restrict__ lambda_out) {
     extern __shared__ double lds[];
@@ -92,10 +93,11 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
     const bool used = active && (pint || xhalo || yhalo);
 
     const int64_t off = active ? (offsets ? offsets[item] : item * stride) : 0;
+    const int64_t off_out = active ? (out_offsets ? out_offsets[item] : off) : 0;
     const int64_t lane_off = (D == 2) ? (int64_t)i * NQ : ((int64_t)j * W + i) * NQ;
     const int64_t layer = (int64_t)S * NQ;        // doubles between marching layers
     const double *src = in + off + lane_off;
-    double *dst = out + off + lane_off;
+    double *dst = out + off_out + lane_off;
     const bool periodic = (flags & kPeriodic) != 0;
 
     // Registers carried from one layer to the next (marching axis m = D-1).
@@ -253,11 +255,13 @@ hipError_t launch_typed(const UpdateLaunch &L, hipStream_t stream) {
     }
     if (B <= 256)
         hipLaunchKernelGGL((update_kernel<D, NQ, 256>), dim3((unsigned)blocks), dim3(B), lds, stream,
-                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma,
+                           L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev,
+                           L.gamma,
                            L.flags, L.lambda_out);
     else
         hipLaunchKernelGGL((update_kernel<D, NQ, 1024>), dim3((unsigned)blocks), dim3(B), lds, stream,
-                           L.in, L.out, L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma,
+                           L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev,
+                           L.gamma,
                            L.flags, L.lambda_out);
     return hipGetLastError();
 }

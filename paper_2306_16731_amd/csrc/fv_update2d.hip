@@ -110,12 +110,15 @@ __device__ __forceinline__ void wave_lds_fence() {
 }
 
 // One wave advances patches item0 .. item0 + ppw - 1 (those below num_items)
-// of size P.  Patch `item` starts at offsets[item] (or item * stride) and its
-// eigenvalue goes to lambda_out[ids[item]] (or [item]).  `ring` is the wave's
+// of size P.  Patch `item` starts at offsets[item] (or item * stride) in `in`
+// and at out_offsets[item] (or the same offset) in `out`; its eigenvalue goes
+// to lambda_out[ids[item]] (or [item]).  `ring` is the wave's
 // LDS region: R output rows of each patch, then the patch bases.
 template <int NQ, int PF, int VEC>
 __device__ __forceinline__ void wave_update(const double *__restrict__ in, double *__restrict__ out,
-                                            const int64_t *__restrict__ offsets, const int32_t *__restrict__ ids,
+                                            const int64_t *__restrict__ offsets,
+                                            const int64_t *__restrict__ out_offsets,
+                                            const int32_t *__restrict__ ids,
                                             int64_t item0, int64_t num_items, int P, int64_t stride, double r,
                                             double gamma, uint32_t flags, double *__restrict__ lambda_out, int R,
                                             double *ring) {
@@ -130,8 +133,9 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
     const bool writer = active && xin;
 
     const int64_t off = active ? (offsets ? offsets[item] : item * stride) : 0;
+    const int64_t off_out = active ? (out_offsets ? out_offsets[item] : off) : 0;
     const double *src = in + off + (int64_t)i * NQ;
-    double *dst = out + off + (int64_t)i * NQ;
+    double *dst = out + off_out + (int64_t)i * NQ;
     const int64_t row = (int64_t)W * NQ;
     const bool periodic = (flags & kPeriodic) != 0;
 
@@ -139,7 +143,7 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
     const int ring_words = ppw * R * W * NQ;
     int64_t *bases = reinterpret_cast<int64_t *>(ring + ring_words);
     wave_lds_fence();  // a previous patch group of this wave may still be reading the ring
-    if (i == 0 && slot < ppw) bases[slot] = active ? off : -1;
+    if (i == 0 && slot < ppw) bases[slot] = active ? off_out : -1;
     wave_lds_fence();
     int k0 = 1;  // first output row held in the ring
 
@@ -251,7 +255,8 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
 template <int NQ, int PF, int VEC>
 __global__ void __launch_bounds__(256)
 update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
-                const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int64_t stride, double r,
+                const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
+                int32_t P, int64_t stride, double r,
                 const double *__restrict__ r_dev, double gamma, uint32_t flags, double *__restrict__ lambda_out,
                 int32_t R) {
     extern __shared__ double lds[];
@@ -259,7 +264,8 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
     const int ppw = 64 / (P + 2);
     const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
     const double rr = r_dev ? *r_dev : r;
-    wave_update<NQ, PF, VEC>(in, out, offsets, ids, item0, num_items, P, stride, rr, gamma, flags, lambda_out, R,
+    wave_update<NQ, PF, VEC>(in, out, offsets, out_offsets, ids, item0, num_items, P, stride, rr, gamma, flags,
+                             lambda_out, R,
                              lds + (size_t)wave * (ppw * R * (P + 2) * NQ + ppw));
 }
 
@@ -270,7 +276,8 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
 template <int NQ, int PF, int VEC>
 __global__ void __launch_bounds__(256)
 update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
-                      const int32_t *__restrict__ ids, const WaveTask *__restrict__ tasks, int32_t num_tasks,
+                      const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids,
+                      const WaveTask *__restrict__ tasks, int32_t num_tasks,
                       double r, const double *__restrict__ r_dev, double gamma, uint32_t flags,
                       double *__restrict__ lambda_out, int32_t ring_words) {
     extern __shared__ double lds[];
@@ -282,8 +289,8 @@ update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, c
     double *ring = lds + (size_t)wave * ring_words;
     for (int64_t t = gw; t < num_tasks; t += nw) {
         const WaveTask tk = tasks[t];
-        wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma,
-                                 flags, lambda_out, tk.rows, ring);
+        wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, out_offsets ? out_offsets + tk.first : nullptr,
+                                 ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma, flags, lambda_out, tk.rows, ring);
     }
 }
 
@@ -314,7 +321,8 @@ hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((update2d_kernel<NQ, PF, VEC>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in, L.out,
-                       L.offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma, L.flags, L.lambda_out, R);
+                       L.offsets, L.out_offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev, L.gamma, L.flags,
+                       L.lambda_out, R);
     return hipGetLastError();
 }
 
@@ -341,7 +349,8 @@ hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
     }
     if (blocks < 1) return hipSuccess;
     hipLaunchKernelGGL((update2d_tasks_kernel<NQ, PF, VEC>), dim3((unsigned)blocks), dim3(B), lds, stream, T.in, T.out,
-                       T.offsets, T.ids, T.tasks, T.num_tasks, T.r, T.r_dev, T.gamma, T.flags, T.lambda_out,
+                       T.offsets, T.out_offsets, T.ids, T.tasks, T.num_tasks, T.r, T.r_dev, T.gamma, T.flags,
+                       T.lambda_out,
                        T.ring_words);
     return hipGetLastError();
 }

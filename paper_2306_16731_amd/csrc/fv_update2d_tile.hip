@@ -152,7 +152,7 @@ struct AxisTile {
 template <int NQ, int VEC>
 __global__ void __launch_bounds__(1024)
 update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
-                     const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int32_t G, int64_t stride,
+                     const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items, int32_t P, int32_t G, int64_t stride,
                      double r_host, const double *__restrict__ r_dev, double gamma, uint32_t flags,
                      double *__restrict__ lambda_out) {
     extern __shared__ double lds[];
@@ -168,12 +168,14 @@ update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, co
     double *FB = QS + (size_t)G * QW;              // [G][NQ+1][FC]  user terms F_n, l_n
     double *FH = FB + (size_t)G * (NQ + 1) * FC;   // [G][NQ][HF]    face fluxes
     int64_t *POFF = reinterpret_cast<int64_t *>(FH + (size_t)G * NQ * HF);  // [G] patch offsets
-    unsigned long long *PMAX = reinterpret_cast<unsigned long long *>(POFF + G);  // [G] lambda bits
+    int64_t *POUT = POFF + G;                                                       // [G] output offsets
+    unsigned long long *PMAX = reinterpret_cast<unsigned long long *>(POUT + G);  // [G] lambda bits
 
     const int64_t item0 = (int64_t)blockIdx.x * G;
     if (tid < G) {
         const int64_t it = item0 + tid;
         POFF[tid] = it < num_items ? (offsets ? offsets[it] : it * stride) : -1;
+        POUT[tid] = it < num_items ? (out_offsets ? out_offsets[it] : POFF[tid]) : -1;
         PMAX[tid] = 0ull;
     }
     block_lds_barrier();
@@ -285,7 +287,7 @@ update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, co
 #pragma unroll
         for (int k = 0; k < NQ; ++k) dsum[k] = dx[k] + dy[k];
         advance<NQ>(q, dsum, r, qn);
-        double *dst = out + POFF[g] + (j * W + i) * NQ;
+        double *dst = out + POUT[g] + (j * W + i) * NQ;
         store_volume<NQ>(dst, qn);
         if (flags & kPeriodic) {
             if (i == P) store_volume<NQ>(dst - (int64_t)P * NQ, qn);
@@ -322,7 +324,7 @@ update2d_tile_kernel(const double *__restrict__ in, double *__restrict__ out, co
 int tile2d_threads(int p) { return p * p; }
 
 size_t tile2d_lds_bytes(int p, int nq, int G) {
-    return sizeof(double) * (size_t)G * (size_t)tile_words(p, nq) + 16 * (size_t)G;
+    return sizeof(double) * (size_t)G * (size_t)tile_words(p, nq) + 24 * (size_t)G;
 }
 
 // Patches per block for a tile launch of `block` threads (0 when it does not fit).
@@ -368,7 +370,8 @@ hipError_t launch_update2d_tile(const UpdateLaunch &L, hipStream_t stream) {
     }
 #define FV_TILE_LAUNCH(NQV, VV)                                                                                   \
     hipLaunchKernelGGL((update2d_tile_kernel<NQV, VV>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in, L.out, \
-                       L.offsets, L.ids, L.num_items, p, G, L.stride, L.r, L.r_dev, L.gamma, L.flags, L.lambda_out)
+                       L.offsets, L.out_offsets, L.ids, L.num_items, p, G, L.stride, L.r, L.r_dev, L.gamma, L.flags, \
+                       L.lambda_out)
     if (L.nq == 5) {
         if (vec2) FV_TILE_LAUNCH(5, 2);
         else FV_TILE_LAUNCH(5, 1);

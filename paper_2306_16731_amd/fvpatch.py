@@ -35,8 +35,12 @@ FV_MAX_P_3D = 24
 
 # Every symbol the header declares (checked by the tests against include/fvpatch.h).
 EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_create", "fv_plan_execute",
-           "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_status_string",
+           "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_server_create",
+           "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
+           "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_status_string",
            "fv_last_error", "fv_version"]
+FV_SERVE_FUSED = 0
+FV_SERVE_PLAIN = 1
 FV_PLAN_NO_PERSIST = 0x100
 FV_KERNEL_AUTO = 0
 FV_KERNEL_BLOCK = 1
@@ -64,6 +68,30 @@ class FvError(RuntimeError):
 class fv_plan_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("num_patches", "num_tasks", "num_class_launches", "prefetch",
                                                 "lds_per_wave_bytes", "persistent", "captured_steps")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class fv_server_config(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("dim", ctypes.c_int32), ("unknowns", ctypes.c_int32),
+                ("h", ctypes.c_double), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("mode", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class fv_serve_request(ctypes.Structure):
+    _fields_ = [("arrival_ns", ctypes.c_int64), ("mesh", ctypes.c_int32), ("first", ctypes.c_int32),
+                ("count", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dt", ctypes.c_double)]
+
+
+SERVE_REQUEST_DTYPE = np.dtype([("arrival_ns", "<i8"), ("mesh", "<i4"), ("first", "<i4"), ("count", "<i4"),
+                                ("reserved", "<i4"), ("dt", "<f8")])
+
+
+class fv_server_stats(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int64) for n in ("submitted", "completed", "queued", "inflight", "peak_queued",
+                                               "peak_inflight", "cells_updated", "resident_bytes", "budget_bytes")]
+                + [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "cell_updates_per_s")])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -107,6 +135,19 @@ def load(path: str = LIBRARY):
     lib.fv_plan_info.restype = ctypes.c_int
     lib.fv_plan_destroy.argtypes = [vp]
     lib.fv_plan_destroy.restype = ctypes.c_int
+    sp = ctypes.POINTER(fv_server_stats)
+    lib.fv_server_create.argtypes = [pp, ctypes.POINTER(fv_server_config)]
+    lib.fv_server_add_mesh.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.fv_server_submit.argtypes = [vp, i32, i32, i32, f64, i64, ctypes.POINTER(ctypes.c_int64)]
+    lib.fv_server_poll.argtypes = [vp, sp]
+    lib.fv_server_drain.argtypes = [vp, sp]
+    lib.fv_server_run_trace.argtypes = [vp, vp, i64, sp]
+    lib.fv_server_read_mesh.argtypes = [vp, i32, vp]
+    lib.fv_server_stats_get.argtypes = [vp, sp]
+    lib.fv_server_destroy.argtypes = [vp]
+    for name in ("fv_server_create", "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain",
+                 "fv_server_run_trace", "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -241,3 +282,82 @@ def fv_plan_info(plan) -> dict:
 
 def fv_plan_destroy(plan) -> int:
     return _check(load().fv_plan_destroy(plan))
+
+
+# ---------------------------------------------------------------- servers (serving form)
+def fv_server_create(budget_bytes: int, dim: int, unknowns: int, h: float, gamma: float = 1.4, flags: int = 0,
+                     mode: int = 0, max_inflight: int = 0, raise_on_error: bool = True):
+    cfg = fv_server_config(int(budget_bytes), int(dim), int(unknowns), float(h), float(gamma), int(flags), int(mode),
+                           int(max_inflight), 0)
+    hdl = ctypes.c_void_p()
+    st = load().fv_server_create(ctypes.byref(hdl), ctypes.byref(cfg))
+    if raise_on_error:
+        _check(st)
+        return hdl.value
+    return st, hdl.value
+
+
+def fv_server_add_mesh(server, sizes, host_state, raise_on_error: bool = True):
+    """Register a mesh (host_state: float64 array in the contiguous layout); returns its id."""
+    sz, sz_p = _host_array(sizes, np.int32)
+    state = np.ascontiguousarray(host_state, dtype=np.float64)
+    mid = ctypes.c_int32(-1)
+    st = load().fv_server_add_mesh(server, sz_p, len(sz), state.ctypes.data, ctypes.byref(mid))
+    del sz
+    if raise_on_error:
+        _check(st)
+        return mid.value
+    return st, mid.value
+
+
+def fv_server_submit(server, mesh: int, first: int, count: int, dt: float, arrival_ns: int = 0,
+                     raise_on_error: bool = True):
+    ticket = ctypes.c_int64(0)
+    st = load().fv_server_submit(server, int(mesh), int(first), int(count), float(dt), int(arrival_ns),
+                                 ctypes.byref(ticket))
+    if raise_on_error:
+        _check(st)
+        return ticket.value
+    return st
+
+
+def _stats_call(fn, server, raise_on_error=True):
+    out = fv_server_stats()
+    st = fn(server, ctypes.byref(out))
+    if raise_on_error:
+        _check(st)
+        return out.as_dict()
+    return st, out.as_dict()
+
+
+def fv_server_poll(server, raise_on_error: bool = True):
+    return _stats_call(load().fv_server_poll, server, raise_on_error)
+
+
+def fv_server_drain(server, raise_on_error: bool = True):
+    return _stats_call(load().fv_server_drain, server, raise_on_error)
+
+
+def fv_server_stats_get(server):
+    return _stats_call(load().fv_server_stats_get, server)
+
+
+def fv_server_run_trace(server, requests: np.ndarray, raise_on_error: bool = True):
+    """requests: structured array of SERVE_REQUEST_DTYPE (arrival_ns relative to the start)."""
+    req = np.ascontiguousarray(requests, dtype=SERVE_REQUEST_DTYPE)
+    out = fv_server_stats()
+    st = load().fv_server_run_trace(server, req.ctypes.data, len(req), ctypes.byref(out))
+    if raise_on_error:
+        _check(st)
+        return out.as_dict()
+    return st, out.as_dict()
+
+
+def fv_server_read_mesh(server, mesh: int, out: np.ndarray) -> np.ndarray:
+    assert out.dtype == np.float64 and out.flags.c_contiguous
+    _check(load().fv_server_read_mesh(server, int(mesh), out.ctypes.data))
+    return out
+
+
+def fv_server_destroy(server) -> int:
+    return _check(load().fv_server_destroy(server))

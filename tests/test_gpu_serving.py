@@ -1,0 +1,148 @@
+"""Serving form vs the CPU oracle through the C ABI (needs a gfx950 GPU).
+
+A server keeps a mesh's patch state on the device and applies batches (ranges
+of patches, each with its own time step) in arrival order.  The final state it
+reads back must equal, to 1e-12, the oracle applying the same batches in the
+same order to the host copy of the mesh.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_16731_amd import workloads as wl
+from tests import hip_path as hp
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _announce(msg):
+    print(f"[gpu-serving] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_16731_amd import fvpatch
+    fvpatch.load()
+
+
+def oracle_replay(mesh: wl.Batch, batches, periodic=True):
+    """Apply (first, count, dt) batches in order with the oracle."""
+    state = mesh.data.copy()
+    for first, count, dt in batches:
+        idx = np.arange(first, first + count)
+        sizes = mesh.sizes[idx]
+        offs = mesh.offsets[idx]
+        out, _ = oracle.batch_update(state, sizes, offs, mesh.dim, mesh.nq, dt, wl.H_DEFAULT, wl.GAMMA, periodic,
+                                     out=state.copy(), want_lambda=False)
+        for t in idx:
+            n = (int(mesh.sizes[t]) + 2) ** mesh.dim * mesh.nq
+            state[mesh.offsets[t]:mesh.offsets[t] + n] = out[mesh.offsets[t]:mesh.offsets[t] + n]
+    return state
+
+
+def batch_sequence(M, n, seed, max_count=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    seq = []
+    for _ in range(n):
+        first = int(rng.integers(0, M))
+        count = int(rng.integers(1, (max_count or M) + 1))
+        count = min(count, M - first)
+        seq.append((first, count, float(rng.uniform(0.5e-3, 1.5e-3))))
+    return seq
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fused", "plain"])
+def test_server_batches_match_oracle_2d(mode):
+    from paper_2306_16731_amd import fvpatch as fv
+    _announce(f"server 2D mixed, mode={mode}")
+    mesh = wl.make_mixed(300, (1, 3, 5, 9, 16, 17, 40, 63), dim=2, nq=5, seed=51)
+    seq = batch_sequence(300, 40, 52)
+    srv = fv.fv_server_create(1 << 30, 2, 5, wl.H_DEFAULT, wl.GAMMA, fv.FV_HALO_PERIODIC, mode, 4)
+    try:
+        mid = fv.fv_server_add_mesh(srv, mesh.sizes, mesh.data)
+        for first, count, dt in seq:
+            fv.fv_server_submit(srv, mid, first, count, dt)
+            fv.fv_server_poll(srv)
+        st = fv.fv_server_drain(srv)
+        assert st["completed"] == len(seq) and st["queued"] == 0 and st["inflight"] == 0
+        got = fv.fv_server_read_mesh(srv, mid, np.empty_like(mesh.data))
+    finally:
+        fv.fv_server_destroy(srv)
+    want = oracle_replay(mesh, seq)
+    assert np.all(hp.component_errors(got, want, 5) <= TOL)
+
+
+def test_server_batches_match_oracle_3d():
+    from paper_2306_16731_amd import fvpatch as fv
+    _announce("server 3D")
+    mesh = wl.make_mixed(60, (2, 5, 8), dim=3, nq=5, seed=53)
+    seq = batch_sequence(60, 15, 54)
+    srv = fv.fv_server_create(1 << 30, 3, 5, wl.H_DEFAULT, wl.GAMMA, fv.FV_HALO_PERIODIC, 0, 3)
+    try:
+        mid = fv.fv_server_add_mesh(srv, mesh.sizes, mesh.data)
+        for first, count, dt in seq:
+            fv.fv_server_submit(srv, mid, first, count, dt)
+        fv.fv_server_drain(srv)
+        got = fv.fv_server_read_mesh(srv, mid, np.empty_like(mesh.data))
+    finally:
+        fv.fv_server_destroy(srv)
+    assert np.all(hp.component_errors(got, oracle_replay(mesh, seq), 5) <= TOL)
+
+
+def test_budget_admission():
+    """A mesh that does not fit is refused; a tight budget queues batches (none dropped); a batch that can
+    never fit is reported."""
+    from paper_2306_16731_amd import fvpatch as fv
+    _announce("server budget admission")
+    mesh = wl.make_mixed(200, (3, 5, 9), dim=2, nq=5, seed=55)
+    resident = 2 * (mesh.data.size + (mesh.data.size & 1)) * 8
+    st, h = fv.fv_server_create(resident - 8, 2, 5, wl.H_DEFAULT, raise_on_error=False, flags=fv.FV_HALO_PERIODIC)
+    assert st == fv.FV_OK
+    try:
+        st, mid = fv.fv_server_add_mesh(h, mesh.sizes, mesh.data, raise_on_error=False)
+        assert st == fv.FV_ERR_BUDGET
+    finally:
+        fv.fv_server_destroy(h)
+    # room for the mesh and about one batch of 100 patches in flight
+    srv = fv.fv_server_create(resident + 100 * 44 + 8, 2, 5, wl.H_DEFAULT, wl.GAMMA, fv.FV_HALO_PERIODIC, 0, 8)
+    try:
+        mid = fv.fv_server_add_mesh(srv, mesh.sizes, mesh.data)
+        seq = [(0, 100, 1e-3), (100, 100, 1e-3), (50, 100, 1e-3), (0, 80, 1e-3), (120, 60, 1e-3)]
+        for first, count, dt in seq:
+            fv.fv_server_submit(srv, mid, first, count, dt)
+        st = fv.fv_server_poll(srv)
+        assert st["inflight"] <= 1 and st["queued"] >= 3
+        st = fv.fv_server_drain(srv)
+        assert st["completed"] == len(seq) and st["peak_queued"] >= 4
+        got = fv.fv_server_read_mesh(srv, mid, np.empty_like(mesh.data))
+        assert np.all(hp.component_errors(got, oracle_replay(mesh, seq), 5) <= TOL)
+        fv.fv_server_submit(srv, mid, 0, 200, 1e-3)  # 200 patches never fit
+        st, _ = fv.fv_server_drain(srv, raise_on_error=False)
+        assert st == fv.FV_ERR_BUDGET
+    finally:
+        fv.fv_server_destroy(srv)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fused", "plain"])
+def test_run_trace_matches_oracle(mode):
+    """A Poisson trace replayed by the C++ loop: every batch completes, latencies are recorded, and the final
+    state equals the oracle applying the trace's batches in arrival order."""
+    from paper_2306_16731_amd import fvpatch as fv
+    from paper_2306_16731_amd import serving
+    _announce(f"run_trace mode={mode}")
+    mesh = wl.make_mixed(400, (3, 5, 9, 17), dim=2, nq=5, seed=56)
+    trace = serving.make_trace(400.0, 0.25, [400], weights=(1,), max_batch=128, dt=(7e-4,), seed=57)
+    st, got = serving.run(mode, mesh, trace, budget=1 << 30, max_inflight=4, read_back=True)
+    assert st["completed"] == len(trace) == st["submitted"]
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    seq = [(int(r["first"]), int(r["count"]), float(r["dt"])) for r in trace]
+    assert np.all(hp.component_errors(got, oracle_replay(mesh, seq), 5) <= TOL)
