@@ -122,19 +122,26 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
  *
  *   kernel    FV_KERNEL_AUTO, FV_KERNEL_BLOCK (plane-marching kernel, any
  *             size), FV_KERNEL_WAVE (2D only: one padded patch row per
- *             wavefront, p + 2 <= 64) or FV_KERNEL_TILE (2D only: whole
+ *             wavefront, p + 2 <= 64), FV_KERNEL_TILE (2D only: whole
  *             patches per block, one thread per interior volume, p*p <= 1024)
+ *             or FV_KERNEL_FIXED (the wave kernel compiled for one patch
+ *             size: 2D, unknowns = 5, p in {3, 5, 9, 16, 17}; the default
+ *             for those classes)
  *   block     threads per block, a multiple of 64 (0 = default); the wave
- *             kernel takes at most 256, the tile kernel at least p*p
+ *             kernel takes at most 256, the tile kernel at least p*p, the
+ *             fixed-size kernel exactly 256
  *   prefetch  rows each lane keeps in flight in the wave kernel, 1..4
- *             (0 = default)
+ *             (0 = default); set by the build for the fixed-size kernel
+ *             (0 or that value)
  *   rows      output rows the wave kernel stages in LDS per patch before
- *             writing them in one burst, 1..16 (0 = default)
+ *             writing them in one burst, 1..16 (0 = default); set by the
+ *             build for the fixed-size kernel (0 or that value)
  */
 #define FV_KERNEL_AUTO 0
 #define FV_KERNEL_BLOCK 1
 #define FV_KERNEL_WAVE 2
 #define FV_KERNEL_TILE 3
+#define FV_KERNEL_FIXED 4
 
 typedef struct fv_tuning {
     int32_t kernel;

@@ -1,8 +1,9 @@
 """Autotuner for the patch-update launches (batching form).
 
 For every patch class (dim, unknowns, p) it times candidate launch parameters
--- kernel (2D wave / 2D tile / plane-marching block kernel), threads per
-block, rows of load prefetch, output rows staged per burst -- on a synthetic
+-- kernel (2D wave kernel built for the size / 2D wave / 2D tile /
+plane-marching block kernel), threads per block, rows of load prefetch,
+output rows staged per burst -- on a synthetic
 batch of that class, ping-ponging steps through the C ABI after a warmup,
 and installs the fastest with fv_set_tuning.  Plans built afterwards pick the
 installed parameters up per size class.  For a whole batch it also picks the
@@ -36,6 +37,8 @@ def class_key(dim: int, nq: int, p: int) -> str:
 def candidates(dim: int, nq: int, p: int) -> list[dict]:
     """Launch parameters worth timing for a class (the library rejects ones that do not fit)."""
     out = []
+    if dim == 2 and nq == 5 and p in fv.FIXED_SIZES_2D:
+        out.append(dict(kernel=fv.FV_KERNEL_FIXED, block=256, prefetch=0, rows=0))
     if dim == 2 and p + 2 <= 64:
         for pf in (2, 3, 4):
             for rows in (4, 6, 8):

@@ -7,10 +7,12 @@ gfx950 only, with packed-FP32 instruction selection disabled.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -26,7 +28,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-variable",
     "-Wno-unused-function",
@@ -41,18 +42,29 @@ def hipcc() -> str:
     return path
 
 
-def build(verbose: bool = False, extra_flags: list[str] | None = None, output: str = LIBRARY) -> str:
-    """Compile every source into the shared library (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc(), *HIPCC_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-I", CSRC, "-o", output + ".tmp", *srcs]
+def _run(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with status {res.returncode}")
+        raise RuntimeError(f"hipcc failed with status {res.returncode}: {' '.join(cmd[-3:])}")
     if verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
+
+
+def build(verbose: bool = False, extra_flags: list[str] | None = None, output: str = LIBRARY) -> str:
+    """Compile every source (in parallel, one object each) and link the shared
+    library (always recompiles)."""
+    flags = [*HIPCC_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="fvpatch_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        jobs = [[hipcc(), *flags, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
+            for f in [pool.submit(_run, j, verbose) for j in jobs]:
+                f.result()
+        _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", output + ".tmp", *objs], verbose)
     os.replace(output + ".tmp", output)
     return output
 

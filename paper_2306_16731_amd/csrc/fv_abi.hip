@@ -220,18 +220,19 @@ static fv_tuning *tune_slot(int dim, int nq, int p) {
 }
 
 static int default_block_for(int kernel, int p, int dim) {
-    if (kernel == FV_KERNEL_WAVE) return 256;
+    if (kernel == FV_KERNEL_WAVE || kernel == FV_KERNEL_FIXED) return 256;
     if (kernel == FV_KERNEL_TILE) return tile2d_default_block(p);
     return default_block(p, dim);
 }
 
 fv_tuning default_tuning(int dim, int nq, int p) {
-    (void)nq;
     fv_tuning t{FV_KERNEL_AUTO, 0, 0, 0};
     t.kernel = (dim == 2 && wave2d_fits(p)) ? FV_KERNEL_WAVE : FV_KERNEL_BLOCK;
+    if (dim == 2 && wave2d_fixed(p, nq)) t.kernel = FV_KERNEL_FIXED;
     t.block = default_block_for(t.kernel, p, dim);
     t.prefetch = t.kernel == FV_KERNEL_WAVE ? 4 : 1;
     t.rows = t.kernel == FV_KERNEL_WAVE ? 6 : 1;
+    if (t.kernel == FV_KERNEL_FIXED) wave2d_fixed_shape(p, &t.prefetch, &t.rows);
     return t;
 }
 
@@ -371,17 +372,35 @@ fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tunin
         *slot = fv_tuning{-1, 0, 0, 0};
         return FV_OK;
     }
-    if (t->kernel < FV_KERNEL_AUTO || t->kernel > FV_KERNEL_TILE) return fail(FV_ERR_INVALID_ARG, "unknown kernel %d", t->kernel);
+    if (t->kernel < FV_KERNEL_AUTO || t->kernel > FV_KERNEL_FIXED) return fail(FV_ERR_INVALID_ARG, "unknown kernel %d", t->kernel);
     if (t->block < 0 || t->block > 1024 || t->block % 64 != 0) return fail(FV_ERR_INVALID_ARG, "block must be a multiple of 64 in [0, 1024]");
     if (t->prefetch < 0 || t->prefetch > 4) return fail(FV_ERR_INVALID_ARG, "prefetch must be in [0, 4]");
     if (t->rows < 0 || t->rows > 16) return fail(FV_ERR_INVALID_ARG, "rows must be in [0, 16]");
     fv_tuning v = *t;
     const fv_tuning d = default_tuning(dim, unknowns, p);
-    if (v.kernel == FV_KERNEL_AUTO) v.kernel = d.kernel;
+    if (v.kernel == FV_KERNEL_AUTO) {
+        v.kernel = d.kernel;
+        // explicit prefetch / rows other than the fixed-size build's: the runtime-size wave kernel
+        if (v.kernel == FV_KERNEL_FIXED && ((v.prefetch != 0 && v.prefetch != d.prefetch) ||
+                                            (v.rows != 0 && v.rows != d.rows)))
+            v.kernel = FV_KERNEL_WAVE;
+    }
     if (v.kernel == FV_KERNEL_WAVE && !(dim == 2 && wave2d_fits(p)))
         return fail(FV_ERR_UNSUPPORTED, "the wave kernel needs 2D and p + 2 <= 64");
     if (v.kernel == FV_KERNEL_TILE && !(dim == 2 && tile2d_fits(p)))
         return fail(FV_ERR_UNSUPPORTED, "the tile kernel needs 2D and p*p <= 1024");
+    if (v.kernel == FV_KERNEL_FIXED) {
+        if (!(dim == 2 && wave2d_fixed(p, unknowns)))
+            return fail(FV_ERR_UNSUPPORTED, "no fixed-size kernel for dim=%d unknowns=%d p=%d", dim, unknowns, p);
+        int pf = 0, rows = 0;
+        wave2d_fixed_shape(p, &pf, &rows);
+        if (v.block != 0 && v.block != 256) return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel takes 256 threads");
+        if ((v.prefetch != 0 && v.prefetch != pf) || (v.rows != 0 && v.rows != rows))
+            return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel for p=%d is built with prefetch %d and rows %d", p,
+                        pf, rows);
+        *slot = fv_tuning{FV_KERNEL_FIXED, 256, pf, rows};
+        return FV_OK;
+    }
     if (v.block == 0) v.block = v.kernel == d.kernel ? d.block : default_block_for(v.kernel, p, dim);
     if (v.kernel == FV_KERNEL_WAVE && v.block > 256) return fail(FV_ERR_INVALID_ARG, "the wave kernel takes at most 256 threads");
     if (v.kernel == FV_KERNEL_TILE) {

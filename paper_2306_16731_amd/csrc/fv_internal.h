@@ -33,7 +33,8 @@ struct UpdateLaunch {
 
 // One wave's work in a task-list launch: `count` (<= 64 / (p + 2)) patches of
 // size p, at entries first .. first + count - 1 of the offsets / ids lists;
-// `rows` output rows are staged per flush.
+// `rows` output rows are staged per flush, or rows == 0 for the fixed-size
+// form (its own rows).
 struct WaveTask {
     int32_t p;
     int32_t rows;
@@ -81,6 +82,12 @@ size_t wave2d_lds_bytes(int p, int nq, int block, int rows);
 int wave2d_ring_words(int p, int nq, int rows);
 hipError_t launch_update2d(const UpdateLaunch &L, hipStream_t stream);
 hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream);
+// Fixed-size form of the same kernel (compile-time patch size; N = 5 and
+// p in {3, 5, 9, 16, 17}).
+bool wave2d_fixed(int p, int nq);
+int wave2d_fixed_ring_words(int p);
+void wave2d_fixed_shape(int p, int *prefetch, int *rows);
+hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream);
 
 // 2D kernel with whole patches per block, one thread per interior volume (p*p <= 1024).
 inline bool tile2d_fits(int p) { return p * p <= 1024; }

@@ -193,15 +193,18 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
         if (!count[p]) continue;
         if (dim == 2 && wave2d_fits(p)) {
             const fv_tuning tu = tuning_for(dim, unknowns, p);
-            const int rows = tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6;
+            // rows == 0: the fixed-size form of the kernel
+            const bool fixed = tu.kernel == FV_KERNEL_FIXED;
+            const int rows = fixed ? 0 : (tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6);
             const int ppw = 64 / (p + 2);
             for (int32_t f = 0; f < count[p]; f += ppw)
                 tasks.push_back(WaveTask{p, rows, start[p] + f, std::min<int32_t>(ppw, count[p] - f)});
-            pl->ring_words = std::max(pl->ring_words, wave2d_ring_words(p, unknowns, rows));
+            pl->ring_words = std::max(pl->ring_words,
+                                      fixed ? wave2d_fixed_ring_words(p) : wave2d_ring_words(p, unknowns, rows));
             const int64_t cells = (int64_t)count[p] * p * p;
             if (cells > best_cells) {
                 best_cells = (int32_t)std::min<int64_t>(cells, INT32_MAX);
-                pl->prefetch = tu.kernel == FV_KERNEL_WAVE ? tu.prefetch : 0;
+                pl->prefetch = (tu.kernel == FV_KERNEL_WAVE || tu.kernel == FV_KERNEL_FIXED) ? tu.prefetch : 0;
             }
             if (((p + 2) * unknowns) % 2) pl->even_offsets = false;
             for (int32_t k = start[p]; k < start[p] + count[p]; ++k)

@@ -161,14 +161,16 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
         if (!count[p]) continue;
         if (dim == 2 && wave2d_fits(p)) {
             const fv_tuning tu = tuning_for(dim, nq, p);
-            const int rows = tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6;
+            // rows == 0: the fixed-size form of the kernel
+            const bool fixed = tu.kernel == FV_KERNEL_FIXED;
+            const int rows = fixed ? 0 : (tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6);
             const int ppw = 64 / (p + 2);
             for (int32_t f = 0; f < count[p]; f += ppw)
                 htask[ntask++] = WaveTask{p, rows, start[p] + f, std::min<int32_t>(ppw, count[p] - f)};
-            ring_words = std::max(ring_words, wave2d_ring_words(p, nq, rows));
+            ring_words = std::max(ring_words, fixed ? wave2d_fixed_ring_words(p) : wave2d_ring_words(p, nq, rows));
             if ((int64_t)count[p] * p * p > best_cells) {
                 best_cells = (int64_t)count[p] * p * p;
-                prefetch = tu.kernel == FV_KERNEL_WAVE ? tu.prefetch : 0;
+                prefetch = (tu.kernel == FV_KERNEL_WAVE || tu.kernel == FV_KERNEL_FIXED) ? tu.prefetch : 0;
             }
             if (((p + 2) * nq) % 2) even = false;
         } else {

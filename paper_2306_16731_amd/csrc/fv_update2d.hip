@@ -39,12 +39,13 @@ constexpr int kDefaultPrefetch2d = 4;
 constexpr int kDefaultRows2d = 6;
 
 // Cross-lane moves of a double through the DPP wave shifts.  They are issued
-// in uniform control flow, so every source lane is enabled.
+// in uniform control flow, so every source lane is enabled; the lane at the
+// wave's edge (no source) reads zero, and no lane that receives it uses it.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
     const int2 v = __builtin_bit_cast(int2, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, v.x, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, v.y, CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(v.x, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(v.y, CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, make_int2(lo, hi));
 }
 __device__ __forceinline__ double from_left(double x) { return dpp_move<0x138>(x); }   // wave_shr:1
@@ -124,7 +125,8 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
                                             double *ring) {
     const int W = P + 2;
     const int ppw = 64 / W;
-    const int lane = threadIdx.x & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // lane-derived values stay inside the task (task-list kernel)
     const int slot = lane / W;
     const int i = lane - slot * W;
     const int64_t item = item0 + slot;
@@ -251,6 +253,240 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
 }
 
 
+// ---------------------------------------------------------------------------
+// Fixed-size form.  The same step with the patch size a template parameter:
+// the row loop unrolls completely and every loop has a static trip count.
+// All global loads and stores are issued unconditionally -- lanes without a
+// patch read the wave's first patch, rows past the patch re-read its last
+// row, spare lanes of an output burst repeat a chunk another lane writes with
+// the same value -- so the compiler can count the wave's outstanding memory
+// operations exactly.  The PF rows in flight then stay in flight across the
+// output bursts; in the runtime-size form the counts are unknown after any
+// branch or loop with memory operations, and every row waits for all of them.
+// Sizes: those of the benchmark batches (16) and the mixed-size batches
+// (3, 5, 9, 17), Euler with five unknowns.
+
+template <int P>
+struct FixedShape {
+    static constexpr int PF = 2;                    // rows in flight per lane
+    static constexpr int R = P <= 9 ? P : 8;        // output rows per burst
+};
+
+inline bool fixed_size(int p) { return p == 3 || p == 5 || p == 9 || p == 16 || p == 17; }
+
+template <int P>
+constexpr int fixed_ring_words() {
+    return (64 / (P + 2)) * FixedShape<P>::R * (P + 2) * 5 + 64 / (P + 2);
+}
+
+template <int NQ, int P, int VEC, bool PERIODIC>
+__device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in, double *__restrict__ out,
+                                                  const int64_t *__restrict__ offsets,
+                                                  const int64_t *__restrict__ out_offsets,
+                                                  const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
+                                                  int64_t stride, double r, double gamma,
+                                                  double *__restrict__ lambda_out, double *ring) {
+    constexpr int W = P + 2;
+    constexpr int ppw = 64 / W;
+    constexpr int ROWD = W * NQ;
+    constexpr int PF = FixedShape<P>::PF;
+    constexpr int R = FixedShape<P>::R;
+    static_assert(VEC == 1 || ROWD % 2 == 0, "16-byte bursts need whole 16-byte rows");
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // lane-derived values stay inside the task (see the bursts below)
+    const int slot = lane / W;
+    const int i = lane - slot * W;
+    const int64_t item = item0 + slot;
+    const bool active = slot < ppw && item < num_items;
+    const bool xin = i >= 1 && i <= P;
+    const bool writer = active && xin;
+    const int64_t self = active ? item : item0;
+    const int64_t off = offsets ? offsets[self] : self * stride;
+    const int64_t off_out = out_offsets ? out_offsets[self] : off;
+    const double *src = in + off + (int64_t)i * NQ;
+
+    int64_t *bases = reinterpret_cast<int64_t *>(ring + ppw * R * ROWD);
+    wave_lds_fence();  // a previous patch group of this wave may still be reading the ring
+    if (i == 0 && slot < ppw) bases[slot] = off_out;
+    wave_lds_fence();
+
+    double qprev[NQ], fyprev[NQ], fhprev[NQ], dxprev[NQ];
+    double lyprev = 0.0, lmax = 0.0;
+    rest_state<NQ>(qprev);
+    rest_state<NQ>(fyprev);
+    rest_state<NQ>(fhprev);
+    rest_state<NQ>(dxprev);
+
+    double qbuf[PF][NQ];
+#pragma unroll
+    for (int m = 0; m < PF; ++m) load_volume<NQ>(src + (int64_t)(m < W ? m : W - 1) * ROWD, qbuf[m]);
+
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double q[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q[c] = qbuf[k % PF][c];
+        load_volume<NQ>(src + (int64_t)(k + PF < W ? k + PF : W - 1) * ROWD, qbuf[k % PF]);
+
+        const Prim a = primitives<NQ>(q, gamma);
+        double fx[NQ], lx, fy[NQ], ly;
+        euler_flux<NQ>(q, a, 0, fx, lx);
+        euler_flux<NQ>(q, a, 1, fy, ly);
+        double qL[NQ], fL[NQ], fhx[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            qL[c] = from_left(q[c]);
+            fL[c] = from_left(fx[c]);
+        }
+        const double lL = from_left(lx);
+        rusanov<NQ>(qL, fL, lL, q, fx, lx, fhx);
+        double dx[NQ], fh[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) dx[c] = fhx[c] - from_right(fhx[c]);
+        rusanov<NQ>(qprev, fyprev, lyprev, q, fy, ly, fh);
+
+        if (k >= 2) {
+            const int kk = k - 1;          // output row completed at this layer
+            const int rr = (kk - 1) % R;   // its row in the ring
+            if (writer) {
+                double d[NQ], qn[NQ];
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) d[c] = dxprev[c] + (fhprev[c] - fh[c]);
+                advance<NQ>(qprev, d, r, qn);
+                double *srow = ring + (slot * R + rr) * ROWD;
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) srow[i * NQ + c] = qn[c];
+                if (PERIODIC) {
+                    if (i == P)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) srow[c] = qn[c];
+                    if (i == 1)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) srow[(P + 1) * NQ + c] = qn[c];
+                }
+                if (lambda_out) lmax = nanmax(lmax, volume_lambda<2, NQ>(qn, gamma));
+            }
+            if (rr == R - 1 || kk == P) {
+                const int nrows = rr + 1;
+                const int k0 = kk - rr;    // first output row in the ring
+                // The burst's per-lane indices are formed here from a lane id
+                // the optimiser cannot see through: otherwise it computes the
+                // indices of every burst up front and keeps them in registers
+                // across all layers (and, in the task-list kernel, across all
+                // tasks).
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+                wave_lds_fence();
+                if (PERIODIC) {
+                    // whole rows (x-halo volumes hold their wrapped copies)
+                    const int per = nrows * ROWD / VEC;
+                    const int total = ppw * per;
+#pragma unroll
+                    for (int j = 0; j < (total + 63) / 64; ++j) {
+                        const int c = ln + 64 * j < total ? ln + 64 * j : total - 1;
+                        int sl = c / per;
+                        const int rem = c - sl * per;
+                        sl = item0 + sl < num_items ? sl : 0;
+                        const int64_t base = bases[sl] + (int64_t)k0 * ROWD;
+                        if constexpr (VEC == 2)
+                            reinterpret_cast<dv2 *>(out + base)[rem] =
+                                reinterpret_cast<const dv2 *>(ring + sl * R * ROWD)[rem];
+                        else
+                            out[base + rem] = ring[sl * R * ROWD + rem];
+                    }
+                    // y-halo rows: row P+1 takes row 1, row 0 takes row P (interior columns)
+                    if (k0 == 1 || kk == P) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (h == 0 ? k0 != 1 : kk != P) continue;
+                            const int from = h == 0 ? 0 : rr;
+                            const int dest = h == 0 ? P + 1 : 0;
+                            constexpr int iper = P * NQ;
+                            constexpr int itotal = ppw * iper;
+#pragma unroll
+                            for (int j = 0; j < (itotal + 63) / 64; ++j) {
+                                const int c = ln + 64 * j < itotal ? ln + 64 * j : itotal - 1;
+                                int sl = c / iper;
+                                const int d = c - sl * iper;
+                                sl = item0 + sl < num_items ? sl : 0;
+                                out[bases[sl] + (int64_t)dest * ROWD + NQ + d] = ring[(sl * R + from) * ROWD + NQ + d];
+                            }
+                        }
+                    }
+                } else {
+                    // interior volumes of each row
+                    constexpr int inner = P * NQ;
+                    const int per = nrows * inner;
+                    const int total = ppw * per;
+#pragma unroll
+                    for (int j = 0; j < (total + 63) / 64; ++j) {
+                        const int c = ln + 64 * j < total ? ln + 64 * j : total - 1;
+                        int sl = c / per;
+                        const int rem = c - sl * per;
+                        const int rw = rem / inner, d = rem - rw * inner;
+                        sl = item0 + sl < num_items ? sl : 0;
+                        out[bases[sl] + (int64_t)(k0 + rw) * ROWD + NQ + d] = ring[(sl * R + rw) * ROWD + NQ + d];
+                    }
+                }
+                wave_lds_fence();
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            qprev[c] = q[c];
+            fyprev[c] = fy[c];
+            fhprev[c] = fh[c];
+            dxprev[c] = dx[c];
+        }
+        lyprev = ly;
+        // keep the layers apart: interleaving them buys no latency (the loads
+        // already run PF layers ahead) and costs registers, hence occupancy
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    if (lambda_out) {
+        for (int o = 1; o < W; o <<= 1) {
+            const double other = __shfl_down(lmax, o, 64);
+            if (i + o < W) lmax = nanmax(lmax, other);
+        }
+        if (active && i == 0) lambda_out[ids ? ids[item] : item] = lmax;
+    }
+}
+
+// One task of the fixed-size form.
+template <int P, int VEC, bool PERIODIC>
+__device__ __forceinline__ void fixed_task_body(const double *__restrict__ in, double *__restrict__ out,
+                                             const int64_t *__restrict__ offsets,
+                                             const int64_t *__restrict__ out_offsets,
+                                             const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
+                                             double *__restrict__ lambda_out, double *ring) {
+    wave_update_fixed<5, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, 0, count, 0, r, gamma, lambda_out,
+                                           ring);
+}
+
+// Task-list body for a fixed size: false when p has no fixed-size build.
+template <int NQ, int VEC, bool PERIODIC>
+__device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in, double *__restrict__ out,
+                                           const int64_t *__restrict__ offsets,
+                                           const int64_t *__restrict__ out_offsets,
+                                           const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
+                                           double *__restrict__ lambda_out, double *ring) {
+    if constexpr (NQ != 5) {
+        return false;
+    } else {
+        switch (p) {
+            case 3: fixed_task_body<3, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 5: fixed_task_body<5, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 9: fixed_task_body<9, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 16: fixed_task_body<16, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 17: fixed_task_body<17, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+        }
+        return false;
+    }
+}
+
+
 // Uniform launch: every wave takes the next ppw patches of one size.
 template <int NQ, int PF, int VEC>
 __global__ void __launch_bounds__(256)
@@ -269,16 +505,34 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
                              lds + (size_t)wave * (ppw * R * (P + 2) * NQ + ppw));
 }
 
+// Uniform launch of the fixed-size form.
+template <int P, int VEC, bool PERIODIC>
+__global__ void __launch_bounds__(256)
+update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
+                      const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
+                      int64_t stride, double r, const double *__restrict__ r_dev, double gamma,
+                      double *__restrict__ lambda_out) {
+    extern __shared__ double lds[];
+    constexpr int ppw = 64 / (P + 2);
+    const int wave = threadIdx.x >> 6;
+    const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
+    if (item0 >= num_items) return;
+    const double rr = r_dev ? *r_dev : r;
+    wave_update_fixed<5, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
+                                           lambda_out, lds + (size_t)wave * fixed_ring_words<P>());
+}
+
 // Task-list launch over mixed patch sizes: task t holds `count` patches of
-// size `p` at offsets[first ..] (ids[first ..]).  Each wave takes tasks
-// gw, gw + nw, ... (nw = waves in the grid), so a grid smaller than the task
-// list is persistent; tasks sorted largest first balance the tail.
-template <int NQ, int PF, int VEC>
+// size `p` at offsets[first ..] (ids[first ..]); rows == 0 selects the
+// fixed-size form.  Each wave takes tasks gw, gw + nw, ... (nw = waves in
+// the grid), so a grid smaller than the task list is persistent; tasks sorted
+// largest first balance the tail.
+template <int NQ, int PF, int VEC, bool PERIODIC>
 __global__ void __launch_bounds__(256)
 update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids,
                       const WaveTask *__restrict__ tasks, int32_t num_tasks,
-                      double r, const double *__restrict__ r_dev, double gamma, uint32_t flags,
+                      double r, const double *__restrict__ r_dev, double gamma,
                       double *__restrict__ lambda_out, int32_t ring_words) {
     extern __shared__ double lds[];
     const int wave = threadIdx.x >> 6;
@@ -289,8 +543,13 @@ update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, c
     double *ring = lds + (size_t)wave * ring_words;
     for (int64_t t = gw; t < num_tasks; t += nw) {
         const WaveTask tk = tasks[t];
-        wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, out_offsets ? out_offsets + tk.first : nullptr,
-                                 ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma, flags, lambda_out, tk.rows, ring);
+        const int64_t *to = out_offsets ? out_offsets + tk.first : nullptr;
+        if (tk.rows == 0 && fixed_task<NQ, VEC, PERIODIC>(tk.p, in, out, offsets + tk.first, to, ids + tk.first,
+                                                          tk.count, rr, gamma, lambda_out, ring))
+            continue;
+        wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, to, ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma,
+                                 PERIODIC ? kPeriodic : 0u, lambda_out, tk.rows > 0 ? tk.rows : kDefaultRows2d,
+                                 ring);
     }
 }
 
@@ -326,7 +585,7 @@ hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <int NQ, int PF, int VEC>
+template <int NQ, int PF, int VEC, bool PERIODIC>
 hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
     const int B = 256;
     const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)T.ring_words;
@@ -336,7 +595,7 @@ hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return hipErrorInvalidDevice;
     if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
-    const void *fn = reinterpret_cast<const void *>(&update2d_tasks_kernel<NQ, PF, VEC>);
+    const void *fn = reinterpret_cast<const void *>(&update2d_tasks_kernel<NQ, PF, VEC, PERIODIC>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -348,10 +607,9 @@ hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
         blocks = std::min<int64_t>(blocks, (int64_t)per_cu * cus);
     }
     if (blocks < 1) return hipSuccess;
-    hipLaunchKernelGGL((update2d_tasks_kernel<NQ, PF, VEC>), dim3((unsigned)blocks), dim3(B), lds, stream, T.in, T.out,
-                       T.offsets, T.out_offsets, T.ids, T.tasks, T.num_tasks, T.r, T.r_dev, T.gamma, T.flags,
-                       T.lambda_out,
-                       T.ring_words);
+    hipLaunchKernelGGL((update2d_tasks_kernel<NQ, PF, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(B), lds, stream,
+                       T.in, T.out, T.offsets, T.out_offsets, T.ids, T.tasks, T.num_tasks, T.r, T.r_dev, T.gamma,
+                       T.lambda_out, T.ring_words);
     return hipGetLastError();
 }
 
@@ -377,21 +635,93 @@ int wave2d_ring_words(int p, int nq, int rows) {
     return ppw * rows * W * nq + ppw;
 }
 
-template <int NQ, int VEC>
+template <int NQ, int VEC, bool PERIODIC>
 static hipError_t tasks_pf(const TaskLaunch &T, hipStream_t stream) {
     switch (T.prefetch > 0 ? T.prefetch : kDefaultPrefetch2d) {
-        case 1: return launch2d_tasks<NQ, 1, VEC>(T, stream);
-        case 2: return launch2d_tasks<NQ, 2, VEC>(T, stream);
-        case 3: return launch2d_tasks<NQ, 3, VEC>(T, stream);
-        case 4: return launch2d_tasks<NQ, 4, VEC>(T, stream);
+        case 1: return launch2d_tasks<NQ, 1, VEC, PERIODIC>(T, stream);
+        case 2: return launch2d_tasks<NQ, 2, VEC, PERIODIC>(T, stream);
+        case 3: return launch2d_tasks<NQ, 3, VEC, PERIODIC>(T, stream);
+        case 4: return launch2d_tasks<NQ, 4, VEC, PERIODIC>(T, stream);
     }
     return hipErrorInvalidValue;
 }
 
+template <int NQ, int VEC>
+static hipError_t tasks_periodic(const TaskLaunch &T, hipStream_t stream) {
+    return (T.flags & kPeriodic) ? tasks_pf<NQ, VEC, true>(T, stream) : tasks_pf<NQ, VEC, false>(T, stream);
+}
+
 hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream) {
     if (T.num_tasks <= 0) return hipSuccess;
-    if (T.nq == 5) return T.vec2 ? tasks_pf<5, 2>(T, stream) : tasks_pf<5, 1>(T, stream);
-    if (T.nq == 4) return T.vec2 ? tasks_pf<4, 2>(T, stream) : tasks_pf<4, 1>(T, stream);
+    if (T.nq == 5) return T.vec2 ? tasks_periodic<5, 2>(T, stream) : tasks_periodic<5, 1>(T, stream);
+    if (T.nq == 4) return T.vec2 ? tasks_periodic<4, 2>(T, stream) : tasks_periodic<4, 1>(T, stream);
+    return hipErrorInvalidValue;
+}
+
+// Uniform launch of the fixed-size form over patches of one size.
+template <int P, int VEC, bool PERIODIC>
+static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
+    constexpr int ppw = 64 / (P + 2);
+    const int B = 256;
+    const int per_block = (B / 64) * ppw;
+    const int64_t blocks = ((int64_t)L.num_items + per_block - 1) / per_block;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)fixed_ring_words<P>();
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return hipErrorInvalidDevice;
+    if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
+    const void *fn = reinterpret_cast<const void *>(&update2d_fixed_kernel<P, VEC, PERIODIC>);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((update2d_fixed_kernel<P, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in,
+                       L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev, L.gamma,
+                       L.lambda_out);
+    return hipGetLastError();
+}
+
+template <int P, int VEC>
+static hipError_t fixed_periodic(const UpdateLaunch &L, hipStream_t stream) {
+    return (L.flags & kPeriodic) ? launch_fixed<P, VEC, true>(L, stream) : launch_fixed<P, VEC, false>(L, stream);
+}
+
+bool wave2d_fixed(int p, int nq) { return nq == 5 && fixed_size(p); }
+
+void wave2d_fixed_shape(int p, int *prefetch, int *rows) {
+    switch (p) {
+        case 3: *prefetch = FixedShape<3>::PF; *rows = FixedShape<3>::R; return;
+        case 5: *prefetch = FixedShape<5>::PF; *rows = FixedShape<5>::R; return;
+        case 9: *prefetch = FixedShape<9>::PF; *rows = FixedShape<9>::R; return;
+        case 16: *prefetch = FixedShape<16>::PF; *rows = FixedShape<16>::R; return;
+        case 17: *prefetch = FixedShape<17>::PF; *rows = FixedShape<17>::R; return;
+    }
+    *prefetch = 0;
+    *rows = 0;
+}
+
+int wave2d_fixed_ring_words(int p) {
+    switch (p) {
+        case 3: return fixed_ring_words<3>();
+        case 5: return fixed_ring_words<5>();
+        case 9: return fixed_ring_words<9>();
+        case 16: return fixed_ring_words<16>();
+        case 17: return fixed_ring_words<17>();
+    }
+    return 0;
+}
+
+hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream) {
+    if (L.nq != 5) return hipErrorInvalidValue;
+    switch (L.p) {
+        case 3: return fixed_periodic<3, 1>(L, stream);
+        case 5: return fixed_periodic<5, 1>(L, stream);
+        case 9: return fixed_periodic<9, 1>(L, stream);
+        case 16: return L.vec2 ? fixed_periodic<16, 2>(L, stream) : fixed_periodic<16, 1>(L, stream);
+        case 17: return fixed_periodic<17, 1>(L, stream);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -46,6 +46,8 @@ FV_KERNEL_AUTO = 0
 FV_KERNEL_BLOCK = 1
 FV_KERNEL_WAVE = 2
 FV_KERNEL_TILE = 3
+FV_KERNEL_FIXED = 4
+FIXED_SIZES_2D = (3, 5, 9, 16, 17)  # patch sizes with a fixed-size build (2D, unknowns = 5)
 
 
 class fv_tuning(ctypes.Structure):

@@ -47,6 +47,10 @@ def test_header_constants_match_binding():
     for name in ["FV_MAX_P_2D", "FV_MAX_P_3D"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name)
     assert int(re.search(r"#define FV_HALO_PERIODIC (0x[0-9a-f]+)u", hdr).group(1), 16) == F.FV_HALO_PERIODIC
+    for name in ["FV_KERNEL_AUTO", "FV_KERNEL_BLOCK", "FV_KERNEL_WAVE", "FV_KERNEL_TILE", "FV_KERNEL_FIXED"]:
+        assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name), name
+    sizes = re.search(r"p in \{([0-9, ]+)\}", hdr).group(1)
+    assert tuple(int(x) for x in sizes.split(",")) == F.FIXED_SIZES_2D
 
 
 def call(**kw):
@@ -153,3 +157,32 @@ def test_plan_validation_before_device():
     assert F.fv_plan_destroy(None) == F.FV_OK
     assert F.load().fv_plan_replay(None, None) == F.FV_ERR_INVALID_ARG
     assert F.load().fv_plan_execute(None, IN, OUT, 1e-3, 1 / 48, 1.4, None, None) == F.FV_ERR_INVALID_ARG
+
+
+def test_tuning_table_on_host():
+    """Defaults and validation of the per-class launch parameters (no device needed)."""
+    try:
+        assert F.fv_get_tuning(2, 5, 16) == dict(kernel=F.FV_KERNEL_FIXED, block=256, prefetch=2, rows=8)
+        for p in F.FIXED_SIZES_2D:
+            assert F.fv_get_tuning(2, 5, p)["kernel"] == F.FV_KERNEL_FIXED
+        assert F.fv_get_tuning(2, 4, 16)["kernel"] == F.FV_KERNEL_WAVE     # no fixed build for four unknowns
+        assert F.fv_get_tuning(2, 5, 7)["kernel"] == F.FV_KERNEL_WAVE
+        assert F.fv_get_tuning(3, 5, 8)["kernel"] == F.FV_KERNEL_BLOCK
+        bad = [
+            ((2, 4, 16, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
+            ((2, 5, 7, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
+            ((3, 5, 8, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
+            ((2, 5, 16, dict(kernel=4, block=128, prefetch=0, rows=0)), F.FV_ERR_INVALID_ARG),
+            ((2, 5, 16, dict(kernel=4, block=0, prefetch=3, rows=0)), F.FV_ERR_INVALID_ARG),
+            ((2, 5, 16, dict(kernel=4, block=0, prefetch=0, rows=5)), F.FV_ERR_INVALID_ARG),
+            ((2, 5, 16, dict(kernel=5, block=0, prefetch=0, rows=0)), F.FV_ERR_INVALID_ARG),
+        ]
+        for (dim, nq, p, t), status in bad:
+            assert F.fv_set_tuning(dim, nq, p, t, raise_on_error=False) == status, (dim, nq, p, t)
+        # the build's own values are accepted; automatic choice with other values falls back to the wave kernel
+        assert F.fv_set_tuning(2, 5, 16, dict(kernel=4, block=256, prefetch=2, rows=8), raise_on_error=False) == F.FV_OK
+        assert F.fv_set_tuning(2, 5, 16, dict(kernel=0, block=0, prefetch=4, rows=6), raise_on_error=False) == F.FV_OK
+        assert F.fv_get_tuning(2, 5, 16) == dict(kernel=F.FV_KERNEL_WAVE, block=256, prefetch=4, rows=6)
+    finally:
+        for p in F.FIXED_SIZES_2D:
+            F.fv_set_tuning(2, 5, p, None)

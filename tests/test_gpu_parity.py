@@ -232,6 +232,8 @@ VARIANTS = [
     (2, 9, dict(kernel=3, block=128)), (2, 17, dict(kernel=3, block=320)), (2, 17, dict(kernel=3, block=640)),
     (2, 32, dict(kernel=3, block=1024)), (2, 30, dict(kernel=2, block=128, prefetch=2)), (2, 17, dict(kernel=1, block=64)),
     (3, 8, dict(kernel=1, block=128)), (3, 8, dict(kernel=1, block=512)),
+    (2, 3, dict(kernel=4)), (2, 5, dict(kernel=4)), (2, 9, dict(kernel=4)), (2, 16, dict(kernel=4)),
+    (2, 17, dict(kernel=4)),
 ]
 
 
@@ -247,3 +249,44 @@ def test_kernel_variants(dim, p, tuning):
         inv.check_constant_state(hp.gpu_step, dim, 5, p=p, T=3)
     finally:
         fvpatch.fv_set_tuning(dim, 5, p, None)
+
+
+# --------------------------------------------------------------------- fixed-size build vs runtime-size kernel
+@pytest.mark.parametrize("p", [3, 5, 9, 16, 17])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_fixed_size_kernel_matches_runtime_size_kernel_bitwise(p, periodic):
+    """Both forms of the wave kernel round identically, so their results agree bit for bit: a ragged
+    last wave (spare slots), patches at gapped offsets (odd and even starts) and contiguous ones."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"fixed vs runtime size: p={p} periodic={periodic}")
+    ppw = 64 // (p + 2)
+    T = 4 * 4 * ppw + ppw // 2 + 1
+    rng = np.random.Generator(np.random.PCG64(90 + p))
+    compact = wl.make_uniform(T, p, dim=2, nq=5, seed=91 + p)
+    vol = (p + 2) ** 2 * 5
+    starts = np.cumsum(np.concatenate([[1], vol + rng.integers(0, 4, size=T - 1)])).astype(np.int64)
+    data = rng.uniform(-1, 1, int(starts[-1] + vol + 3))
+    for t in range(T):
+        data[starts[t]:starts[t] + vol] = compact.data[t * vol:(t + 1) * vol]
+    sizes = np.full(T, p, np.int32)
+    results = {}
+    try:
+        for kernel in (fvpatch.FV_KERNEL_FIXED, fvpatch.FV_KERNEL_WAVE):
+            fvpatch.fv_set_tuning(2, 5, p, dict(kernel=kernel, block=256, prefetch=0, rows=0))
+            results[kernel] = (hp.gpu_step(data, sizes, starts, 2, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic),
+                               hp.gpu_step(compact.data, sizes, None, 2, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic,
+                                           pass_offsets=False))
+    finally:
+        fvpatch.fv_set_tuning(2, 5, p, None)
+    (fo, fc), (wo, wc) = results[fvpatch.FV_KERNEL_FIXED], results[fvpatch.FV_KERNEL_WAVE]
+    for f, w in ((fo, wo), (fc, wc)):
+        assert np.array_equal(f[0], w[0]) and np.array_equal(f[1], w[1])
+    mask = np.ones(len(data), bool)
+    for t in range(T):
+        mask[starts[t]:starts[t] + vol] = False
+    assert np.array_equal(fo[0][mask], data[mask]), "bytes outside the patches were written"
+    want, want_lam = oracle.batch_update(compact.data, sizes, compact.offsets, 2, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA,
+                                         periodic)
+    assert np.all(hp.component_errors(fc[0], want, 5) <= TOL)
+    assert hp.lambda_error(fc[1], want_lam) <= TOL

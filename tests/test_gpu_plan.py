@@ -84,6 +84,25 @@ def test_plan_mixed_sizes(persistent):
     check_against_oracle(b, dts, False, got, lams)
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+def test_plan_mixed_sizes_runtime_size_bodies(periodic):
+    """The task list with every class on the runtime-size wave kernel (the fixed-size build switched
+    off), so both task bodies stay covered."""
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"plan: mixed sizes, runtime-size bodies, periodic={periodic}")
+    b, _ = wl.build_workload("c3_2d_mixed_T200000", seed=24, num_patches=1500)
+    try:
+        for p in (3, 5, 9, 17):
+            fvpatch.fv_set_tuning(2, 5, p, dict(kernel=fvpatch.FV_KERNEL_WAVE, block=256, prefetch=3, rows=4))
+        dts = oracle_dts(b, 3, periodic, 1.5e-3)
+        got, lams, info = run_plan(b, dts, periodic)
+        assert info["prefetch"] == 3
+    finally:
+        for p in (3, 5, 9, 17):
+            fvpatch.fv_set_tuning(2, 5, p, None)
+    check_against_oracle(b, dts, periodic, got, lams)
+
+
 def test_plan_mixed_with_large_class_odd_offsets_periodic():
     """Sizes the wave kernel cannot take (p = 63, 64) run as class launches in the same step;
     patches start at odd doubles (8- not 16-byte aligned), with gaps."""
