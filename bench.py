@@ -44,6 +44,11 @@ def alg_bytes_per_patch(p: int, dim: int, nq: int, periodic: bool, with_lambda: 
     return read + write + (8 if with_lambda else 0)
 
 
+KERNEL_LABELS = {1: "update_kernel (plane-marching block kernel)", 2: "update2d_kernel (2D wave kernel, runtime size)",
+                 3: "update2d_tile_kernel (2D tile kernel)",
+                 4: "update2d_fixed_kernel (2D wave kernel built for the patch size)"}
+
+
 def kernel_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -161,7 +166,8 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
-                "kernel": "update2d_kernel (2D wave kernel, N=5)", "alg_bytes_per_launch": per_launch,
+                "kernel": KERNEL_LABELS.get(fvpatch.fv_get_tuning(dim, nq, p)["kernel"], "?"),
+                "alg_bytes_per_launch": per_launch,
                 "alg_bytes_per_cell": round(per_launch / cells, 3)}
 
     out = {

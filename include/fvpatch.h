@@ -129,7 +129,7 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
  *             for those classes)
  *   block     threads per block, a multiple of 64 (0 = default); the wave
  *             kernel takes at most 256, the tile kernel at least p*p, the
- *             fixed-size kernel exactly 256
+ *             fixed-size kernel exactly 64
  *   prefetch  rows each lane keeps in flight in the wave kernel, 1..4
  *             (0 = default); set by the build for the fixed-size kernel
  *             (0 or that value)

@@ -38,7 +38,7 @@ def candidates(dim: int, nq: int, p: int) -> list[dict]:
     """Launch parameters worth timing for a class (the library rejects ones that do not fit)."""
     out = []
     if dim == 2 and nq == 5 and p in fv.FIXED_SIZES_2D:
-        out.append(dict(kernel=fv.FV_KERNEL_FIXED, block=256, prefetch=0, rows=0))
+        out.append(dict(kernel=fv.FV_KERNEL_FIXED, block=0, prefetch=0, rows=0))
     if dim == 2 and p + 2 <= 64:
         for pf in (2, 3, 4):
             for rows in (4, 6, 8):

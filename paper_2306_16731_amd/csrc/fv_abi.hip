@@ -220,7 +220,8 @@ static fv_tuning *tune_slot(int dim, int nq, int p) {
 }
 
 static int default_block_for(int kernel, int p, int dim) {
-    if (kernel == FV_KERNEL_WAVE || kernel == FV_KERNEL_FIXED) return 256;
+    if (kernel == FV_KERNEL_WAVE) return 256;
+    if (kernel == FV_KERNEL_FIXED) return wave2d_fixed_block();
     if (kernel == FV_KERNEL_TILE) return tile2d_default_block(p);
     return default_block(p, dim);
 }
@@ -394,11 +395,12 @@ fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tunin
             return fail(FV_ERR_UNSUPPORTED, "no fixed-size kernel for dim=%d unknowns=%d p=%d", dim, unknowns, p);
         int pf = 0, rows = 0;
         wave2d_fixed_shape(p, &pf, &rows);
-        if (v.block != 0 && v.block != 256) return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel takes 256 threads");
+        const int fb = wave2d_fixed_block();
+        if (v.block != 0 && v.block != fb) return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel takes %d threads", fb);
         if ((v.prefetch != 0 && v.prefetch != pf) || (v.rows != 0 && v.rows != rows))
             return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel for p=%d is built with prefetch %d and rows %d", p,
                         pf, rows);
-        *slot = fv_tuning{FV_KERNEL_FIXED, 256, pf, rows};
+        *slot = fv_tuning{FV_KERNEL_FIXED, fb, pf, rows};
         return FV_OK;
     }
     if (v.block == 0) v.block = v.kernel == d.kernel ? d.block : default_block_for(v.kernel, p, dim);

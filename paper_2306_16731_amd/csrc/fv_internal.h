@@ -87,6 +87,7 @@ hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream);
 bool wave2d_fixed(int p, int nq);
 int wave2d_fixed_ring_words(int p);
 void wave2d_fixed_shape(int p, int *prefetch, int *rows);
+int wave2d_fixed_block();
 hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream);
 
 // 2D kernel with whole patches per block, one thread per interior volume (p*p <= 1024).

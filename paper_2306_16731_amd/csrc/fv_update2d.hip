@@ -21,8 +21,14 @@
 // Writing R consecutive rows of a patch in one burst keeps HBM write pages
 // whole; storing each lane's 40-byte volume as it completes leaves every
 // page to be reopened once per row and costs about a fifth of the write rate.
+// The bursts are non-temporal stores: the output is not read again in this
+// launch, and keeping it out of the L2 leaves that to the input rows.
 // The waves of a block never synchronise with each other.  The per-patch
 // maximum is a segmented tree reduction over the patch's lanes at the end.
+//
+// Two forms: the runtime-size kernel (any p + 2 <= 64, launch parameters
+// from the tuning table) and the fixed-size kernel (compile-time p, see
+// wave_update_fixed), which keeps its loads in flight across the bursts.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -83,9 +89,9 @@ __device__ __forceinline__ void flush_rows(double *__restrict__ out, const doubl
             if (base < 0) continue;
             if constexpr (VEC == 2) {
                 const dv2 v = reinterpret_cast<const dv2 *>(ring + (size_t)sl * R * ROWD)[rem];
-                reinterpret_cast<dv2 *>(out + base + k0 * row)[rem] = v;
+                __builtin_nontemporal_store(v, reinterpret_cast<dv2 *>(out + base + k0 * row) + rem);
             } else {
-                out[base + k0 * row + rem] = ring[(size_t)sl * R * ROWD + rem];
+                __builtin_nontemporal_store(ring[(size_t)sl * R * ROWD + rem], out + base + k0 * row + rem);
             }
         }
     } else {
@@ -99,7 +105,7 @@ __device__ __forceinline__ void flush_rows(double *__restrict__ out, const doubl
             const int r = small_div(rem, inner, inv_inner, d);
             const int64_t base = bases[sl];
             if (base < 0) continue;
-            out[base + (k0 + r) * row + NQ + d] = ring[((size_t)sl * R + r) * ROWD + NQ + d];
+            __builtin_nontemporal_store(ring[((size_t)sl * R + r) * ROWD + NQ + d], out + base + (k0 + r) * row + NQ + d);
         }
     }
 }
@@ -269,8 +275,10 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
 template <int P>
 struct FixedShape {
     static constexpr int PF = 2;                    // rows in flight per lane
-    static constexpr int R = P <= 9 ? P : 8;        // output rows per burst
+    static constexpr int R = P <= 12 ? P : 12;      // output rows per burst
 };
+constexpr int kFixedBlock = 64;                     // one wave per block: LDS, not registers, bounds residency
+constexpr int kTaskBlock = 64;                      // the same for the task-list kernel
 
 inline bool fixed_size(int p) { return p == 3 || p == 5 || p == 9 || p == 16 || p == 17; }
 
@@ -390,10 +398,10 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                         sl = item0 + sl < num_items ? sl : 0;
                         const int64_t base = bases[sl] + (int64_t)k0 * ROWD;
                         if constexpr (VEC == 2)
-                            reinterpret_cast<dv2 *>(out + base)[rem] =
-                                reinterpret_cast<const dv2 *>(ring + sl * R * ROWD)[rem];
+                            __builtin_nontemporal_store(reinterpret_cast<const dv2 *>(ring + sl * R * ROWD)[rem],
+                                                        reinterpret_cast<dv2 *>(out + base) + rem);
                         else
-                            out[base + rem] = ring[sl * R * ROWD + rem];
+                            __builtin_nontemporal_store(ring[sl * R * ROWD + rem], out + base + rem);
                     }
                     // y-halo rows: row P+1 takes row 1, row 0 takes row P (interior columns)
                     if (k0 == 1 || kk == P) {
@@ -410,7 +418,8 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                                 int sl = c / iper;
                                 const int d = c - sl * iper;
                                 sl = item0 + sl < num_items ? sl : 0;
-                                out[bases[sl] + (int64_t)dest * ROWD + NQ + d] = ring[(sl * R + from) * ROWD + NQ + d];
+                                __builtin_nontemporal_store(ring[(sl * R + from) * ROWD + NQ + d],
+                                                            out + bases[sl] + (int64_t)dest * ROWD + NQ + d);
                             }
                         }
                     }
@@ -426,7 +435,8 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                         const int rem = c - sl * per;
                         const int rw = rem / inner, d = rem - rw * inner;
                         sl = item0 + sl < num_items ? sl : 0;
-                        out[bases[sl] + (int64_t)(k0 + rw) * ROWD + NQ + d] = ring[(sl * R + rw) * ROWD + NQ + d];
+                        __builtin_nontemporal_store(ring[(sl * R + rw) * ROWD + NQ + d],
+                                                    out + bases[sl] + (int64_t)(k0 + rw) * ROWD + NQ + d);
                     }
                 }
                 wave_lds_fence();
@@ -507,7 +517,7 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
 
 // Uniform launch of the fixed-size form.
 template <int P, int VEC, bool PERIODIC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFixedBlock)
 update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
                       int64_t stride, double r, const double *__restrict__ r_dev, double gamma,
@@ -528,7 +538,7 @@ update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
 // the grid), so a grid smaller than the task list is persistent; tasks sorted
 // largest first balance the tail.
 template <int NQ, int PF, int VEC, bool PERIODIC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kTaskBlock)
 update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids,
                       const WaveTask *__restrict__ tasks, int32_t num_tasks,
@@ -587,7 +597,7 @@ hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
 
 template <int NQ, int PF, int VEC, bool PERIODIC>
 hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
-    const int B = 256;
+    const int B = kTaskBlock;
     const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)T.ring_words;
     int dev = 0, lds_max = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -662,7 +672,7 @@ hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream) {
 template <int P, int VEC, bool PERIODIC>
 static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
     constexpr int ppw = 64 / (P + 2);
-    const int B = 256;
+    const int B = kFixedBlock;
     const int per_block = (B / 64) * ppw;
     const int64_t blocks = ((int64_t)L.num_items + per_block - 1) / per_block;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -701,6 +711,8 @@ void wave2d_fixed_shape(int p, int *prefetch, int *rows) {
     *prefetch = 0;
     *rows = 0;
 }
+
+int wave2d_fixed_block() { return kFixedBlock; }
 
 int wave2d_fixed_ring_words(int p) {
     switch (p) {

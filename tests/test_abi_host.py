@@ -162,7 +162,7 @@ def test_plan_validation_before_device():
 def test_tuning_table_on_host():
     """Defaults and validation of the per-class launch parameters (no device needed)."""
     try:
-        assert F.fv_get_tuning(2, 5, 16) == dict(kernel=F.FV_KERNEL_FIXED, block=256, prefetch=2, rows=8)
+        assert F.fv_get_tuning(2, 5, 16) == dict(kernel=F.FV_KERNEL_FIXED, block=64, prefetch=2, rows=12)
         for p in F.FIXED_SIZES_2D:
             assert F.fv_get_tuning(2, 5, p)["kernel"] == F.FV_KERNEL_FIXED
         assert F.fv_get_tuning(2, 4, 16)["kernel"] == F.FV_KERNEL_WAVE     # no fixed build for four unknowns
@@ -172,7 +172,7 @@ def test_tuning_table_on_host():
             ((2, 4, 16, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
             ((2, 5, 7, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
             ((3, 5, 8, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
-            ((2, 5, 16, dict(kernel=4, block=128, prefetch=0, rows=0)), F.FV_ERR_INVALID_ARG),
+            ((2, 5, 16, dict(kernel=4, block=256, prefetch=0, rows=0)), F.FV_ERR_INVALID_ARG),
             ((2, 5, 16, dict(kernel=4, block=0, prefetch=3, rows=0)), F.FV_ERR_INVALID_ARG),
             ((2, 5, 16, dict(kernel=4, block=0, prefetch=0, rows=5)), F.FV_ERR_INVALID_ARG),
             ((2, 5, 16, dict(kernel=5, block=0, prefetch=0, rows=0)), F.FV_ERR_INVALID_ARG),
@@ -180,7 +180,7 @@ def test_tuning_table_on_host():
         for (dim, nq, p, t), status in bad:
             assert F.fv_set_tuning(dim, nq, p, t, raise_on_error=False) == status, (dim, nq, p, t)
         # the build's own values are accepted; automatic choice with other values falls back to the wave kernel
-        assert F.fv_set_tuning(2, 5, 16, dict(kernel=4, block=256, prefetch=2, rows=8), raise_on_error=False) == F.FV_OK
+        assert F.fv_set_tuning(2, 5, 16, dict(kernel=4, block=64, prefetch=2, rows=12), raise_on_error=False) == F.FV_OK
         assert F.fv_set_tuning(2, 5, 16, dict(kernel=0, block=0, prefetch=4, rows=6), raise_on_error=False) == F.FV_OK
         assert F.fv_get_tuning(2, 5, 16) == dict(kernel=F.FV_KERNEL_WAVE, block=256, prefetch=4, rows=6)
     finally:

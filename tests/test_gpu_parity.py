@@ -273,7 +273,7 @@ def test_fixed_size_kernel_matches_runtime_size_kernel_bitwise(p, periodic):
     results = {}
     try:
         for kernel in (fvpatch.FV_KERNEL_FIXED, fvpatch.FV_KERNEL_WAVE):
-            fvpatch.fv_set_tuning(2, 5, p, dict(kernel=kernel, block=256, prefetch=0, rows=0))
+            fvpatch.fv_set_tuning(2, 5, p, dict(kernel=kernel, block=0, prefetch=0, rows=0))
             results[kernel] = (hp.gpu_step(data, sizes, starts, 2, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic),
                                hp.gpu_step(compact.data, sizes, None, 2, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic,
                                            pass_offsets=False))
