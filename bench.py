@@ -234,7 +234,7 @@ def bench_batching(args) -> int:
         autotune.load(args.tuning_table)
         tuned = {"table": os.path.basename(args.tuning_table)}
     else:
-        tuned = autotune.tune_classes([(2, 5, p) for p in (3, 5, 9, 17)] + [(3, 5, 8)])
+        tuned = autotune.tune_classes([(2, 5, p) for p in (3, 5, 9, 17)] + [(3, 5, 8)], periodic=False)
     t_tune = time.perf_counter() - t_tune
     for name in ("c3_2d_mixed_T200000", "c4_3d_p8_T32768"):
         b, spec = wl.build_workload(name, seed=args.seed)

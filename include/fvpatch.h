@@ -124,9 +124,10 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
  *             size), FV_KERNEL_WAVE (2D only: one padded patch row per
  *             wavefront, p + 2 <= 64), FV_KERNEL_TILE (2D only: whole
  *             patches per block, one thread per interior volume, p*p <= 1024)
- *             or FV_KERNEL_FIXED (the wave kernel compiled for one patch
- *             size: 2D, unknowns = 5, p in {3, 5, 9, 16, 17}; the default
- *             for those classes)
+ *             or FV_KERNEL_FIXED (a kernel compiled for one patch size,
+ *             unknowns = 5: the 2D wave kernel for p in {3, 5, 9, 16, 17},
+ *             a 3D kernel with one patch cross-section per wavefront for
+ *             3D p in {4, 6, 8}; the default for those classes)
  *   block     threads per block, a multiple of 64 (0 = default); the wave
  *             kernel takes at most 256, the tile kernel at least p*p, the
  *             fixed-size kernel exactly 64

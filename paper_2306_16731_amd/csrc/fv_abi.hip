@@ -62,15 +62,24 @@ static bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b
 fv_status check_layout(const int32_t *sizes, const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t nq,
                        BatchShape *shape) {
     if (!sizes) return fail(FV_ERR_INVALID_ARG, "sizes must be non-null");
+    if (num_patches <= 0) return fail(FV_ERR_INVALID_ARG, "num_patches must be > 0");
     const int pmax = max_p(dim);
-    shape->uniform_p = sizes[0];
     shape->contiguous = offsets == nullptr;
     int64_t lo = INT64_MAX, hi = 0;
+    // Branch-free min / max over the sizes (the compiler vectorises it: this
+    // runs once per call over up to millions of entries); the offending entry
+    // is looked up only when the range check fails.
+    int32_t smin = INT32_MAX, smax = INT32_MIN;
     for (int32_t t = 0; t < num_patches; ++t) {
-        const int32_t p = sizes[t];
-        if (p < 1 || p > pmax) return fail(FV_ERR_INVALID_ARG, "sizes[%d]=%d outside [1, %d] for %dD", t, p, pmax, dim);
-        if (p != shape->uniform_p) shape->uniform_p = -1;
+        smin = std::min(smin, sizes[t]);
+        smax = std::max(smax, sizes[t]);
     }
+    if (smin < 1 || smax > pmax) {
+        for (int32_t t = 0; t < num_patches; ++t)
+            if (sizes[t] < 1 || sizes[t] > pmax)
+                return fail(FV_ERR_INVALID_ARG, "sizes[%d]=%d outside [1, %d] for %dD", t, sizes[t], pmax, dim);
+    }
+    shape->uniform_p = smin == smax ? smin : -1;
     if (offsets == nullptr) {
         if (shape->uniform_p < 0) return fail(FV_ERR_INVALID_ARG, "offsets == NULL requires equal sizes");
         lo = 0;
@@ -226,14 +235,19 @@ static int default_block_for(int kernel, int p, int dim) {
     return default_block(p, dim);
 }
 
+static void fixed_shape(int dim, int p, int *prefetch, int *rows) {
+    if (dim == 2) wave2d_fixed_shape(p, prefetch, rows);
+    else wave3d_fixed_shape(p, prefetch, rows);
+}
+
 fv_tuning default_tuning(int dim, int nq, int p) {
     fv_tuning t{FV_KERNEL_AUTO, 0, 0, 0};
     t.kernel = (dim == 2 && wave2d_fits(p)) ? FV_KERNEL_WAVE : FV_KERNEL_BLOCK;
-    if (dim == 2 && wave2d_fixed(p, nq)) t.kernel = FV_KERNEL_FIXED;
+    if ((dim == 2 && wave2d_fixed(p, nq)) || (dim == 3 && wave3d_fixed(p, nq))) t.kernel = FV_KERNEL_FIXED;
     t.block = default_block_for(t.kernel, p, dim);
     t.prefetch = t.kernel == FV_KERNEL_WAVE ? 4 : 1;
     t.rows = t.kernel == FV_KERNEL_WAVE ? 6 : 1;
-    if (t.kernel == FV_KERNEL_FIXED) wave2d_fixed_shape(p, &t.prefetch, &t.rows);
+    if (t.kernel == FV_KERNEL_FIXED) fixed_shape(dim, p, &t.prefetch, &t.rows);
     return t;
 }
 
@@ -391,10 +405,10 @@ fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tunin
     if (v.kernel == FV_KERNEL_TILE && !(dim == 2 && tile2d_fits(p)))
         return fail(FV_ERR_UNSUPPORTED, "the tile kernel needs 2D and p*p <= 1024");
     if (v.kernel == FV_KERNEL_FIXED) {
-        if (!(dim == 2 && wave2d_fixed(p, unknowns)))
+        if (!((dim == 2 && wave2d_fixed(p, unknowns)) || (dim == 3 && wave3d_fixed(p, unknowns))))
             return fail(FV_ERR_UNSUPPORTED, "no fixed-size kernel for dim=%d unknowns=%d p=%d", dim, unknowns, p);
         int pf = 0, rows = 0;
-        wave2d_fixed_shape(p, &pf, &rows);
+        fixed_shape(dim, p, &pf, &rows);
         const int fb = wave2d_fixed_block();
         if (v.block != 0 && v.block != fb) return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel takes %d threads", fb);
         if ((v.prefetch != 0 && v.prefetch != pf) || (v.rows != 0 && v.rows != rows))

@@ -88,6 +88,11 @@ bool wave2d_fixed(int p, int nq);
 int wave2d_fixed_ring_words(int p);
 void wave2d_fixed_shape(int p, int *prefetch, int *rows);
 int wave2d_fixed_block();
+// 3D kernel with a patch's cross-section in one wavefront (compile-time
+// p in {4, 6, 8}, N = 5; one wave per block).
+bool wave3d_fixed(int p, int nq);
+void wave3d_fixed_shape(int p, int *prefetch, int *rows);
+hipError_t launch_update3d_fixed(const UpdateLaunch &L, hipStream_t stream);
 hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream);
 
 // 2D kernel with whole patches per block, one thread per interior volume (p*p <= 1024).

@@ -289,12 +289,15 @@ size_t update_lds_bytes(int dim, int nq, int block) {
 
 hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream) {
     if (L.num_items <= 0) return hipSuccess;
-    // kernel: 0 default, 1 block, 2 wave, 3 tile, 4 fixed-size wave
+    // kernel: 0 default, 1 block, 2 wave, 3 tile, 4 fixed-size wave (2D and 3D)
     if (L.dim == 2 && L.kernel == 2) return wave2d_fits(L.p) ? launch_update2d(L, stream) : hipErrorInvalidConfiguration;
     if (L.dim == 2 && L.kernel == 3) return tile2d_fits(L.p) ? launch_update2d_tile(L, stream) : hipErrorInvalidConfiguration;
     if (L.dim == 2 && L.kernel == 4)
         return wave2d_fixed(L.p, L.nq) ? launch_update2d_fixed(L, stream) : hipErrorInvalidConfiguration;
+    if (L.dim == 3 && L.kernel == 4)
+        return wave3d_fixed(L.p, L.nq) ? launch_update3d_fixed(L, stream) : hipErrorInvalidConfiguration;
     if (L.dim == 2 && L.kernel == 0 && wave2d_fixed(L.p, L.nq)) return launch_update2d_fixed(L, stream);
+    if (L.dim == 3 && L.kernel == 0 && wave3d_fixed(L.p, L.nq)) return launch_update3d_fixed(L, stream);
     if (L.dim == 2 && L.kernel == 0 && wave2d_fits(L.p)) return launch_update2d(L, stream);
     if (L.dim == 2 && L.nq == 5) return launch_typed<2, 5>(L, stream);
     if (L.dim == 2 && L.nq == 4) return launch_typed<2, 4>(L, stream);

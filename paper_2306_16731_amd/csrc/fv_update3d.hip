@@ -1,0 +1,412 @@
+// fv_update3d.hip -- 3D patch update with a whole patch cross-section in one wavefront.
+//
+// The same step as the other kernels (conservative update of Sec. 2.2 with
+// the Rusanov flux of Eq. 2 and the Euler user terms; per-patch eigenvalue
+// of the new state), for small 3D patches: compile-time p with p + 2 even and
+// (p + 2)^2 / 2 <= 64.  A lane owns two x-adjacent volumes (i = 2m, 2m + 1)
+// of one row j of the cross-section, so a patch's (p + 2)^2 plane takes
+// (p + 2)^2 / 2 lanes (50 for p = 8) and a wave holds floor(64 / that)
+// patches.  The wave marches along z through the p + 2 layers:
+//
+//   layer k:  read layer k (layers k+1 .. k+PF-1 already in flight): each
+//               lane reads its two volumes, 80 contiguous bytes, so the wave
+//               reads the patch's 40 (p+2)^2-byte layer as one contiguous run
+//             user terms of both volumes once: 1/rho, p, c, F and l per axis
+//             x faces: the face between the lane's two volumes in registers,
+//               the face to the left from the lane to the left (DPP shift),
+//               the right face of the second volume from the lane to the
+//               right (second DPP shift)
+//             y faces: the lane p/2 + 1 positions down the wave holds row j-1
+//               (ds_bpermute; no LDS allocation, no barrier)
+//             z face between layers k-1 and k from registers
+//             complete layer k-1 into an LDS ring of R layers, fold l into the
+//               patch maximum
+//             every R layers: write the ring in contiguous chunks
+//
+// As in the 2D fixed-size kernel, every loop has a static trip count and every
+// global load and store is issued unconditionally (lanes without a patch read
+// the wave's first patch, layers past the patch re-read its last layer, spare
+// lanes of a burst repeat a chunk another lane writes with the same value), so
+// the compiler counts outstanding memory operations exactly and the loads
+// stay in flight across the bursts.  No block barriers: a wave is a block.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "fv_internal.h"
+#include "fv_physics.h"
+
+namespace fv {
+namespace {
+
+constexpr uint32_t kPeriodic3 = 0x2u;
+constexpr int kBlock3 = 64;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp3(double x) {
+    const int2 v = __builtin_bit_cast(int2, x);
+    const int lo = __builtin_amdgcn_mov_dpp(v.x, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(v.y, CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, make_int2(lo, hi));
+}
+__device__ __forceinline__ double lane_left(double x) { return dpp3<0x138>(x); }   // wave_shr:1
+__device__ __forceinline__ double lane_right(double x) { return dpp3<0x130>(x); }  // wave_shl:1
+
+// x from lane `src` (0 <= src < 64) through the LDS crossbar (ds_bpermute).
+__device__ __forceinline__ double lane_from(double x, int src) {
+    const int2 v = __builtin_bit_cast(int2, x);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, v.x);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, v.y);
+    return __builtin_bit_cast(double, make_int2(lo, hi));
+}
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <int P>
+struct Shape3 {
+    static constexpr int W = P + 2;
+    static constexpr int H = W / 2;          // volume pairs per row
+    static constexpr int LP = H * W;         // lanes per patch
+    static constexpr int ppw = 64 / LP;      // patches per wave
+    static constexpr int PLANE = W * W * 5;  // doubles per layer
+    static constexpr int PF = 2;             // layers in flight per lane
+    static constexpr int R = 2;              // layers per burst
+    static constexpr int ring_words = ppw * R * PLANE + ppw;
+    static_assert(W % 2 == 0 && ppw >= 1, "needs p + 2 even and (p + 2)^2 / 2 <= 64");
+};
+
+template <int NQ>
+__device__ __forceinline__ void load_pair(const double *__restrict__ src, double (&q)[2][NQ]) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q[v][c] = src[v * NQ + c];
+}
+
+template <int NQ>
+__device__ __forceinline__ void load_pair16(const double *__restrict__ src, double (&q)[2][NQ]) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    double t[2 * NQ];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+        const dv2 x = reinterpret_cast<const dv2 *>(src)[c];
+        t[2 * c] = x.x;
+        t[2 * c + 1] = x.y;
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q[v][c] = t[v * NQ + c];
+}
+
+// Copy `runs` runs of `len` doubles (run r starting at src_off(r) in the LDS
+// layer and dst_off(r) in the patch) for every (slot, layer) of a burst.
+// Spare lanes repeat the last chunk; chunks of slots without a patch repeat
+// slot 0's.  VEC = 2 moves 16-byte chunks (len and both offsets even).
+template <int VEC, int PPW, int NL, int RUNS, int LEN, class SrcOff, class DstOff>
+__device__ __forceinline__ void burst(double *__restrict__ out, const double *ring, const int64_t *bases,
+                                      int64_t item0, int64_t num_items, int lane, SrcOff src_off,
+                                      DstOff dst_off) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    constexpr int per_run = LEN / VEC;
+    constexpr int per_layer = RUNS * per_run;
+    constexpr int per_slot = NL * per_layer;
+    constexpr int total = PPW * per_slot;
+#pragma unroll
+    for (int jj = 0; jj < (total + 63) / 64; ++jj) {
+        const int c = lane + 64 * jj < total ? lane + 64 * jj : total - 1;
+        int sl = c / per_slot;
+        int rem = c - sl * per_slot;
+        const int ly = rem / per_layer;
+        rem -= ly * per_layer;
+        const int run = rem / per_run;
+        const int e = (rem - run * per_run) * VEC;
+        sl = item0 + sl < num_items ? sl : 0;
+        const double *s = ring + src_off(sl, ly, run) + e;
+        double *d = out + bases[sl] + dst_off(ly, run) + e;
+        if constexpr (VEC == 2)
+            __builtin_nontemporal_store(*reinterpret_cast<const dv2 *>(s), reinterpret_cast<dv2 *>(d));
+        else
+            __builtin_nontemporal_store(*s, d);
+    }
+}
+
+template <int P, int VEC, bool PERIODIC>
+__device__ __forceinline__ void wave_update3d(const double *__restrict__ in, double *__restrict__ out,
+                                              const int64_t *__restrict__ offsets,
+                                              const int64_t *__restrict__ out_offsets,
+                                              const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
+                                              int64_t stride, double r, double gamma,
+                                              double *__restrict__ lambda_out, double *ring) {
+    using S = Shape3<P>;
+    constexpr int NQ = 5;
+    constexpr int W = S::W, H = S::H, LP = S::LP, ppw = S::ppw, PLANE = S::PLANE, PF = S::PF, R = S::R;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int slot = lane / LP;
+    const int l = lane - slot * LP;
+    const int j = l / H;
+    const int m = l - j * H;
+    const int i0 = 2 * m;  // x index of the lane's first volume; the second is i0 + 1
+    const int64_t item = item0 + slot;
+    const bool active = slot < ppw && item < num_items;
+    const bool yin = j >= 1 && j <= P;
+    const bool int0 = active && yin && i0 >= 1;       // first volume in the plane interior
+    const bool int1 = active && yin && i0 + 1 <= P;   // second volume in the plane interior
+    const int64_t self = active ? item : item0;
+    const int64_t off = offsets ? offsets[self] : self * stride;
+    const int64_t off_out = out_offsets ? out_offsets[self] : off;
+    const double *src = in + off + (int64_t)(j * W + i0) * NQ;
+    const int below = lane >= H ? lane - H : lane;    // row j - 1 of the same patch (j >= 1)
+    const int above = lane + H < 64 ? lane + H : lane;  // row j + 1
+
+    int64_t *bases = reinterpret_cast<int64_t *>(ring + ppw * R * PLANE);
+    wave_fence();
+    if (l == 0 && slot < ppw) bases[slot] = off_out;
+    wave_fence();
+
+    double qprev[2][NQ], fzprev[2][NQ], fhzprev[2][NQ], dprev[2][NQ], lzprev[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        rest_state<NQ>(qprev[v]);
+        rest_state<NQ>(fzprev[v]);
+        rest_state<NQ>(fhzprev[v]);
+        rest_state<NQ>(dprev[v]);
+        lzprev[v] = 0.0;
+    }
+    double lmax = 0.0;
+
+    double qbuf[PF][2][NQ];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+        const double *p = src + (int64_t)(t < W ? t : W - 1) * PLANE;
+        if constexpr (VEC == 2) load_pair16<NQ>(p, qbuf[t]);
+        else load_pair<NQ>(p, qbuf[t]);
+    }
+
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double q[2][NQ];
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) q[v][c] = qbuf[k % PF][v][c];
+        {
+            const double *p = src + (int64_t)(k + PF < W ? k + PF : W - 1) * PLANE;
+            if constexpr (VEC == 2) load_pair16<NQ>(p, qbuf[k % PF]);
+            else load_pair<NQ>(p, qbuf[k % PF]);
+        }
+
+        // Phases in this order keep few values alive at once: the primitives,
+        // then the z face and the completion of layer k - 1 (its carried state
+        // dies there), then the x and y differences of layer k.
+        Prim a[2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) a[v] = primitives<NQ>(q[v], gamma);
+
+        // z: the face between layers k - 1 and k
+        double fz[2][NQ], lz[2], fhz[2][NQ];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            euler_flux<NQ>(q[v], a[v], 2, fz[v], lz[v]);
+            rusanov<NQ>(qprev[v], fzprev[v], lzprev[v], q[v], fz[v], lz[v], fhz[v]);
+        }
+        if (k >= 2) {
+            const int kk = k - 1;         // layer completed now
+            const int rr = (kk - 1) % R;  // its place in the ring
+            double *lay = ring + (slot * R + rr) * PLANE;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                if (v == 0 ? int0 : int1) {
+                    double dsum[NQ], qn[NQ];
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) dsum[c] = dprev[v][c] + (fhzprev[v][c] - fhz[v][c]);
+                    advance<NQ>(qprev[v], dsum, r, qn);
+                    const int i = i0 + v;
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) lay[(j * W + i) * NQ + c] = qn[c];
+                    if (PERIODIC) {
+                        // face-halo copies inside the layer (edges never)
+                        if (i == P)
+#pragma unroll
+                            for (int c = 0; c < NQ; ++c) lay[(j * W) * NQ + c] = qn[c];
+                        if (i == 1)
+#pragma unroll
+                            for (int c = 0; c < NQ; ++c) lay[(j * W + P + 1) * NQ + c] = qn[c];
+                        if (j == P)
+#pragma unroll
+                            for (int c = 0; c < NQ; ++c) lay[i * NQ + c] = qn[c];
+                        if (j == 1)
+#pragma unroll
+                            for (int c = 0; c < NQ; ++c) lay[((P + 1) * W + i) * NQ + c] = qn[c];
+                    }
+                    if (lambda_out) lmax = nanmax(lmax, volume_lambda<3, NQ>(qn, gamma));
+                }
+            }
+            if (rr == R - 1 || kk == P) {
+                const int nl = rr + 1;
+                const int k0 = kk - rr;  // first layer in the ring
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+                wave_fence();
+                auto ring_layer = [&](int sl, int ly) { return (sl * R + ly) * PLANE; };
+                if (PERIODIC) {
+                    // rows 1 .. p whole (x face halos hold their copies), rows 0 and p+1 interior
+                    auto body = [&](auto NLc) {
+                        constexpr int NL = decltype(NLc)::value;
+                        burst<VEC, ppw, NL, 1, P * W * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int ly, int) { return ring_layer(sl, ly) + W * NQ; },
+                            [&](int ly, int) { return (int64_t)(k0 + ly) * PLANE + W * NQ; });
+                        burst<1, ppw, NL, 2, P * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int ly, int run) { return ring_layer(sl, ly) + (run * (P + 1) * W + 1) * NQ; },
+                            [&](int ly, int run) { return (int64_t)(k0 + ly) * PLANE + (run * (P + 1) * W + 1) * NQ; });
+                    };
+                    if (nl == R) body(std::integral_constant<int, R>{});
+                    else body(std::integral_constant<int, 1>{});
+                    // z face halos: layer p+1 takes layer 1, layer 0 takes layer p (plane interior)
+#pragma unroll
+                    for (int hz = 0; hz < 2; ++hz) {
+                        if (hz == 0 ? k0 != 1 : kk != P) continue;
+                        const int from = hz == 0 ? 0 : rr;
+                        const int dest = hz == 0 ? P + 1 : 0;
+                        burst<1, ppw, 1, P, P * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int, int run) { return ring_layer(sl, from) + ((run + 1) * W + 1) * NQ; },
+                            [&](int, int run) { return (int64_t)dest * PLANE + ((run + 1) * W + 1) * NQ; });
+                    }
+                } else {
+                    auto body = [&](auto NLc) {
+                        constexpr int NL = decltype(NLc)::value;
+                        burst<1, ppw, NL, P, P * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int ly, int run) { return ring_layer(sl, ly) + ((run + 1) * W + 1) * NQ; },
+                            [&](int ly, int run) { return (int64_t)(k0 + ly) * PLANE + ((run + 1) * W + 1) * NQ; });
+                    };
+                    if (nl == R) body(std::integral_constant<int, R>{});
+                    else body(std::integral_constant<int, 1>{});
+                }
+                wave_fence();
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                qprev[v][c] = q[v][c];
+                fzprev[v][c] = fz[v][c];
+                fhzprev[v][c] = fhz[v][c];
+            }
+            lzprev[v] = lz[v];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        // x: D_x = Fhat(i - 1/2) - Fhat(i + 1/2)
+        double din[2][NQ];
+        {
+            double fx[2][NQ], lx[2], fmid[NQ], fleft[NQ], qL[NQ], fL[NQ];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) euler_flux<NQ>(q[v], a[v], 0, fx[v], lx[v]);
+            rusanov<NQ>(q[0], fx[0], lx[0], q[1], fx[1], lx[1], fmid);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                qL[c] = lane_left(q[1][c]);
+                fL[c] = lane_left(fx[1][c]);
+            }
+            rusanov<NQ>(qL, fL, lane_left(lx[1]), q[0], fx[0], lx[0], fleft);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                din[0][c] = fleft[c] - fmid[c];
+                din[1][c] = fmid[c] - lane_right(fleft[c]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // y: the face below each volume from row j - 1, the face above from row j + 1
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            double fy[NQ], ly, qS[NQ], fS[NQ], fbelow[NQ];
+            euler_flux<NQ>(q[v], a[v], 1, fy, ly);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                qS[c] = lane_from(q[v][c], below);
+                fS[c] = lane_from(fy[c], below);
+            }
+            rusanov<NQ>(qS, fS, lane_from(ly, below), q[v], fy, ly, fbelow);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) dprev[v][c] = din[v][c] + (fbelow[c] - lane_from(fbelow[c], above));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    if (lambda_out) {
+        // segmented maximum over the lanes of each patch
+        for (int o = 1; o < LP; o <<= 1) {
+            const double other = __shfl_down(lmax, o, 64);
+            if (l + o < LP) lmax = nanmax(lmax, other);
+        }
+        if (active && l == 0) lambda_out[ids ? ids[item] : item] = lmax;
+    }
+}
+
+template <int P, int VEC, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock3)
+update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
+                      const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
+                      int64_t stride, double r, const double *__restrict__ r_dev, double gamma,
+                      double *__restrict__ lambda_out) {
+    extern __shared__ double lds[];
+    const int64_t item0 = (int64_t)blockIdx.x * Shape3<P>::ppw;
+    if (item0 >= num_items) return;
+    const double rr = r_dev ? *r_dev : r;
+    wave_update3d<P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
+                                    lambda_out, lds);
+}
+
+template <int P, int VEC, bool PERIODIC>
+hipError_t launch3d(const UpdateLaunch &L, hipStream_t stream) {
+    using S = Shape3<P>;
+    const int64_t blocks = ((int64_t)L.num_items + S::ppw - 1) / S::ppw;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(double) * (size_t)S::ring_words;
+    hipLaunchKernelGGL((update3d_fixed_kernel<P, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(kBlock3), lds, stream,
+                       L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev, L.gamma,
+                       L.lambda_out);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch3d_p(const UpdateLaunch &L, hipStream_t stream) {
+    const bool periodic = (L.flags & kPeriodic3) != 0;
+    if (L.vec2) return periodic ? launch3d<P, 2, true>(L, stream) : launch3d<P, 2, false>(L, stream);
+    return periodic ? launch3d<P, 1, true>(L, stream) : launch3d<P, 1, false>(L, stream);
+}
+
+}  // namespace
+
+bool wave3d_fixed(int p, int nq) { return nq == 5 && (p == 4 || p == 6 || p == 8); }
+
+void wave3d_fixed_shape(int p, int *prefetch, int *rows) {
+    *prefetch = 0;
+    *rows = 0;
+    if (!wave3d_fixed(p, 5)) return;
+    *prefetch = Shape3<8>::PF;  // the same for every built size
+    *rows = Shape3<8>::R;
+}
+
+hipError_t launch_update3d_fixed(const UpdateLaunch &L, hipStream_t stream) {
+    if (L.nq != 5) return hipErrorInvalidValue;
+    switch (L.p) {
+        case 4: return launch3d_p<4>(L, stream);
+        case 6: return launch3d_p<6>(L, stream);
+        case 8: return launch3d_p<8>(L, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fv

@@ -48,6 +48,7 @@ FV_KERNEL_WAVE = 2
 FV_KERNEL_TILE = 3
 FV_KERNEL_FIXED = 4
 FIXED_SIZES_2D = (3, 5, 9, 16, 17)  # patch sizes with a fixed-size build (2D, unknowns = 5)
+FIXED_SIZES_3D = (4, 6, 8)          # the same in 3D
 
 
 class fv_tuning(ctypes.Structure):

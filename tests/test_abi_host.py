@@ -49,8 +49,9 @@ def test_header_constants_match_binding():
     assert int(re.search(r"#define FV_HALO_PERIODIC (0x[0-9a-f]+)u", hdr).group(1), 16) == F.FV_HALO_PERIODIC
     for name in ["FV_KERNEL_AUTO", "FV_KERNEL_BLOCK", "FV_KERNEL_WAVE", "FV_KERNEL_TILE", "FV_KERNEL_FIXED"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name), name
-    sizes = re.search(r"p in \{([0-9, ]+)\}", hdr).group(1)
-    assert tuple(int(x) for x in sizes.split(",")) == F.FIXED_SIZES_2D
+    found = re.findall(r"p in \{([0-9, ]+)\}", hdr)
+    assert tuple(int(x) for x in found[0].split(",")) == F.FIXED_SIZES_2D
+    assert tuple(int(x) for x in found[1].split(",")) == F.FIXED_SIZES_3D
 
 
 def call(**kw):
@@ -167,11 +168,14 @@ def test_tuning_table_on_host():
             assert F.fv_get_tuning(2, 5, p)["kernel"] == F.FV_KERNEL_FIXED
         assert F.fv_get_tuning(2, 4, 16)["kernel"] == F.FV_KERNEL_WAVE     # no fixed build for four unknowns
         assert F.fv_get_tuning(2, 5, 7)["kernel"] == F.FV_KERNEL_WAVE
-        assert F.fv_get_tuning(3, 5, 8)["kernel"] == F.FV_KERNEL_BLOCK
+        assert F.fv_get_tuning(3, 5, 7)["kernel"] == F.FV_KERNEL_BLOCK
+        for p in F.FIXED_SIZES_3D:
+            assert F.fv_get_tuning(3, 5, p) == dict(kernel=F.FV_KERNEL_FIXED, block=64, prefetch=2, rows=2)
         bad = [
             ((2, 4, 16, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
             ((2, 5, 7, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
-            ((3, 5, 8, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
+            ((3, 5, 7, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
+            ((3, 5, 10, dict(kernel=4, block=0, prefetch=0, rows=0)), F.FV_ERR_UNSUPPORTED),
             ((2, 5, 16, dict(kernel=4, block=256, prefetch=0, rows=0)), F.FV_ERR_INVALID_ARG),
             ((2, 5, 16, dict(kernel=4, block=0, prefetch=3, rows=0)), F.FV_ERR_INVALID_ARG),
             ((2, 5, 16, dict(kernel=4, block=0, prefetch=0, rows=5)), F.FV_ERR_INVALID_ARG),
@@ -183,6 +187,9 @@ def test_tuning_table_on_host():
         assert F.fv_set_tuning(2, 5, 16, dict(kernel=4, block=64, prefetch=2, rows=12), raise_on_error=False) == F.FV_OK
         assert F.fv_set_tuning(2, 5, 16, dict(kernel=0, block=0, prefetch=4, rows=6), raise_on_error=False) == F.FV_OK
         assert F.fv_get_tuning(2, 5, 16) == dict(kernel=F.FV_KERNEL_WAVE, block=256, prefetch=4, rows=6)
+        assert F.fv_set_tuning(3, 5, 8, dict(kernel=4, block=64, prefetch=2, rows=2), raise_on_error=False) == F.FV_OK
     finally:
         for p in F.FIXED_SIZES_2D:
             F.fv_set_tuning(2, 5, p, None)
+        for p in F.FIXED_SIZES_3D:
+            F.fv_set_tuning(3, 5, p, None)

@@ -206,6 +206,19 @@ def test_invariants_on_gpu(step, dim, nq):
     inv.check_nan_propagates(step, dim, nq)
 
 
+@pytest.mark.parametrize("dim,p", [(2, 16), (2, 9), (2, 3), (3, 8), (3, 4)])
+def test_invariants_on_gpu_fixed_sizes(dim, p):
+    """The invariants at sizes the fixed-size kernels serve by default."""
+    _announce(f"invariants at fixed size dim={dim} p={p}")
+    inv.check_constant_state(hp.gpu_step, dim, 5, p=p)
+    inv.check_conservation(hp.gpu_step, dim, 5, p=p)
+    inv.check_mirror(hp.gpu_step, dim, 5, p=p)
+    inv.check_permutation(hp.gpu_step, dim, 5, p=p)
+    inv.check_corner_independence(hp.gpu_step, dim, 5, p=p)
+    inv.check_lambda_reduction(hp.gpu_step, dim, 5, p=p)
+    inv.check_nan_propagates(hp.gpu_step, dim, 5, p=p)
+
+
 def test_dimension_reduction_and_closed_form_on_gpu():
     inv.check_dimension_reduction(hp.gpu_step)
     inv.check_passive_scalar(hp.gpu_step)
@@ -233,7 +246,8 @@ VARIANTS = [
     (2, 32, dict(kernel=3, block=1024)), (2, 30, dict(kernel=2, block=128, prefetch=2)), (2, 17, dict(kernel=1, block=64)),
     (3, 8, dict(kernel=1, block=128)), (3, 8, dict(kernel=1, block=512)),
     (2, 3, dict(kernel=4)), (2, 5, dict(kernel=4)), (2, 9, dict(kernel=4)), (2, 16, dict(kernel=4)),
-    (2, 17, dict(kernel=4)),
+    (2, 17, dict(kernel=4)), (3, 4, dict(kernel=4)), (3, 6, dict(kernel=4)), (3, 8, dict(kernel=4)),
+    (3, 4, dict(kernel=1, block=128)), (3, 6, dict(kernel=1, block=128)),
 ]
 
 
@@ -287,6 +301,47 @@ def test_fixed_size_kernel_matches_runtime_size_kernel_bitwise(p, periodic):
         mask[starts[t]:starts[t] + vol] = False
     assert np.array_equal(fo[0][mask], data[mask]), "bytes outside the patches were written"
     want, want_lam = oracle.batch_update(compact.data, sizes, compact.offsets, 2, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA,
+                                         periodic)
+    assert np.all(hp.component_errors(fc[0], want, 5) <= TOL)
+    assert hp.lambda_error(fc[1], want_lam) <= TOL
+
+
+@pytest.mark.parametrize("p", [4, 6, 8])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_fixed_3d_kernel_matches_block_kernel_bitwise(p, periodic):
+    """The 3D one-wave-per-cross-section kernel and the plane-marching block kernel round
+    identically: bit-equal results, with a ragged last wave, gapped offsets and contiguous ones."""
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"3D fixed vs block: p={p} periodic={periodic}")
+    lanes = (p + 2) ** 2 // 2
+    ppw = 64 // lanes
+    T = 7 * ppw + max(ppw - 1, 1)
+    rng = np.random.Generator(np.random.PCG64(190 + p))
+    compact = wl.make_uniform(T, p, dim=3, nq=5, seed=191 + p)
+    vol = (p + 2) ** 3 * 5
+    starts = np.cumsum(np.concatenate([[1], vol + rng.integers(0, 4, size=T - 1)])).astype(np.int64)
+    data = rng.uniform(-1, 1, int(starts[-1] + vol + 3))
+    for t in range(T):
+        data[starts[t]:starts[t] + vol] = compact.data[t * vol:(t + 1) * vol]
+    sizes = np.full(T, p, np.int32)
+    results = {}
+    try:
+        for kernel in (fvpatch.FV_KERNEL_FIXED, fvpatch.FV_KERNEL_BLOCK):
+            fvpatch.fv_set_tuning(3, 5, p, dict(kernel=kernel, block=0, prefetch=0, rows=0))
+            results[kernel] = (hp.gpu_step(data, sizes, starts, 3, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic),
+                               hp.gpu_step(compact.data, sizes, None, 3, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic,
+                                           pass_offsets=False))
+    finally:
+        fvpatch.fv_set_tuning(3, 5, p, None)
+    (fo, fc), (bo, bc) = results[fvpatch.FV_KERNEL_FIXED], results[fvpatch.FV_KERNEL_BLOCK]
+    for f, b in ((fo, bo), (fc, bc)):
+        assert np.array_equal(f[1], b[1])
+        assert np.array_equal(f[0], b[0])
+    mask = np.ones(len(data), bool)
+    for t in range(T):
+        mask[starts[t]:starts[t] + vol] = False
+    assert np.array_equal(fo[0][mask], data[mask]), "bytes outside the patches were written"
+    want, want_lam = oracle.batch_update(compact.data, sizes, compact.offsets, 3, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA,
                                          periodic)
     assert np.all(hp.component_errors(fc[0], want, 5) <= TOL)
     assert hp.lambda_error(fc[1], want_lam) <= TOL
