@@ -49,6 +49,17 @@ KERNEL_LABELS = {1: "update_kernel (plane-marching block kernel)", 2: "update2d_
                  4: "update2d_fixed_kernel (2D wave kernel built for the patch size)"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -160,6 +171,37 @@ def main() -> int:
     cells = T * p ** dim
     value = cells * args.steps / (gpu_ms / 1e3)
 
+    # the oracle's sample is compared against the state right after the timed steps
+    S = min(args.cpu_sample_patches, T)
+    sample_state = d_a[: S * int(b.offsets[1])].clone()
+
+    # the same K-step measurement repeated (median of 16 samples), then a plain device copy of the
+    # state as the streaming ceiling of this GPU (sanity check of the roofline)
+    samples = []
+    for _ in range(16):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            step(d_a, d_b)
+            d_a, d_b = d_b, d_a
+        e1.record(stream)
+        torch.cuda.synchronize()
+        samples.append(e0.elapsed_time(e1) / args.steps)
+    samples.sort()
+    scratch = torch.empty_like(d_a)
+    for _ in range(3):
+        scratch.copy_(d_a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        scratch.copy_(d_a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * d_a.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del scratch
+
     per_launch = alg_bytes_per_patch(p, dim, nq, periodic, True) * T
     achieved = per_launch / (ms_per_step / 1e3) / 1e9
     traffic = measured_traffic()
@@ -168,7 +210,8 @@ def main() -> int:
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
                 "kernel": KERNEL_LABELS.get(fvpatch.fv_get_tuning(dim, nq, p)["kernel"], "?"),
                 "alg_bytes_per_launch": per_launch,
-                "alg_bytes_per_cell": round(per_launch / cells, 3)}
+                "alg_bytes_per_cell": round(per_launch / cells, 3),
+                "torch_copy_GBs": round(copy_gbs, 1), "frac_of_torch_copy": round(achieved / copy_gbs, 4)}
 
     out = {
         "metric": "cell-updates/s", "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1,
@@ -179,12 +222,13 @@ def main() -> int:
         "dof_updates_per_s": round(value * nq, 1),
         "roofline": roofline,
         "host_wall_s": round(wall, 4),
+        "repeat": {"samples": len(samples), "median_ms_per_step": round(samples[len(samples) // 2], 5),
+                   "min_ms_per_step": round(samples[0], 5), "max_ms_per_step": round(samples[-1], 5)},
         "tuning": fvpatch.fv_get_tuning(dim, nq, p),
     }
 
     if not args.no_cpu_baseline:
         import oracle
-        S = min(args.cpu_sample_patches, T)
         steps_total = args.warmup + args.steps
         sub = b.data[: S * int(b.offsets[1])]
         threads = oracle.max_threads()
@@ -192,12 +236,22 @@ def main() -> int:
         ora_state, _ = oracle.run_steps(sub, b.sizes[:S], b.offsets[:S], dim, nq, [dt] * steps_total, h, gamma,
                                         periodic, nthreads=threads)
         cpu_s = time.perf_counter() - t0
+        # one thread on a smaller sample of the same patches and steps
+        S1 = max(1, S // 16)
+        t1 = time.perf_counter()
+        oracle.run_steps(b.data[: S1 * int(b.offsets[1])], b.sizes[:S1], b.offsets[:S1], dim, nq, [dt] * steps_total,
+                         h, gamma, periodic, nthreads=1)
+        cpu1_s = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": round(S * p ** dim * steps_total / cpu_s, 1), "unit": "cell-updates/s",
                                "cores": threads, "kind": "oracle",
                                "sample": f"first {S} of the {T} patches, {steps_total} steps, same dt, "
-                                         f"OpenMP over patches ({cpu_s:.2f} s wall)"}
+                                         f"OpenMP over patches ({cpu_s:.2f} s wall)",
+                               "single_thread": {"value": round(S1 * p ** dim * steps_total / cpu1_s, 1),
+                                                 "sample": f"first {S1} patches, {steps_total} steps "
+                                                           f"({cpu1_s:.2f} s wall)"},
+                               "host_cpus_visible": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
         # the timed GPU run advanced the same patches with the same dt: compare them
-        got = d_a[: S * int(b.offsets[1])].cpu().numpy()
+        got = sample_state.cpu().numpy()
         g = got.reshape(-1, nq)
         w = ora_state.reshape(-1, nq)
         errs = np.max(np.abs(g - w), axis=0) / np.max(np.abs(w), axis=0)
