@@ -65,6 +65,12 @@ def _bind(lib):
     lib.fvo_rusanov.restype = None
     lib.fvo_max_threads.argtypes = []
     lib.fvo_max_threads.restype = ctypes.c_int32
+    lib.fvo_halo_fill.argtypes = [dp, dp, ip, lp, ip, i32, i32, i32]
+    lib.fvo_halo_fill.restype = ctypes.c_int
+    lib.fvo_batch_update_lts.argtypes = [dp, dp, ip, lp, i32, i32, i32, dp, dp, f64, dp, i32]
+    lib.fvo_batch_update_lts.restype = ctypes.c_int
+    lib.fvo_local_dt.argtypes = [dp, dp, i32, i32, f64, dp]
+    lib.fvo_local_dt.restype = ctypes.c_int
     return lib
 
 
@@ -130,6 +136,55 @@ def batch_wrap(state: np.ndarray, sizes, offsets, dim: int, nq: int, lib=None) -
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return state
+
+
+def halo_fill(src: np.ndarray, sizes, offsets, neighbors, dim: int, nq: int, dst: np.ndarray | None = None,
+              lib=None) -> np.ndarray:
+    """Face halos of every patch from its neighbours (neighbors: [T, 2*dim], -1 = none).
+    Writes into ``dst`` (default: a copy of ``src``) and returns it."""
+    lib = lib or load()
+    num_patches = len(offsets)
+    sizes, offsets = _descriptors(sizes, offsets, num_patches)
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    dst = src.copy() if dst is None else dst
+    nb = np.ascontiguousarray(np.asarray(neighbors, dtype=np.int32).reshape(num_patches, 2 * dim))
+    rc = lib.fvo_halo_fill(_dptr(src), _dptr(dst), sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), num_patches, dim, nq)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return dst
+
+
+def batch_update_lts(state_in: np.ndarray, sizes, offsets, dim: int, nq: int, dt, h, gamma: float = 1.4,
+                     out: np.ndarray | None = None, nthreads: int = 0, lib=None):
+    """One step of every patch t with its own dt[t] and h[t].  Returns (out, lambda)."""
+    lib = lib or load()
+    num_patches = len(offsets)
+    sizes, offsets = _descriptors(sizes, offsets, num_patches)
+    state_in = np.ascontiguousarray(state_in, dtype=np.float64)
+    out = state_in.copy() if out is None else out
+    dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (num_patches,)))
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), (num_patches,)))
+    lam = np.zeros(num_patches, dtype=np.float64)
+    rc = lib.fvo_batch_update_lts(_dptr(state_in), _dptr(out), sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), num_patches, dim, nq,
+                                  _dptr(dt), _dptr(h), gamma, _dptr(lam), nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out, lam
+
+
+def local_dt(lam, h, dim: int, cfl: float, lib=None) -> np.ndarray:
+    """Per-patch step size cfl * h[t] / (dim * lambda[t])."""
+    lib = lib or load()
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), lam.shape))
+    out = np.zeros_like(lam)
+    rc = lib.fvo_local_dt(_dptr(lam), _dptr(h), len(lam), dim, cfl, _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out
 
 
 def flux(q, n: int, nq: int, gamma: float = 1.4, lib=None):

@@ -256,6 +256,91 @@ int fvo_batch_wrap(double *state, const int32_t *sizes, const int64_t *offsets,
     return 0;
 }
 
+/*
+ * Face-halo fill from the neighbouring patches of a conforming patch mesh:
+ * the step before the update that equips each patch with its halo layer
+ * (Sec. 2.2).  neighbors[t*2d + 2n + s] is the patch that touches patch t
+ * across its face on axis n, side s (s = 0: the face at coordinate 0, s = 1:
+ * the face at p+1), or -1 for a face without a neighbour, whose halo volumes
+ * are left as they are.  The halo layer on side 0 of axis n takes the
+ * neighbour's interior layer at p (the layer next to their common face), the
+ * halo layer on side 1 the neighbour's interior layer at 1; the coordinates
+ * along the other axes are the same in both patches.  Faces only: corner /
+ * edge halo volumes are untouched.  Values are read from src and written to
+ * dst (which may be src itself: only interior volumes are read, only halo
+ * volumes written).  Returns -1 when a neighbour has another size.
+ */
+int fvo_halo_fill(const double *src, double *dst, const int32_t *sizes, const int64_t *offsets,
+                  const int32_t *neighbors, int32_t num_patches, int32_t dim, int32_t nq)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    for (int32_t t = 0; t < num_patches; ++t) {
+        int p = sizes[t];
+        for (int n = 0; n < dim; ++n)
+            for (int s = 0; s < 2; ++s) {
+                int32_t nb = neighbors[(size_t)t * 2 * dim + 2 * n + s];
+                if (nb < 0) continue;
+                if (sizes[nb] != p) return -1;
+                /* every volume (i, j, k) of the face: coordinate n fixed, the others 1..p */
+                int kbeg = (dim == 3) ? 1 : 0, kend = (dim == 3) ? p : 0;
+                for (int k = kbeg; k <= kend; ++k)
+                    for (int j = 1; j <= p; ++j)
+                        for (int i = 1; i <= p; ++i) {
+                            int h[3] = {i, j, k}, g[3] = {i, j, k};
+                            if (n == 0 && i != 1) continue;  /* axis n takes one value per face */
+                            if (n == 1 && j != 1) continue;
+                            if (n == 2 && k != 1) continue;
+                            h[n] = (s == 0) ? 0 : p + 1;    /* halo volume of patch t */
+                            g[n] = (s == 0) ? p : 1;        /* interior volume of the neighbour */
+                            memcpy(dst + offsets[t] + ora_vol(p, dim, h[0], h[1], h[2], nq),
+                                   src + offsets[nb] + ora_vol(p, dim, g[0], g[1], g[2], nq), sizeof(double) * nq);
+                        }
+            }
+    }
+    return 0;
+}
+
+/*
+ * One explicit Euler step of every patch with its own step size and mesh
+ * width: patch t advances by dt[t] with volumes of width h[t] (local time
+ * stepping: each patch has its own CFL-limited step, end of Sec. 2.2).  The
+ * face halos are taken as they are in `in` (filled beforehand, e.g. by
+ * fvo_halo_fill); out gets the new interiors, lambda_out (may be NULL) the
+ * maximum wave speed of each new interior.
+ */
+int fvo_batch_update_lts(const double *in, double *out, const int32_t *sizes, const int64_t *offsets,
+                         int32_t num_patches, int32_t dim, int32_t nq, const double *dt, const double *h,
+                         double gamma, double *lambda_out, int32_t nthreads)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    if (!(nq == 5 || (dim == 2 && nq == 4))) return -1;
+    if (num_patches < 0) return -1;
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+    for (int32_t t = 0; t < num_patches; ++t) {
+        int p = sizes[t];
+        ora_patch_step(in + offsets[t], out + offsets[t], p, dim, nq, dt[t], h[t], gamma);
+        if (lambda_out) lambda_out[t] = ora_patch_lambda(out + offsets[t], p, dim, nq, gamma);
+    }
+    (void)nthreads;
+    return 0;
+}
+
+/*
+ * Per-patch CFL step size from the patch's maximum wave speed (local time
+ * stepping):  dt[t] = cfl * h[t] / (d * lambda[t]).  The same expression
+ * as the global step size, per patch.
+ */
+int fvo_local_dt(const double *lambda, const double *h, int32_t num_patches, int32_t dim, double cfl,
+                 double *dt_out)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    for (int32_t t = 0; t < num_patches; ++t) dt_out[t] = cfl * h[t] / (dim * lambda[t]);
+    return 0;
+}
+
 /* Single-volume user terms, exposed so tests can evaluate F_n and lambda_n of
  * a given state directly. */
 void fvo_flux(const double *q, int32_t n, int32_t nq, double gamma, double *f, double *lam)

@@ -131,6 +131,94 @@ def make_mixed(num_patches: int, choices=(3, 5, 9, 17), dim: int = 2, nq: int = 
 
 
 # Named workloads.  Each entry: (builder kwargs, steps, periodic halo write).
+# ---------------------------------------------------------------- patch meshes
+# A conforming Cartesian mesh of n^d patches of one size covering the unit
+# square / cube, stored in the order of a space-filling curve over the patch
+# grid (Peano for n = 3^k in 2D, Morton for n = 2^k, row-major otherwise).
+# Only topology: which patch sits where and which patch touches which face.
+
+
+def _peano2d(n: int):
+    """Cells (x, y) of an n x n grid, n = 3^k, in Peano-curve order: columns of
+    3 x 3 blocks traversed bottom-up, top-down, bottom-up, each block
+    reflected so that consecutive cells share a face."""
+    if n == 1:
+        return [(0, 0)]
+    m = n // 3
+    sub = _peano2d(m)
+    out = []
+    for bi in range(3):
+        rows = range(3) if bi % 2 == 0 else range(2, -1, -1)
+        for vis, bj in enumerate(rows):
+            flip_x = vis % 2 == 1
+            flip_y = bi % 2 == 1
+            for (x, y) in sub:
+                xx = m - 1 - x if flip_x else x
+                yy = m - 1 - y if flip_y else y
+                out.append((bi * m + xx, bj * m + yy))
+    return out
+
+
+def _morton(n: int, dim: int):
+    cells = []
+    bits = n.bit_length() - 1
+    for code in range(n ** dim):
+        c = [0] * dim
+        for b in range(bits):
+            for a in range(dim):
+                c[a] |= ((code >> (b * dim + a)) & 1) << b
+        cells.append(tuple(c))
+    return cells
+
+
+def mesh_order(n: int, dim: int):
+    """Patch grid coordinates in storage order."""
+    if dim == 2 and n >= 3 and 3 ** round(np.log(n) / np.log(3)) == n:
+        return _peano2d(n)
+    if n >= 2 and n & (n - 1) == 0:
+        return _morton(n, dim)
+    if dim == 2:
+        return [(x, y) for y in range(n) for x in range(n)]
+    return [(x, y, z) for z in range(n) for y in range(n) for x in range(n)]
+
+
+@dataclass
+class Mesh:
+    batch: Batch
+    n: int                 # patches per axis
+    coords: np.ndarray     # int32 [T, dim]: grid position of patch t
+    neighbors: np.ndarray  # int32 [T, 2 dim]: patch across face (axis a, side s) at 2 a + s, or -1
+    periodic: bool
+
+    @property
+    def h(self) -> float:
+        """Volume width of the unit domain."""
+        return 1.0 / (self.n * int(self.batch.sizes[0]))
+
+
+def make_mesh(n: int, p: int, dim: int = 2, nq: int = 5, seed: int = 0, periodic: bool = True,
+              pulse: bool = False) -> Mesh:
+    """n^d patches of p^d volumes in space-filling-curve order with their
+    face-neighbour table (wrapping around when periodic, -1 at the boundary
+    otherwise); states drawn as in make_uniform."""
+    cells = mesh_order(n, dim)
+    T = len(cells)
+    index = {c: t for t, c in enumerate(cells)}
+    nb = np.full((T, 2 * dim), -1, np.int32)
+    for t, c in enumerate(cells):
+        for a in range(dim):
+            for s, step in ((0, -1), (1, 1)):
+                q = list(c)
+                q[a] += step
+                if not 0 <= q[a] < n:
+                    if not periodic:
+                        continue
+                    q[a] %= n
+                nb[t, 2 * a + s] = index[tuple(q)]
+    batch = make_uniform(T, p, dim=dim, nq=nq, seed=seed, pulse=pulse)
+    return Mesh(batch=batch, n=n, coords=np.asarray(cells, np.int32), neighbors=nb, periodic=periodic)
+
+
 WORKLOADS = {
     "c1_2d_p3_T16": dict(kind="uniform", num_patches=16, p=3, dim=2, steps=1, periodic=False, pulse=False),
     "c2_2d_p16_T65536": dict(kind="uniform", num_patches=65536, p=16, dim=2, steps=10, periodic=True, pulse=True),
