@@ -302,6 +302,61 @@ fv_status fv_server_stats_get(fv_server *server, fv_server_stats *stats);
 /* Wait for the server's stream, then free everything it holds (NULL: no-op). */
 fv_status fv_server_destroy(fv_server *server);
 
+/* ------------------------------------------------------------------------
+ * Patch mesh: the steps either side of the update (Sec. 2.2).  Before its
+ * update every patch is equipped with a halo layer taken from the patches
+ * that touch its faces, and after it the patch's maximum eigenvalue sets its
+ * own next step size (local time stepping).
+ *
+ * A mesh is a fixed set of num_patches patches of one size p (layout as in
+ * fv_patch_batch_update: sizes / offsets on the host, offsets NULL =
+ * contiguous) and a face-neighbour table: neighbors (host, [num_patches *
+ * 2 * dim]) holds at t*2*dim + 2*a + s the patch that touches patch t across
+ * its face on axis a (0 = x, 1 = y, 2 = z), side s (0: the face at index 0,
+ * 1: the face at p+1), or -1 for a face without a neighbour.  The halo
+ * layer on side 0 of axis a takes the neighbour's interior layer at p, on
+ * side 1 its interior layer at 1, at the same coordinates along the other
+ * axes.  Corner / edge halo volumes are never read or written.  The tables
+ * are copied to the device at creation; the caller's arrays may be freed.
+ * ------------------------------------------------------------------------ */
+typedef struct fv_mesh fv_mesh;
+
+/* Validate and upload a mesh.  Errors: FV_ERR_INVALID_ARG (dim, unknowns,
+ * num_patches <= 0, sizes, offsets, a neighbour index outside -1 ..
+ * num_patches-1), FV_ERR_UNSUPPORTED (patches of different sizes),
+ * FV_ERR_OVERLAP (patch ranges overlap), FV_ERR_NO_DEVICE, FV_ERR_OOM. */
+fv_status fv_mesh_create(fv_mesh **mesh, const int32_t *sizes, const int64_t *offsets, const int32_t *neighbors,
+                         int32_t num_patches, int32_t dim, int32_t unknowns);
+
+/* Write every face halo of `patches` (device) from the neighbours' interiors,
+ * in place (only halo volumes are written, only interior volumes read);
+ * faces without a neighbour keep their halo.  Any patch size.  Asynchronous
+ * on `stream`. */
+fv_status fv_mesh_halo_fill(fv_mesh *mesh, double *patches, void *stream);
+
+/* One explicit Euler step of every patch of the mesh, patch t by dt[t] with
+ * volumes of width h[t] (dt, h: device arrays [num_patches]); the face halos
+ * are read from the neighbours' interiors in patches_in during the update
+ * (no separate fill; a face without a neighbour uses the patch's own halo).
+ * patches_out gets the new interiors (its halo volumes are not written);
+ * lambda_out (device [num_patches] or NULL) the maximum wave speed of each
+ * new interior.  Built for 2D p in {3, 5, 9, 16, 17} and 3D p in {4, 6, 8}
+ * with 5 unknowns (FV_ERR_UNSUPPORTED otherwise: use fv_mesh_halo_fill and
+ * fv_patch_batch_update).  Errors also: FV_ERR_INVALID_ARG (null / unaligned
+ * pointers, gamma, another device), FV_ERR_OVERLAP (in / out / lambda / dt /
+ * h overlap), FV_ERR_LAUNCH. */
+fv_status fv_mesh_step(fv_mesh *mesh, const double *patches_in, double *patches_out, const double *dt,
+                       const double *h, double gamma, double *lambda_out, void *stream);
+
+/* Per-patch step sizes for local time stepping: dt_out[t] = cfl * h[t] /
+ * (dim * lambda[t]) on the device (all device arrays [num_patches]); the same
+ * expression as the global step size, per patch.  num_patches = 0: no-op. */
+fv_status fv_local_dt(const double *lambda, const double *h, int32_t num_patches, int32_t dim, double cfl,
+                      double *dt_out, void *stream);
+
+/* Wait for the device, then free the mesh's device tables (NULL: no-op). */
+fv_status fv_mesh_destroy(fv_mesh *mesh);
+
 /* Text for a status code (static storage). */
 const char *fv_status_string(fv_status status);
 

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(PKG, "libfvpatch.so")
 
 SOURCES = ["fv_update.hip", "fv_update2d.hip", "fv_update2d_tile.hip", "fv_update3d.hip", "fv_step.hip", "fv_abi.hip",
-           "fv_plan.hip", "fv_serve.hip"]
+           "fv_plan.hip", "fv_serve.hip", "fv_mesh.hip"]
 HEADERS = ["fv_internal.h", "fv_host.h", "fv_physics.h"]
 
 HIPCC_FLAGS = [
@@ -30,6 +30,7 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
+    "-Wshadow",
     "-Wno-unused-variable",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

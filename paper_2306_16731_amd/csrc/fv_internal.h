@@ -7,6 +7,15 @@
 
 namespace fv {
 
+// Face neighbours and per-patch step data of a patch mesh (the mesh form of
+// the fixed-size kernels: face halos are read from the neighbouring patches'
+// interiors, every patch has its own dt and h).  Null in the batch forms.
+struct MeshArgs {
+    const int32_t *neighbors = nullptr;  // device [T][2 dim]: patch across face (axis a, side s) at 2a + s, or -1
+    const double *dt = nullptr;          // device [T]
+    const double *h = nullptr;           // device [T]
+};
+
 // One launch of the patch-update kernel over `num_items` patches of one size.
 struct UpdateLaunch {
     const double *in = nullptr;
@@ -29,6 +38,7 @@ struct UpdateLaunch {
     int32_t prefetch = 0;              // rows in flight per lane (2D wave kernel), 0 = default
     bool vec2 = false;                 // every patch (and both buffers) 16-byte aligned: 16-byte loads
     int32_t rows = 0;                  // output rows staged per flush (2D wave kernel), 0 = default
+    MeshArgs mesh;                     // set: the mesh form (fixed-size kernels only)
 };
 
 // One wave's work in a task-list launch: `count` (<= 64 / (p + 2)) patches of

@@ -287,13 +287,18 @@ constexpr int fixed_ring_words() {
     return (64 / (P + 2)) * FixedShape<P>::R * (P + 2) * 5 + 64 / (P + 2);
 }
 
-template <int NQ, int P, int VEC, bool PERIODIC>
+// MESH: the face halos come from the neighbouring patches' interiors (the
+// halo volumes of a patch without a neighbour on that face are its own), and
+// patch t advances by dt[t] / h[t]; the output is the interior only.
+template <int NQ, int P, int VEC, bool PERIODIC, bool MESH = false>
 __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in, double *__restrict__ out,
                                                   const int64_t *__restrict__ offsets,
                                                   const int64_t *__restrict__ out_offsets,
                                                   const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
                                                   int64_t stride, double r, double gamma,
-                                                  double *__restrict__ lambda_out, double *ring) {
+                                                  double *__restrict__ lambda_out, double *ring,
+                                                  MeshArgs mesh = MeshArgs{}) {
+    static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
     constexpr int W = P + 2;
     constexpr int ppw = 64 / W;
     constexpr int ROWD = W * NQ;
@@ -313,6 +318,22 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     const int64_t off = offsets ? offsets[self] : self * stride;
     const int64_t off_out = out_offsets ? out_offsets[self] : off;
     const double *src = in + off + (int64_t)i * NQ;
+    // Row k is read at src_mid + k ROWD (k = 1 .. p), src_lo (k = 0) or src_hi
+    // (k = p+1): the patch's own column, or in the mesh form the neighbour's
+    // column (x halo lanes) / row (rows 0 and p+1).
+    const double *src_mid = src, *src_lo = src, *src_hi = src + (int64_t)(W - 1) * ROWD;
+    double ratio = r;  // dt / h of the lane's patch
+    if constexpr (MESH) {
+        const int32_t *nb = mesh.neighbors + 4 * self;
+        const int32_t nl = nb[0], nr = nb[1], nd = nb[2], nu = nb[3];
+        auto base = [&](int32_t q) { return in + (offsets ? offsets[q >= 0 ? q : self] : (q >= 0 ? q : self) * stride); };
+        const double *bl = base(nl), *br = base(nr), *bd = base(nd), *bu = base(nu);
+        src_mid = (i == 0 && nl >= 0) ? bl + P * NQ : ((i == P + 1 && nr >= 0) ? br + NQ : src);
+        src_lo = (xin && nd >= 0) ? bd + (int64_t)P * ROWD + i * NQ : src;
+        src_hi = (xin && nu >= 0) ? bu + (int64_t)ROWD + i * NQ : src_hi;
+        ratio = mesh.dt[self] / mesh.h[self];
+    }
+    auto row_ptr = [&](int k) { return k == 0 ? src_lo : (k == W - 1 ? src_hi : src_mid + (int64_t)k * ROWD); };
 
     int64_t *bases = reinterpret_cast<int64_t *>(ring + ppw * R * ROWD);
     wave_lds_fence();  // a previous patch group of this wave may still be reading the ring
@@ -328,14 +349,14 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
 
     double qbuf[PF][NQ];
 #pragma unroll
-    for (int m = 0; m < PF; ++m) load_volume<NQ>(src + (int64_t)(m < W ? m : W - 1) * ROWD, qbuf[m]);
+    for (int m = 0; m < PF; ++m) load_volume<NQ>(row_ptr(m < W ? m : W - 1), qbuf[m]);
 
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         double q[NQ];
 #pragma unroll
         for (int c = 0; c < NQ; ++c) q[c] = qbuf[k % PF][c];
-        load_volume<NQ>(src + (int64_t)(k + PF < W ? k + PF : W - 1) * ROWD, qbuf[k % PF]);
+        load_volume<NQ>(row_ptr(k + PF < W ? k + PF : W - 1), qbuf[k % PF]);
 
         const Prim a = primitives<NQ>(q, gamma);
         double fx[NQ], lx, fy[NQ], ly;
@@ -361,7 +382,7 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                 double d[NQ], qn[NQ];
 #pragma unroll
                 for (int c = 0; c < NQ; ++c) d[c] = dxprev[c] + (fhprev[c] - fh[c]);
-                advance<NQ>(qprev, d, r, qn);
+                advance<NQ>(qprev, d, ratio, qn);
                 double *srow = ring + (slot * R + rr) * ROWD;
 #pragma unroll
                 for (int c = 0; c < NQ; ++c) srow[i * NQ + c] = qn[c];
@@ -516,20 +537,20 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
 }
 
 // Uniform launch of the fixed-size form.
-template <int P, int VEC, bool PERIODIC>
+template <int P, int VEC, bool PERIODIC, bool MESH>
 __global__ void __launch_bounds__(kFixedBlock)
 update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
                       int64_t stride, double r, const double *__restrict__ r_dev, double gamma,
-                      double *__restrict__ lambda_out) {
+                      double *__restrict__ lambda_out, MeshArgs mesh) {
     extern __shared__ double lds[];
     constexpr int ppw = 64 / (P + 2);
     const int wave = threadIdx.x >> 6;
     const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
     if (item0 >= num_items) return;
     const double rr = r_dev ? *r_dev : r;
-    wave_update_fixed<5, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
-                                           lambda_out, lds + (size_t)wave * fixed_ring_words<P>());
+    wave_update_fixed<5, P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr,
+                                                 gamma, lambda_out, lds + (size_t)wave * fixed_ring_words<P>(), mesh);
 }
 
 // Task-list launch over mixed patch sizes: task t holds `count` patches of
@@ -669,7 +690,7 @@ hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream) {
 }
 
 // Uniform launch of the fixed-size form over patches of one size.
-template <int P, int VEC, bool PERIODIC>
+template <int P, int VEC, bool PERIODIC, bool MESH = false>
 static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
     constexpr int ppw = 64 / (P + 2);
     const int B = kFixedBlock;
@@ -682,19 +703,20 @@ static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return hipErrorInvalidDevice;
     if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
-    const void *fn = reinterpret_cast<const void *>(&update2d_fixed_kernel<P, VEC, PERIODIC>);
+    const void *fn = reinterpret_cast<const void *>(&update2d_fixed_kernel<P, VEC, PERIODIC, MESH>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((update2d_fixed_kernel<P, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(B), lds, stream, L.in,
-                       L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev, L.gamma,
-                       L.lambda_out);
+    hipLaunchKernelGGL((update2d_fixed_kernel<P, VEC, PERIODIC, MESH>), dim3((unsigned)blocks), dim3(B), lds, stream,
+                       L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev, L.gamma,
+                       L.lambda_out, L.mesh);
     return hipGetLastError();
 }
 
 template <int P, int VEC>
 static hipError_t fixed_periodic(const UpdateLaunch &L, hipStream_t stream) {
+    if (L.mesh.neighbors) return (L.flags & kPeriodic) ? hipErrorInvalidValue : launch_fixed<P, VEC, false, true>(L, stream);
     return (L.flags & kPeriodic) ? launch_fixed<P, VEC, true>(L, stream) : launch_fixed<P, VEC, false>(L, stream);
 }
 

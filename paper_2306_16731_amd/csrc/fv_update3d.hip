@@ -136,13 +136,18 @@ __device__ __forceinline__ void burst(double *__restrict__ out, const double *ri
     }
 }
 
-template <int P, int VEC, bool PERIODIC>
+// MESH: the face halos come from the neighbouring patches' interiors (a
+// patch without a neighbour on a face keeps reading its own halo there), and
+// patch t advances by dt[t] / h[t]; the output is the interior only.
+template <int P, int VEC, bool PERIODIC, bool MESH = false>
 __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, double *__restrict__ out,
                                               const int64_t *__restrict__ offsets,
                                               const int64_t *__restrict__ out_offsets,
                                               const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
                                               int64_t stride, double r, double gamma,
-                                              double *__restrict__ lambda_out, double *ring) {
+                                              double *__restrict__ lambda_out, double *ring,
+                                              MeshArgs mesh = MeshArgs{}) {
+    static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
     using S = Shape3<P>;
     constexpr int NQ = 5;
     constexpr int W = S::W, H = S::H, LP = S::LP, ppw = S::ppw, PLANE = S::PLANE, PF = S::PF, R = S::R;
@@ -162,6 +167,45 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
     const int64_t off = offsets ? offsets[self] : self * stride;
     const int64_t off_out = out_offsets ? out_offsets[self] : off;
     const double *src = in + off + (int64_t)(j * W + i0) * NQ;
+    // Mesh form: volume v of layer k is read at vbase[v][0] (k = 0), vbase[v][1] + k PLANE
+    // (k = 1 .. p) or vbase[v][2] (k = p + 1): its own, or a neighbour's volume.
+    const double *vbase[2][3];
+    double ratio = r;  // dt / h of the lane's patch
+    if constexpr (MESH) {
+        const int32_t *nb = mesh.neighbors + 6 * self;
+        auto base = [&](int32_t q) { return in + (offsets ? offsets[q >= 0 ? q : self] : (q >= 0 ? q : self) * stride); };
+        const double *b[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) b[f] = base(nb[f]);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int i = i0 + v;
+            const bool xi = i >= 1 && i <= P;
+            const double *own = in + off + (int64_t)(j * W + i) * NQ;
+            const double *mid = own;
+            if (i == 0 && yin && nb[0] >= 0) mid = b[0] + (int64_t)(j * W + P) * NQ;
+            if (i == W - 1 && yin && nb[1] >= 0) mid = b[1] + (int64_t)(j * W + 1) * NQ;
+            if (j == 0 && xi && nb[2] >= 0) mid = b[2] + (int64_t)(P * W + i) * NQ;
+            if (j == W - 1 && xi && nb[3] >= 0) mid = b[3] + (int64_t)(W + i) * NQ;
+            vbase[v][1] = mid;
+            vbase[v][0] = (xi && yin && nb[4] >= 0) ? b[4] + (int64_t)P * PLANE + (int64_t)(j * W + i) * NQ : own;
+            vbase[v][2] = (xi && yin && nb[5] >= 0) ? b[5] + (int64_t)PLANE + (int64_t)(j * W + i) * NQ
+                                                     : own + (int64_t)(W - 1) * PLANE;
+        }
+        ratio = mesh.dt[self] / mesh.h[self];
+    }
+    auto load_layer = [&](int k, double (&q)[2][NQ]) {
+        if constexpr (MESH) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                load_volume<NQ>(k == 0 ? vbase[v][0] : (k == W - 1 ? vbase[v][2] : vbase[v][1] + (int64_t)k * PLANE),
+                                q[v]);
+        } else {
+            const double *p = src + (int64_t)k * PLANE;
+            if constexpr (VEC == 2) load_pair16<NQ>(p, q);
+            else load_pair<NQ>(p, q);
+        }
+    };
     const int below = lane >= H ? lane - H : lane;    // row j - 1 of the same patch (j >= 1)
     const int above = lane + H < 64 ? lane + H : lane;  // row j + 1
 
@@ -184,9 +228,7 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
     double qbuf[PF][2][NQ];
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
-        const double *p = src + (int64_t)(t < W ? t : W - 1) * PLANE;
-        if constexpr (VEC == 2) load_pair16<NQ>(p, qbuf[t]);
-        else load_pair<NQ>(p, qbuf[t]);
+        load_layer(t < W ? t : W - 1, qbuf[t]);
     }
 
 #pragma unroll
@@ -197,9 +239,7 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
 #pragma unroll
             for (int c = 0; c < NQ; ++c) q[v][c] = qbuf[k % PF][v][c];
         {
-            const double *p = src + (int64_t)(k + PF < W ? k + PF : W - 1) * PLANE;
-            if constexpr (VEC == 2) load_pair16<NQ>(p, qbuf[k % PF]);
-            else load_pair<NQ>(p, qbuf[k % PF]);
+            load_layer(k + PF < W ? k + PF : W - 1, qbuf[k % PF]);
         }
 
         // Phases in this order keep few values alive at once: the primitives,
@@ -226,7 +266,7 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
                     double dsum[NQ], qn[NQ];
 #pragma unroll
                     for (int c = 0; c < NQ; ++c) dsum[c] = dprev[v][c] + (fhzprev[v][c] - fhz[v][c]);
-                    advance<NQ>(qprev[v], dsum, r, qn);
+                    advance<NQ>(qprev[v], dsum, ratio, qn);
                     const int i = i0 + v;
 #pragma unroll
                     for (int c = 0; c < NQ; ++c) lay[(j * W + i) * NQ + c] = qn[c];
@@ -354,35 +394,39 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
     }
 }
 
-template <int P, int VEC, bool PERIODIC>
+template <int P, int VEC, bool PERIODIC, bool MESH>
 __global__ void __launch_bounds__(kBlock3)
 update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
                       int64_t stride, double r, const double *__restrict__ r_dev, double gamma,
-                      double *__restrict__ lambda_out) {
+                      double *__restrict__ lambda_out, MeshArgs mesh) {
     extern __shared__ double lds[];
     const int64_t item0 = (int64_t)blockIdx.x * Shape3<P>::ppw;
     if (item0 >= num_items) return;
     const double rr = r_dev ? *r_dev : r;
-    wave_update3d<P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
-                                    lambda_out, lds);
+    wave_update3d<P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
+                                          lambda_out, lds, mesh);
 }
 
-template <int P, int VEC, bool PERIODIC>
+template <int P, int VEC, bool PERIODIC, bool MESH = false>
 hipError_t launch3d(const UpdateLaunch &L, hipStream_t stream) {
     using S = Shape3<P>;
     const int64_t blocks = ((int64_t)L.num_items + S::ppw - 1) / S::ppw;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(double) * (size_t)S::ring_words;
-    hipLaunchKernelGGL((update3d_fixed_kernel<P, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(kBlock3), lds, stream,
-                       L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev, L.gamma,
-                       L.lambda_out);
+    hipLaunchKernelGGL((update3d_fixed_kernel<P, VEC, PERIODIC, MESH>), dim3((unsigned)blocks), dim3(kBlock3), lds,
+                       stream, L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev,
+                       L.gamma, L.lambda_out, L.mesh);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch3d_p(const UpdateLaunch &L, hipStream_t stream) {
     const bool periodic = (L.flags & kPeriodic3) != 0;
+    if (L.mesh.neighbors) {
+        if (periodic) return hipErrorInvalidValue;
+        return L.vec2 ? launch3d<P, 2, false, true>(L, stream) : launch3d<P, 1, false, true>(L, stream);
+    }
     if (L.vec2) return periodic ? launch3d<P, 2, true>(L, stream) : launch3d<P, 2, false>(L, stream);
     return periodic ? launch3d<P, 1, true>(L, stream) : launch3d<P, 1, false>(L, stream);
 }

@@ -37,7 +37,8 @@ FV_MAX_P_3D = 24
 EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_create", "fv_plan_execute",
            "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_server_create",
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
-           "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_status_string",
+           "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_mesh_create",
+           "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_status_string",
            "fv_last_error", "fv_version"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
@@ -150,6 +151,13 @@ def load(path: str = LIBRARY):
     lib.fv_server_destroy.argtypes = [vp]
     for name in ("fv_server_create", "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain",
                  "fv_server_run_trace", "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.fv_mesh_create.argtypes = [pp, vp, vp, vp, i32, i32, i32]
+    lib.fv_mesh_halo_fill.argtypes = [vp, vp, vp]
+    lib.fv_mesh_step.argtypes = [vp, vp, vp, vp, vp, f64, vp, vp]
+    lib.fv_local_dt.argtypes = [vp, vp, i32, i32, f64, vp, vp]
+    lib.fv_mesh_destroy.argtypes = [vp]
+    for name in ("fv_mesh_create", "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -285,6 +293,47 @@ def fv_plan_info(plan) -> dict:
 
 def fv_plan_destroy(plan) -> int:
     return _check(load().fv_plan_destroy(plan))
+
+
+# ---------------------------------------------------------------- patch meshes (halo fill, local time stepping)
+def fv_mesh_create(sizes, offsets, neighbors, num_patches: int, dim: int, unknowns: int,
+                   raise_on_error: bool = True):
+    """Build a mesh (neighbors: host [num_patches, 2*dim]); returns its handle, or
+    (status, None) when raise_on_error is False."""
+    lib = load()
+    h = ctypes.c_void_p()
+    sz, sz_p = _host_array(sizes, np.int32)
+    of, of_p = _host_array(offsets, np.int64)
+    nb, nb_p = _host_array(neighbors, np.int32)
+    st = lib.fv_mesh_create(ctypes.byref(h), sz_p, of_p, nb_p, int(num_patches), int(dim), int(unknowns))
+    del sz, of, nb
+    if raise_on_error:
+        _check(st)
+        return h.value
+    return st, h.value
+
+
+def fv_mesh_halo_fill(mesh, patches, stream=None, raise_on_error: bool = True) -> int:
+    st = load().fv_mesh_halo_fill(mesh, _dev_ptr(patches), _stream_handle(stream))
+    return _check(st) if raise_on_error else st
+
+
+def fv_mesh_step(mesh, patches_in, patches_out, dt, h, gamma: float = 1.4, lambda_out=None, stream=None,
+                 raise_on_error: bool = True) -> int:
+    st = load().fv_mesh_step(mesh, _dev_ptr(patches_in), _dev_ptr(patches_out), _dev_ptr(dt), _dev_ptr(h),
+                             float(gamma), _dev_ptr(lambda_out), _stream_handle(stream))
+    return _check(st) if raise_on_error else st
+
+
+def fv_local_dt(lam, h, num_patches: int, dim: int, cfl: float, dt_out, stream=None,
+                raise_on_error: bool = True) -> int:
+    st = load().fv_local_dt(_dev_ptr(lam), _dev_ptr(h), int(num_patches), int(dim), float(cfl), _dev_ptr(dt_out),
+                            _stream_handle(stream))
+    return _check(st) if raise_on_error else st
+
+
+def fv_mesh_destroy(mesh) -> int:
+    return _check(load().fv_mesh_destroy(mesh))
 
 
 # ---------------------------------------------------------------- servers (serving form)

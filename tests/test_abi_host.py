@@ -193,3 +193,39 @@ def test_tuning_table_on_host():
             F.fv_set_tuning(2, 5, p, None)
         for p in F.FIXED_SIZES_3D:
             F.fv_set_tuning(3, 5, p, None)
+
+
+def test_mesh_validation_before_device():
+    """Mesh creation and the mesh calls reject bad arguments before any device work."""
+    nb_ok = [[-1, -1, -1, -1]] * 2
+    bad = [
+        (dict(sizes=[4, 4], offsets=None, neighbors=nb_ok, num_patches=2, dim=4, unknowns=5), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=None, neighbors=nb_ok, num_patches=0, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=None, neighbors=None, num_patches=2, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 5], offsets=[0, 1000], neighbors=nb_ok, num_patches=2, dim=2, unknowns=5),
+         F.FV_ERR_UNSUPPORTED),
+        (dict(sizes=[4, 4], offsets=None, neighbors=[[2, -1, -1, -1], [-1] * 4], num_patches=2, dim=2, unknowns=5),
+         F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=None, neighbors=[[-2, -1, -1, -1], [-1] * 4], num_patches=2, dim=2, unknowns=5),
+         F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=[0, 10], neighbors=nb_ok, num_patches=2, dim=2, unknowns=5), F.FV_ERR_OVERLAP),
+    ]
+    for kw, status in bad:
+        st, h = F.fv_mesh_create(raise_on_error=False, **kw)
+        assert st == status and not h, (kw, st, F.fv_last_error())
+    lib = F.load()
+    assert lib.fv_mesh_halo_fill(None, IN, None) == F.FV_ERR_INVALID_ARG
+    assert lib.fv_mesh_step(None, IN, OUT, LAM, LAM, 1.4, None, None) == F.FV_ERR_INVALID_ARG
+    assert F.fv_mesh_destroy(None) == F.FV_OK
+    assert lib.fv_local_dt(LAM, LAM, 0, 2, 0.4, OUT, None) == F.FV_OK
+    assert lib.fv_local_dt(LAM, LAM, 4, 5, 0.4, OUT, None) == F.FV_ERR_INVALID_ARG
+    assert lib.fv_local_dt(LAM, LAM, 4, 2, 0.0, OUT, None) == F.FV_ERR_INVALID_ARG
+    assert lib.fv_local_dt(None, LAM, 4, 2, 0.4, OUT, None) == F.FV_ERR_INVALID_ARG
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    st, h = F.fv_mesh_create([4, 4], None, nb_ok, 2, 2, 5, raise_on_error=False)
+    assert st == F.FV_ERR_NO_DEVICE and not h
