@@ -90,7 +90,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patches", type=int, default=4096,
                     help="patches the CPU oracle advances through all warmup + timed steps")
-    ap.add_argument("--form", choices=["plain", "batching", "serving"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh"], default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
                          "plans and captured graphs (one line each).  serving: the request loop (config 5)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
@@ -115,6 +115,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.form == "mesh":
+        return bench_mesh(args)
     if args.form == "batching":
         return bench_batching(args)
     if args.form == "serving":
@@ -270,6 +272,87 @@ def _timed(fn, steps: int) -> float:
         fn()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def bench_mesh(args) -> int:
+    """Patch meshes with face halos from neighbours and local time stepping: the fused mesh
+    step (fv_mesh_step: halos read from the neighbours in the kernel, per-patch dt / h) with
+    per-patch step sizes formed on the device (fv_local_dt) after every step, against a
+    separate halo fill followed by the plain launch (global dt) on the same mesh."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    steps, gamma = args.steps, wl.GAMMA
+    for n, p, dim in ((256, 16, 2), (32, 8, 3)):
+        m = wl.make_mesh(n, p, dim=dim, seed=args.seed, periodic=True)
+        b = m.batch
+        T, nq = b.num_patches, b.nq
+        cells = T * p ** dim
+        h = m.h
+        a = torch.from_numpy(b.data).to("cuda")
+        c = a.clone()
+        lam = torch.empty(T, dtype=torch.float64, device="cuda")
+        hv = torch.full((T,), h, dtype=torch.float64, device="cuda")
+        mesh = fvpatch.fv_mesh_create(b.sizes, None, m.neighbors, T, dim, nq)
+        try:
+            # initial per-patch dt from the initial state's eigenvalues
+            fvpatch.fv_mesh_step(mesh, a, c, torch.full((T,), 1e-9, dtype=torch.float64, device="cuda"), hv, gamma,
+                                 lam)
+            dt = torch.empty_like(lam)
+            fvpatch.fv_local_dt(lam, hv, T, dim, wl.CFL, dt)
+            dt0 = dt.clone()
+
+            def fused_step(x, y):
+                fvpatch.fv_mesh_step(mesh, x, y, dt, hv, gamma, lam)
+                fvpatch.fv_local_dt(lam, hv, T, dim, wl.CFL, dt)
+
+            dtg = float(dt0.min().item())
+
+            def unfused_step(x, y):
+                fvpatch.fv_mesh_halo_fill(mesh, x)
+                fvpatch.fv_patch_batch_update(x, y, b.sizes, None, T, dim, nq, dtg, h, gamma, 0, lam)
+
+            res = {}
+            for name, fn in (("fused", fused_step), ("fill+plain", unfused_step)):
+                bufs = [a, c]
+                for _ in range(args.warmup):
+                    fn(bufs[0], bufs[1])
+                    bufs.reverse()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(steps):
+                    fn(bufs[0], bufs[1])
+                    bufs.reverse()
+                e1.record()
+                torch.cuda.synchronize()
+                res[name] = e0.elapsed_time(e1) / steps
+            dt_spread = (float(dt.min().item()), float(dt.max().item()))
+        finally:
+            fvpatch.fv_mesh_destroy(mesh)
+        # the method's bytes: face-halo-padded input (halos are neighbours' interiors), interior output,
+        # lambda, and the per-patch dt and h read / dt written
+        alg = T * (((p ** dim + 2 * dim * p ** (dim - 1)) + p ** dim) * nq * 8 + 8 + 24)
+        ms = res["fused"]
+        line = {"metric": "cell-updates/s", "form": "mesh", "value": round(cells / (ms / 1e3), 1),
+                "unit": "cell-updates/s", "ms_per_step": round(ms, 5), "alg_GBs": round(alg / (ms / 1e3) / 1e9, 1),
+                "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "fill_plus_plain_ms_per_step": round(res["fill+plain"], 5),
+                "speedup_vs_fill_plus_plain": round(res["fill+plain"] / ms, 3),
+                "local_dt_range": [round(v, 8) for v in dt_spread],
+                "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"{dim}D mesh {n}^{dim} x {p}^{dim}", "patches": T, "order": "Morton",
+                           "halos": "face neighbours (periodic domain)", "time_stepping": "local (per-patch dt)",
+                           "steps": steps},
+                "timing": "HIP events around the timed steps (mesh step + per-patch dt)"}
+        print(json.dumps(line), flush=True)
+        del a, c
+        torch.cuda.empty_cache()
+    return 0
 
 
 def bench_batching(args) -> int:
