@@ -357,6 +357,36 @@ fv_status fv_local_dt(const double *lambda, const double *h, int32_t num_patches
 /* Wait for the device, then free the mesh's device tables (NULL: no-op). */
 fv_status fv_mesh_destroy(fv_mesh *mesh);
 
+/* ------------------------------------------------------------------------
+ * The paper's three kernel realisations (Sec. 3) as comparison variants of
+ * the fused update: the same step, the same microkernels in the same order
+ * per volume (results equal to fv_patch_batch_update's bit for bit), mapped
+ * differently onto the GPU:
+ *   FV_FLAVOUR_BATCHED     one launch per algorithmic step over all volumes
+ *                          of all patches (user terms, face fluxes, update,
+ *                          eigenvalue reduction) with HBM temporaries;
+ *   FV_FLAVOUR_PATCH_WISE  one work-group per patch, the steps in sequence
+ *                          inside it with a barrier between them;
+ *   FV_FLAVOUR_TASK_GRAPH  one hipGraph per call with a node per (patch,
+ *                          microkernel): d independent face-flux nodes and
+ *                          an update node per patch, assembled and
+ *                          instantiated on the host every call.
+ * Arguments as fv_patch_batch_update; additionally FV_ERR_UNSUPPORTED
+ * unless all patches have one size with at most 512 interior volumes and
+ * unknowns = 5.  The batched and task-graph forms keep temporaries in a
+ * grow-only device workspace owned by the library (one per device, kept
+ * until the process ends, shared by all calls on that device: calls on
+ * different streams must not overlap).  With offsets the call waits for its
+ * stream once (offset upload).
+ * ------------------------------------------------------------------------ */
+#define FV_FLAVOUR_BATCHED 1
+#define FV_FLAVOUR_PATCH_WISE 2
+#define FV_FLAVOUR_TASK_GRAPH 3
+
+fv_status fv_flavour_update(int32_t flavour, const double *patches_in, double *patches_out, const int32_t *sizes,
+                            const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t unknowns, double dt,
+                            double h, double gamma, uint32_t flags, double *lambda_out, void *stream);
+
 /* Text for a status code (static storage). */
 const char *fv_status_string(fv_status status);
 

@@ -38,7 +38,8 @@ EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_c
            "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_server_create",
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
            "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_mesh_create",
-           "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_status_string",
+           "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_flavour_update",
+           "fv_status_string",
            "fv_last_error", "fv_version"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
@@ -48,6 +49,9 @@ FV_KERNEL_BLOCK = 1
 FV_KERNEL_WAVE = 2
 FV_KERNEL_TILE = 3
 FV_KERNEL_FIXED = 4
+FV_FLAVOUR_BATCHED = 1
+FV_FLAVOUR_PATCH_WISE = 2
+FV_FLAVOUR_TASK_GRAPH = 3
 FIXED_SIZES_2D = (3, 5, 9, 16, 17)  # patch sizes with a fixed-size build (2D, unknowns = 5)
 FIXED_SIZES_3D = (4, 6, 8)          # the same in 3D
 
@@ -159,6 +163,8 @@ def load(path: str = LIBRARY):
     lib.fv_mesh_destroy.argtypes = [vp]
     for name in ("fv_mesh_create", "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.fv_flavour_update.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp, vp]
+    lib.fv_flavour_update.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -334,6 +340,19 @@ def fv_local_dt(lam, h, num_patches: int, dim: int, cfl: float, dt_out, stream=N
 
 def fv_mesh_destroy(mesh) -> int:
     return _check(load().fv_mesh_destroy(mesh))
+
+
+# ---------------------------------------------------------------- the paper's realisations (comparison)
+def fv_flavour_update(flavour: int, patches_in, patches_out, sizes, offsets, num_patches: int, dim: int,
+                      unknowns: int, dt: float, h: float, gamma: float = 1.4, flags: int = 0, lambda_out=None,
+                      stream=None, raise_on_error: bool = True) -> int:
+    sz, sz_p = _host_array(sizes, np.int32)
+    of, of_p = _host_array(offsets, np.int64)
+    st = load().fv_flavour_update(int(flavour), _dev_ptr(patches_in), _dev_ptr(patches_out), sz_p, of_p,
+                                  int(num_patches), int(dim), int(unknowns), float(dt), float(h), float(gamma),
+                                  int(flags), _dev_ptr(lambda_out), _stream_handle(stream))
+    del sz, of
+    return _check(st) if raise_on_error else st
 
 
 # ---------------------------------------------------------------- servers (serving form)

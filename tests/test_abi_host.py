@@ -229,3 +229,29 @@ def test_mesh_validation_before_device():
         pass
     st, h = F.fv_mesh_create([4, 4], None, nb_ok, 2, 2, 5, raise_on_error=False)
     assert st == F.FV_ERR_NO_DEVICE and not h
+
+
+def test_flavour_validation_before_device():
+    kw = dict(patches_in=IN, patches_out=OUT, sizes=[4] * 3, offsets=None, num_patches=3, dim=2, unknowns=5,
+              dt=1e-3, h=1 / 48, gamma=1.4, flags=0, lambda_out=LAM, stream=0)
+
+    def call(flavour, **over):
+        a = dict(kw)
+        a.update(over)
+        return F.fv_flavour_update(flavour, raise_on_error=False, **a)
+
+    assert call(0) == F.FV_ERR_INVALID_ARG
+    assert call(4) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_FLAVOUR_BATCHED, unknowns=4) == F.FV_ERR_UNSUPPORTED
+    assert call(F.FV_FLAVOUR_BATCHED, sizes=[4, 5, 4], offsets=[0, 200, 500]) == F.FV_ERR_UNSUPPORTED
+    assert call(F.FV_FLAVOUR_PATCH_WISE, dim=3, sizes=[9] * 3) == F.FV_ERR_UNSUPPORTED   # 729 interior volumes
+    assert call(F.FV_FLAVOUR_TASK_GRAPH, dt=-1.0) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_FLAVOUR_TASK_GRAPH, patches_out=IN) == F.FV_ERR_OVERLAP
+    assert call(F.FV_FLAVOUR_BATCHED, num_patches=0, sizes=None, patches_in=0, patches_out=0) == F.FV_OK
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    assert call(F.FV_FLAVOUR_BATCHED) == F.FV_ERR_NO_DEVICE
