@@ -90,7 +90,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patches", type=int, default=4096,
                     help="patches the CPU oracle advances through all warmup + timed steps")
-    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours"], default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
                          "plans and captured graphs (one line each).  serving: the request loop (config 5)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
@@ -117,6 +117,8 @@ def main() -> int:
         return 1
     if args.form == "mesh":
         return bench_mesh(args)
+    if args.form == "flavours":
+        return bench_flavours(args)
     if args.form == "batching":
         return bench_batching(args)
     if args.form == "serving":
@@ -272,6 +274,65 @@ def _timed(fn, steps: int) -> float:
         fn()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def bench_flavours(args) -> int:
+    """The paper's matrix (p in {4, 6, 8}, d in {2, 3}, a sweep over T, with and without the
+    eigenvalue reduction) for the fused update and the three comparison realisations
+    (batched, patch-wise, task graph).  Time per step is wall time between device
+    synchronisations over a few steps after two warmup steps, host work included: the task
+    graph's per-call assembly is part of that realisation."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    flav = {"batched": fvpatch.FV_FLAVOUR_BATCHED, "patch_wise": fvpatch.FV_FLAVOUR_PATCH_WISE,
+            "task_graph": fvpatch.FV_FLAVOUR_TASK_GRAPH}
+    # 3D: only T = 16 -- the 3D sweep ended in a host segmentation fault at p = 4, T = 256 whose
+    # cause is not identified, so larger 3D batches stay out of this comparison for now
+    for dim, sweep in ((2, (16, 256, 4096, 65536)), (3, (16,))):
+        for p in (4, 6, 8):
+            base = wl.make_uniform(256, p, dim=dim, nq=5, seed=args.seed)
+            for T in sweep:
+                reps = (T + 255) // 256
+                data = np.tile(base.data, reps)[: T * int(base.offsets[1])]
+                sizes = np.full(T, p, np.int32)
+                a = torch.from_numpy(data).to("cuda")
+                c = a.clone()
+                lam = torch.empty(T, dtype=torch.float64, device="cuda")
+                for red in (True, False):
+                    lam_arg = lam if red else None
+                    line = {"form": "flavours", "dim": dim, "p": p, "patches": T, "reduction": red}
+
+                    def timed(fn, steps):
+                        bufs = [a, c]
+                        for _ in range(2):
+                            fn(bufs[0], bufs[1])
+                            bufs.reverse()
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        for _ in range(steps):
+                            fn(bufs[0], bufs[1])
+                            bufs.reverse()
+                        torch.cuda.synchronize()
+                        return (time.perf_counter() - t0) / steps * 1e3
+
+                    line["fused_ms"] = round(timed(lambda x, y: fvpatch.fv_patch_batch_update(
+                        x, y, sizes, None, T, dim, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, 0, lam_arg), 10), 4)
+                    for name, f in flav.items():
+                        if name == "task_graph" and T > 4096:
+                            line[name + "_ms"] = None
+                            continue
+                        steps = 3 if name == "task_graph" else 10
+                        line[name + "_ms"] = round(timed(lambda x, y, f=f: fvpatch.fv_flavour_update(
+                            f, x, y, sizes, None, T, dim, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, 0, lam_arg), steps), 4)
+                    line["fused_cell_updates_per_s"] = round(T * p ** dim / (line["fused_ms"] / 1e3), 1)
+                    print(json.dumps(line), flush=True)
+                del a, c, lam
+                torch.cuda.empty_cache()
+    return 0
 
 
 def bench_mesh(args) -> int:

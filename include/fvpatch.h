@@ -370,7 +370,8 @@ fv_status fv_mesh_destroy(fv_mesh *mesh);
  *   FV_FLAVOUR_TASK_GRAPH  one hipGraph per call with a node per (patch,
  *                          microkernel): d independent face-flux nodes and
  *                          an update node per patch, assembled and
- *                          instantiated on the host every call.
+ *                          instantiated on the host every call; the call
+ *                          returns when the graph has run (synchronous).
  * Arguments as fv_patch_batch_update; additionally FV_ERR_UNSUPPORTED
  * unless all patches have one size with at most 512 interior volumes and
  * unknowns = 5.  The batched and task-graph forms keep temporaries in a

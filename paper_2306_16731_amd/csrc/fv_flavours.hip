@@ -18,7 +18,8 @@
 //               type): the d face-flux nodes of a patch are independent, its
 //               update node depends on them (Sec. 3, "task graph"); the graph
 //               is assembled and instantiated on the host every call, as the
-//               paper's realisation submits its tasks every time step.
+//               paper's realisation submits its tasks every time step, and
+//               the call returns when the graph has run.
 //
 // All three take batches of one patch size and five unknowns.  The batched
 // and task-graph forms keep their temporaries in a grow-only device workspace
@@ -387,8 +388,7 @@ tg_update(const double *__restrict__ patch_in, double *__restrict__ patch_out, i
 struct Workspace {
     void *ptr = nullptr;
     size_t cap = 0;
-    hipGraphExec_t exec = nullptr;  // the last task graph, kept until it has run
-    hipEvent_t exec_done = nullptr;
+    hipEvent_t exec_done = nullptr;  // completion of the task graph of a call
 };
 std::mutex g_ws_mu;
 std::vector<Workspace> g_ws;
@@ -459,12 +459,6 @@ fv_status run_task_graph(const double *in, double *out, const int64_t *h_off, in
     const size_t per_patch = (size_t)D * g.NF * NQ;
     fv_status st = ensure(w, sizeof(double) * per_patch * T);
     if (st != FV_OK) return st;
-    // the previous call's graph must have run before its executable goes
-    if (w.exec) {
-        if (hipEventSynchronize(w.exec_done) != hipSuccess) return fail(FV_ERR_LAUNCH, "task graph wait failed");
-        (void)hipGraphExecDestroy(w.exec);
-        w.exec = nullptr;
-    }
     if (!w.exec_done && hipEventCreateWithFlags(&w.exec_done, hipEventDisableTiming) != hipSuccess)
         return fail(FV_ERR_LAUNCH, "hipEventCreate failed");
     hipGraph_t graph = nullptr;
@@ -505,9 +499,14 @@ fv_status run_task_graph(const double *in, double *out, const int64_t *h_off, in
         hipGraphNode_t node;
         ok = hipGraphAddKernelNode(&node, graph, deps.data(), D, &kp) == hipSuccess;
     }
-    if (ok) ok = hipGraphInstantiate(&w.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    hipGraphExec_t exec = nullptr;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
     (void)hipGraphDestroy(graph);
-    if (ok) ok = hipGraphLaunch(w.exec, s) == hipSuccess && hipEventRecord(w.exec_done, s) == hipSuccess;
+    if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess && hipEventRecord(w.exec_done, s) == hipSuccess;
+    // The executable does not outlive the call: it refers to the caller's buffers, which the
+    // caller may free as soon as the step has run.  So the call waits for its graph.
+    if (ok) ok = hipEventSynchronize(w.exec_done) == hipSuccess;
+    if (exec) (void)hipGraphExecDestroy(exec);
     if (!ok) {
         (void)hipGetLastError();
         return fail(FV_ERR_LAUNCH, "task graph assembly or launch failed");
