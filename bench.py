@@ -90,7 +90,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patches", type=int, default=4096,
                     help="patches the CPU oracle advances through all warmup + timed steps")
-    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer"], default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
                          "plans and captured graphs (one line each).  serving: the request loop (config 5)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
@@ -119,6 +119,8 @@ def main() -> int:
         return bench_mesh(args)
     if args.form == "flavours":
         return bench_flavours(args)
+    if args.form == "transfer":
+        return bench_transfer(args)
     if args.form == "batching":
         return bench_batching(args)
     if args.form == "serving":
@@ -333,6 +335,130 @@ def bench_flavours(args) -> int:
                 del a, c, lam
                 torch.cuda.empty_cache()
     return 0
+
+
+def bench_transfer(args) -> int:
+    """Patches scattered in host memory (one allocation per patch, as on a mesh code's CPU
+    heap) through one step on the GPU and back: per-patch synchronous copies into recycled
+    device memory, the pipelined form (host threads each carrying chunks through gather into
+    pinned staging, async copies, update, copy back and scatter, overlapped), and the staged
+    form (threaded gather of the whole batch, one copy each way, no overlap); against the
+    device-resident step (no transfers) and the
+    copy engines' own ceiling (pinned host <-> device copies of the same bytes, each
+    direction alone and both at once).  Wall time per step between synchronisations."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    gamma, h, dt = wl.GAMMA, wl.H_DEFAULT, 1e-3
+    for name in ("c2_2d_p16_T65536", "c4_3d_p8_T32768"):
+        b, spec = wl.build_workload(name, seed=args.seed)
+        T, p, dim, nq = b.num_patches, int(b.sizes[0]), b.dim, b.nq
+        cells = T * p ** dim
+        nbytes = b.data.nbytes
+        src = wl.scatter_to_host(b, seed=args.seed)
+        dst = [np.empty_like(a) for a in src]
+        tin, tout = fvpatch.host_pointer_table(src), fvpatch.host_pointer_table(dst)
+        lam = np.empty(T)
+
+        def host_step(cfg, stats=None):
+            fvpatch.fv_host_patches_update(tin, tout, b.sizes, T, dim, nq, dt, h, gamma, 0, lam, config=cfg,
+                                           stats=stats)
+
+        def wall(fn, warm, steps):
+            """Median milliseconds of `steps` timed calls after `warm` untimed ones (each call
+            is synchronous; the host's memory system makes single calls vary by ~10%)."""
+            for _ in range(warm):
+                fn()
+            ts = []
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                fn()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return float(np.median(ts))
+
+        res = {}
+        # device-resident: the same step on patches already in HBM
+        a = torch.from_numpy(b.data).to("cuda")
+        c = a.clone()
+        dlam = torch.empty(T, dtype=torch.float64, device="cuda")
+        res["resident_ms"] = _timed_ms(lambda: fvpatch.fv_patch_batch_update(
+            a, c, b.sizes, None, T, dim, nq, dt, h, gamma, 0, dlam), 10, 20)
+        # copy-engine ceiling with pinned host memory
+        hp_in = torch.empty(nbytes // 8, dtype=torch.float64, pin_memory=True)
+        hp_out = torch.empty(nbytes // 8, dtype=torch.float64, pin_memory=True)
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+        def h2d():
+            a.copy_(hp_in, non_blocking=True)
+
+        def d2h():
+            hp_out.copy_(c, non_blocking=True)
+
+        def both():
+            with torch.cuda.stream(s1):
+                a.copy_(hp_in, non_blocking=True)
+            with torch.cuda.stream(s2):
+                hp_out.copy_(c, non_blocking=True)
+            s1.synchronize()
+            s2.synchronize()
+
+        res["pinned_h2d_GBs"] = round(nbytes / _timed_ms(h2d, 2, 5) / 1e6, 2)
+        res["pinned_d2h_GBs"] = round(nbytes / _timed_ms(d2h, 2, 5) / 1e6, 2)
+        res["pinned_both_GBs"] = round(2 * nbytes / _timed_ms(both, 2, 5) / 1e6, 2)
+        del hp_in, hp_out, a, c, dlam
+        torch.cuda.empty_cache()
+        # pipelined, defaults and a small sweep; staged without overlap; per patch
+        stats = {}
+        res["pipelined_ms"] = wall(lambda: host_step(None, stats), 3, 11)
+        res["pipelined_host_copy_ms"] = stats["host_copy_seconds"] * 1e3
+        sweep = []
+        for chunk_mb, slots, threads in ((2, 2, 8), (4, 2, 8), (16, 2, 8), (32, 2, 8), (8, 1, 8), (8, 3, 8),
+                                         (8, 2, 4), (8, 2, 12), (8, 2, 16)):
+            cfg = {"chunk_bytes": chunk_mb << 20, "slots": slots, "host_threads": threads}
+            sweep.append({"chunk_MiB": chunk_mb, "slots": slots, "host_threads": threads,
+                          "ms": round(wall(lambda cfg=cfg: host_step(cfg), 1, 5), 3)})
+        res["staged_no_overlap_ms"] = wall(lambda: host_step({"mode": fvpatch.FV_TRANSFER_STAGED}), 2, 7)
+        pp_T = min(T, 8192)
+
+        def per_patch():
+            fvpatch.fv_host_patches_update(tin, tout, b.sizes, pp_T, dim, nq, dt, h, gamma, 0, lam,
+                                           config={"mode": fvpatch.FV_TRANSFER_PER_PATCH})
+
+        res["per_patch_ms_full_batch"] = wall(per_patch, 1, 2) * T / pp_T
+        moved = 2 * nbytes + 8 * T
+        ms = res["pipelined_ms"]
+        line = {"metric": "cell-updates/s", "form": "transfer", "value": round(cells / (ms / 1e3), 1),
+                "unit": "cell-updates/s", "ms_per_step": round(ms, 3),
+                "transfer_GBs": round(moved / (ms / 1e3) / 1e9, 2),
+                "frac_of_pinned_both": round(moved / (ms / 1e3) / 1e9 / res["pinned_both_GBs"], 3),
+                "resident_ms_per_step": round(res["resident_ms"], 4),
+                "staged_no_overlap_ms_per_step": round(res["staged_no_overlap_ms"], 3),
+                "per_patch_ms_per_step": round(res["per_patch_ms_full_batch"], 1),
+                "per_patch_measured_on": pp_T,
+                "speedup_vs_per_patch": round(res["per_patch_ms_full_batch"] / ms, 2),
+                "speedup_vs_staged": round(res["staged_no_overlap_ms"] / ms, 3),
+                "host_copy_ms": round(res["pipelined_host_copy_ms"], 3),
+                "pinned_h2d_GBs": res["pinned_h2d_GBs"], "pinned_d2h_GBs": res["pinned_d2h_GBs"],
+                "pinned_both_GBs": res["pinned_both_GBs"], "sweep": sweep,
+                "dtype": "f64", "data": "synthetic",
+                "config": {"workload": name, "patches": T, "p": p, "dim": dim,
+                           "host_layout": "one allocation per patch, shuffled allocation order",
+                           "bytes_each_way": nbytes},
+                "timing": "median wall clock of synchronous calls (host gather / scatter and PCIe copies included)"}
+        print(json.dumps(line), flush=True)
+        del src, dst, tin, tout
+    return 0
+
+
+def _timed_ms(fn, warm: int, steps: int) -> float:
+    """Milliseconds per call of fn over `steps` calls after `warm` untimed ones (device synchronised)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    return _timed(fn, steps) / steps * 1e3
 
 
 def bench_mesh(args) -> int:

@@ -388,6 +388,76 @@ fv_status fv_flavour_update(int32_t flavour, const double *patches_in, double *p
                             const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t unknowns, double dt,
                             double h, double gamma, uint32_t flags, double *lambda_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Patches in host memory (Sec. 5, data transfer; Sec. 6, Fig. 4).  In the
+ * paper every patch is a separate allocation on the CPU heap, brought to the
+ * accelerator one by one; those scattered copies dominate its runtime.  This
+ * call takes such patches, moves them through the fused update and writes
+ * the results back to host memory:
+ *   FV_TRANSFER_PER_PATCH  each patch its own synchronous hipMemcpy to and
+ *                          from a recycled device area, one launch over the
+ *                          batch in between (the paper's explicit copy with
+ *                          device allocations kept, not freed);
+ *   FV_TRANSFER_STAGED     host_threads threads gather all patches into one
+ *                          pinned buffer, one copy to the device, one launch,
+ *                          one copy back, threaded scatter (bulk, no overlap);
+ *   FV_TRANSFER_PIPELINED  the batch cut into chunks of whole patches of about
+ *                          chunk_bytes; each of host_threads threads takes
+ *                          chunks in turn and carries each through gather into
+ *                          pinned staging, hipMemcpyAsync to the device, the
+ *                          update, the copy back on the thread's own stream
+ *                          and the scatter, keeping `slots` chunks of its own
+ *                          in flight: gathers, scatters, both copy directions
+ *                          and updates of different chunks overlap.
+ * patches_in / patches_out: host arrays [num_patches] of host pointers, patch
+ * t a padded AoS patch of sizes[t] (all sizes equal) as in
+ * fv_patch_batch_update, in pageable or pinned memory, 8-byte aligned.  The
+ * copies into and out of the staging use streaming stores.  patches_out[t]
+ * receives the whole patch: the new interior, and halo volumes equal to the
+ * input's (FV_HALO_PERIODIC: its face halos wrapped from the new interior).
+ * lambda_out: host [num_patches] or NULL.  dt, h, gamma, flags as in
+ * fv_patch_batch_update; results equal its results bit for bit.
+ * config: NULL = pipelined with the defaults; a 0 field = its default
+ * (chunk_bytes 8 MiB, slots 2, host_threads 8).  Pinned staging and device
+ * buffers are kept per device, grow-only, until the process ends: pipelined
+ * 2 * host_threads * slots chunks of each kind, staged 2 batches of each.
+ * stats: NULL or filled on success (bytes moved each way, wall time of the
+ * call, host thread time spent gathering and scattering, summed over the
+ * threads).  Synchronous: returns when every output is in host memory; the
+ * library's streams are its own, none of the caller's is used; calls on one
+ * device are serialised.
+ * Errors: FV_ERR_INVALID_ARG (scalars, null pointers, config ranges, a chunk
+ * smaller than one patch), FV_ERR_UNSUPPORTED (mixed sizes), FV_ERR_OVERLAP
+ * (an output patch overlaps an input or another output patch),
+ * FV_ERR_NO_DEVICE, FV_ERR_OOM, FV_ERR_LAUNCH (after an error the outputs of
+ * some patches may be unwritten).  num_patches = 0: no-op.
+ * ------------------------------------------------------------------------ */
+#define FV_TRANSFER_PIPELINED 0
+#define FV_TRANSFER_PER_PATCH 1
+#define FV_TRANSFER_STAGED 2
+#define FV_TRANSFER_MAX_SLOTS 8
+#define FV_TRANSFER_MAX_THREADS 64
+
+typedef struct fv_transfer_config {
+    int64_t chunk_bytes;  /* staging chunk (pipelined), >= one patch; 0 = 8 MiB */
+    int32_t slots;        /* chunks in flight per thread (pipelined), 1 .. FV_TRANSFER_MAX_SLOTS; 0 = 2 */
+    int32_t host_threads; /* threads incl. the caller's, 1 .. FV_TRANSFER_MAX_THREADS; 0 = 8 */
+    int32_t mode;         /* FV_TRANSFER_* */
+    int32_t reserved;     /* 0 */
+} fv_transfer_config;
+
+typedef struct fv_transfer_stats {
+    int64_t bytes_to_device;
+    int64_t bytes_to_host;
+    double seconds;           /* wall time of the call */
+    double host_copy_seconds; /* gathering into / scattering from the staging, summed over threads */
+} fv_transfer_stats;
+
+fv_status fv_host_patches_update(const double *const *patches_in, double *const *patches_out, const int32_t *sizes,
+                                 int32_t num_patches, int32_t dim, int32_t unknowns, double dt, double h,
+                                 double gamma, uint32_t flags, double *lambda_out, const fv_transfer_config *config,
+                                 fv_transfer_stats *stats);
+
 /* Text for a status code (static storage). */
 const char *fv_status_string(fv_status status);
 

@@ -39,7 +39,7 @@ EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_c
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
            "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_mesh_create",
            "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_flavour_update",
-           "fv_status_string",
+           "fv_host_patches_update", "fv_status_string",
            "fv_last_error", "fv_version"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
@@ -52,6 +52,11 @@ FV_KERNEL_FIXED = 4
 FV_FLAVOUR_BATCHED = 1
 FV_FLAVOUR_PATCH_WISE = 2
 FV_FLAVOUR_TASK_GRAPH = 3
+FV_TRANSFER_PIPELINED = 0
+FV_TRANSFER_PER_PATCH = 1
+FV_TRANSFER_STAGED = 2
+FV_TRANSFER_MAX_SLOTS = 8
+FV_TRANSFER_MAX_THREADS = 64
 FIXED_SIZES_2D = (3, 5, 9, 16, 17)  # patch sizes with a fixed-size build (2D, unknowns = 5)
 FIXED_SIZES_3D = (4, 6, 8)          # the same in 3D
 
@@ -100,6 +105,19 @@ class fv_server_stats(ctypes.Structure):
     _fields_ = ([(n, ctypes.c_int64) for n in ("submitted", "completed", "queued", "inflight", "peak_queued",
                                                "peak_inflight", "cells_updated", "resident_bytes", "budget_bytes")]
                 + [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "cell_updates_per_s")])
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class fv_transfer_config(ctypes.Structure):
+    _fields_ = [("chunk_bytes", ctypes.c_int64), ("slots", ctypes.c_int32), ("host_threads", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class fv_transfer_stats(ctypes.Structure):
+    _fields_ = [("bytes_to_device", ctypes.c_int64), ("bytes_to_host", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("host_copy_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -165,6 +183,9 @@ def load(path: str = LIBRARY):
         getattr(lib, name).restype = ctypes.c_int
     lib.fv_flavour_update.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp, vp]
     lib.fv_flavour_update.restype = ctypes.c_int
+    lib.fv_host_patches_update.argtypes = [vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp,
+                                           ctypes.POINTER(fv_transfer_config), ctypes.POINTER(fv_transfer_stats)]
+    lib.fv_host_patches_update.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -352,6 +373,54 @@ def fv_flavour_update(flavour: int, patches_in, patches_out, sizes, offsets, num
                                   int(num_patches), int(dim), int(unknowns), float(dt), float(h), float(gamma),
                                   int(flags), _dev_ptr(lambda_out), _stream_handle(stream))
     del sz, of
+    return _check(st) if raise_on_error else st
+
+
+# ---------------------------------------------------------------- patches in host memory
+def host_pointer_table(patches) -> np.ndarray:
+    """Host addresses of a sequence of numpy float64 arrays (C-contiguous), as the
+    pointer table fv_host_patches_update takes; the arrays must outlive its use."""
+    addrs = np.empty(len(patches), np.uintp)
+    for t, a in enumerate(patches):
+        if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise ValueError(f"patch {t} must be a C-contiguous float64 numpy array")
+        addrs[t] = a.ctypes.data
+    return addrs
+
+
+def fv_host_patches_update(patches_in, patches_out, sizes, num_patches: int, dim: int, unknowns: int, dt: float,
+                           h: float, gamma: float = 1.4, flags: int = 0, lambda_out=None, config=None, stats=None,
+                           raise_on_error: bool = True) -> int:
+    """One step of patches held in host memory (see include/fvpatch.h).  patches_in /
+    patches_out: sequences of float64 numpy arrays, or uintp tables of host addresses
+    (host_pointer_table); lambda_out: float64 numpy array or None; config: a dict of
+    fv_transfer_config fields or None; stats: a dict filled with fv_transfer_stats."""
+    def table(x, writable):
+        if isinstance(x, np.ndarray) and x.dtype == np.uintp:
+            return x
+        if writable and any(not a.flags.writeable for a in x):
+            raise ValueError("output patches must be writable")
+        return host_pointer_table(x)
+    tin, tout = table(patches_in, False), table(patches_out, True)
+    if len(tin) < num_patches or len(tout) < num_patches:
+        raise ValueError("fewer patch pointers than num_patches")
+    sz, sz_p = _host_array(sizes, np.int32)
+    lam_p = None
+    if lambda_out is not None:
+        if not isinstance(lambda_out, np.ndarray) or lambda_out.dtype != np.float64 or \
+                not lambda_out.flags.c_contiguous or lambda_out.size < num_patches:
+            raise ValueError("lambda_out must be a contiguous float64 numpy array of num_patches entries")
+        lam_p = lambda_out.ctypes.data
+    cfg = None
+    if config is not None:
+        cfg = fv_transfer_config(**config) if isinstance(config, dict) else config
+    st_out = fv_transfer_stats()
+    st = load().fv_host_patches_update(tin.ctypes.data, tout.ctypes.data, sz_p, int(num_patches), int(dim),
+                                       int(unknowns), float(dt), float(h), float(gamma), int(flags), lam_p,
+                                       ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(st_out))
+    del sz
+    if stats is not None:
+        stats.update(st_out.as_dict())
     return _check(st) if raise_on_error else st
 
 

@@ -237,3 +237,19 @@ def build_workload(name: str, seed: int = 0, num_patches: int | None = None, nq:
     else:
         b = make_mixed(T, spec["choices"], spec["dim"], nq, seed, spec["pulse"])
     return b, spec
+
+
+# ---------------------------------------------------------------- patches scattered in host memory
+def scatter_to_host(batch: Batch, seed: int = 0) -> list:
+    """The batch's patches as separate host arrays (one allocation each, made in a
+    shuffled order so that consecutive patches do not sit side by side), as the
+    patches of a mesh code live on the CPU heap.  Entry t is patch t."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = batch.num_patches
+    order = rng.permutation(T)
+    out = [None] * T
+    for t in order:
+        o = int(batch.offsets[t])
+        n = int((int(batch.sizes[t]) + 2) ** batch.dim * batch.nq)
+        out[t] = batch.data[o:o + n].copy()
+    return out

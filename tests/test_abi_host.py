@@ -255,3 +255,53 @@ def test_flavour_validation_before_device():
     except ImportError:
         pass
     assert call(F.FV_FLAVOUR_BATCHED) == F.FV_ERR_NO_DEVICE
+
+
+def test_host_patches_validation_before_device():
+    """fv_host_patches_update checks its arguments on the host before it touches a device."""
+    p, T = 4, 3
+    n = (p + 2) ** 2 * 5
+    src = [np.zeros(n) for _ in range(T)]
+    dst = [np.zeros(n) for _ in range(T)]
+    lam = np.zeros(T)
+    kw = dict(patches_in=src, patches_out=dst, sizes=[p] * T, num_patches=T, dim=2, unknowns=5, dt=1e-3, h=1 / 48,
+              gamma=1.4, flags=0, lambda_out=lam)
+
+    def call(**over):
+        a = dict(kw)
+        a.update(over)
+        return F.fv_host_patches_update(raise_on_error=False, **a)
+
+    assert call(dt=-1.0) == F.FV_ERR_INVALID_ARG
+    assert call(dim=4) == F.FV_ERR_INVALID_ARG
+    assert call(sizes=[p, p + 1, p]) == F.FV_ERR_UNSUPPORTED
+    assert call(sizes=[0] * T) == F.FV_ERR_INVALID_ARG
+    assert call(config={"mode": 3}) == F.FV_ERR_INVALID_ARG
+    assert call(config={"slots": F.FV_TRANSFER_MAX_SLOTS + 1}) == F.FV_ERR_INVALID_ARG
+    assert call(config={"host_threads": -1}) == F.FV_ERR_INVALID_ARG
+    assert call(config={"chunk_bytes": 8 * n - 8}) == F.FV_ERR_INVALID_ARG   # below one patch
+    assert call(patches_out=[dst[0], src[1], dst[2]]) == F.FV_ERR_OVERLAP     # an output is an input
+    assert call(patches_out=[dst[0], dst[0], dst[2]]) == F.FV_ERR_OVERLAP     # two outputs share an array
+    big = np.zeros(2 * n)
+    half = np.array([big.ctypes.data, big.ctypes.data + 8 * (n // 2), dst[2].ctypes.data], np.uintp)
+    assert call(patches_out=half) == F.FV_ERR_OVERLAP                         # outputs overlap in part
+    assert call(patches_in=np.array([src[0].ctypes.data, 0, src[2].ctypes.data], np.uintp)) == F.FV_ERR_INVALID_ARG
+    assert call(num_patches=0, sizes=None, patches_in=[], patches_out=[]) == F.FV_OK
+    with pytest.raises(ValueError):
+        call(patches_in=[np.zeros(n, np.float32)] * T)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    assert call() == F.FV_ERR_NO_DEVICE
+
+
+def test_host_patches_alignment():
+    n = (4 + 2) ** 2 * 5
+    raw = np.zeros(3 * n + 1)
+    src = [np.zeros(n) for _ in range(2)]
+    odd = np.array([raw.ctypes.data + 4, raw.ctypes.data + 8 * n + 8], np.uintp)   # 4 bytes off
+    assert F.fv_host_patches_update(src, odd, [4, 4], 2, 2, 5, 1e-3, 0.1, 1.4,
+                                    raise_on_error=False) == F.FV_ERR_INVALID_ARG
