@@ -71,6 +71,12 @@ def _bind(lib):
     lib.fvo_batch_update_lts.restype = ctypes.c_int
     lib.fvo_local_dt.argtypes = [dp, dp, i32, i32, f64, dp]
     lib.fvo_local_dt.restype = ctypes.c_int
+    lib.fvo_pde_shape.argtypes = [i32, i32, ip, ip, ip]
+    lib.fvo_pde_shape.restype = ctypes.c_int
+    lib.fvo_pde_update.argtypes = [i32, dp, i32, dp, dp, ip, lp, i32, i32, f64, f64, i32, dp]
+    lib.fvo_pde_update.restype = ctypes.c_int
+    lib.fvo_pde_terms.argtypes = [i32, i32, dp, dp, i32, dp, dp, dp, dp, dp]
+    lib.fvo_pde_terms.restype = ctypes.c_int
     return lib
 
 
@@ -223,3 +229,56 @@ def run_steps(state: np.ndarray, sizes, offsets, dim: int, nq: int, dts, h: floa
         lams.append(lam)
         a, b = b, a
     return a, lams
+
+
+# ---------------------------------------------------------------- the generic solver of Eq. 1
+PDE_EULER = 0
+PDE_SHALLOW_WATER = 1
+PDE_ADVECTION = 2
+PDE_ACOUSTICS = 3
+PDE_ACOUSTICS_NCP = 4
+
+
+def pde_shape(pde: int, dim: int, lib=None) -> tuple[int, int, int]:
+    """(unknowns per volume, evolved unknowns, parameters) of a PDE in dim dimensions."""
+    lib = lib or load()
+    nq, nv, npr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    if lib.fvo_pde_shape(pde, dim, ctypes.byref(nq), ctypes.byref(nv), ctypes.byref(npr)) != 0:
+        raise ValueError(f"no PDE {pde} in {dim}D")
+    return nq.value, nv.value, npr.value
+
+
+def pde_update(pde: int, prm, state_in: np.ndarray, sizes, offsets, dim: int, dt: float, h: float,
+               periodic: bool = False, out: np.ndarray | None = None, want_lambda: bool = True, lib=None):
+    """One explicit Euler step of every patch for the PDE `pde` with parameters prm.
+    Returns (out, lambda or None); ``out`` defaults to a copy of the input."""
+    lib = lib or load()
+    num_patches = len(offsets)
+    sizes, offsets = _descriptors(sizes, offsets, num_patches)
+    state_in = np.ascontiguousarray(state_in, dtype=np.float64)
+    prm = np.ascontiguousarray(np.asarray(prm, np.float64).reshape(-1))
+    out = state_in.copy() if out is None else out
+    lam = np.zeros(num_patches, dtype=np.float64) if want_lambda else None
+    rc = lib.fvo_pde_update(pde, _dptr(prm), len(prm), _dptr(state_in), _dptr(out),
+                            sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), num_patches, dim, dt, h,
+                            int(bool(periodic)), _dptr(lam) if lam is not None else None)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out, lam
+
+
+def pde_terms(pde: int, dim: int, prm, q, n: int, dq=None, lib=None):
+    """User terms of one volume: (F_n(q), lambda_max,n(q), B_n(q) dq, S(q)); vectors over
+    the evolved unknowns."""
+    lib = lib or load()
+    nq, nv, _ = pde_shape(pde, dim, lib)
+    prm = np.ascontiguousarray(np.asarray(prm, np.float64).reshape(-1))
+    q = np.ascontiguousarray(np.asarray(q, np.float64))
+    dq = np.zeros(nq) if dq is None else np.ascontiguousarray(np.asarray(dq, np.float64))
+    f, b, s = np.zeros(nv), np.zeros(nv), np.zeros(nv)
+    lam = np.zeros(1)
+    if lib.fvo_pde_terms(pde, dim, _dptr(prm), _dptr(q), n, _dptr(dq), _dptr(f), _dptr(lam), _dptr(b),
+                         _dptr(s)) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return f, float(lam[0]), b, s

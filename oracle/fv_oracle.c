@@ -364,3 +364,314 @@ int32_t fvo_max_threads(void)
     return 1;
 #endif
 }
+
+/* ========================================================================
+ * The generic solver of Eq. 1: the same step assembled from a PDE's user
+ * terms -- flux F_n, non-conservative product B_n(Q) dQ/dx_n, source S and
+ * largest wave speed lambda_max,n (Sec. 2.2: the user provides these and the
+ * engine assembles the solver).  Point sources (the delta terms) are not
+ * covered.
+ *
+ * Readings (the paper omits the treatment of B in the flux, Sec. 2.2):
+ *   - the conservative part is Eq. 2 over the evolved unknowns;
+ *   - B enters at every face as the jump B_n(Qbar) (Q_R - Q_L) with the face
+ *     average Qbar = (Q_L + Q_R) / 2, half of it charged to each of the two
+ *     volumes (the central, path-conservative discretisation of
+ *     -B dQ/dx), so the volume right of the face receives
+ *         G+ = Fhat - 1/2 B_n(Qbar) (Q_R - Q_L)
+ *     and the volume left of it loses
+ *         G- = Fhat + 1/2 B_n(Qbar) (Q_R - Q_L);
+ *     with B = 0 both are Fhat and the step is the Euler step above;
+ *   - the update of a volume is, difference first and in axis order,
+ *         Q_new = Q + (dt/h) sum_n [G+_n(c - e_n/2) - G-_n(c + e_n/2)] + dt S(Q)
+ *     (explicit Euler for the source, evaluated on the old state);
+ *   - a PDE may carry parameters as unknowns (the bathymetry of the shallow
+ *     water equations): the unknowns from nv on are not evolved, they keep
+ *     their values and enter only through F, B, S and lambda.
+ *
+ * The PDEs (parameters in prm[]):
+ *   FVO_PDE_EULER          the Euler equations of the first part, N = 5;
+ *                          prm = {gamma}.
+ *   FVO_PDE_SHALLOW_WATER  2D shallow water over a bathymetry b, Q = (h, hu,
+ *                          hv, b), nv = 3; prm = {g, f}:
+ *                            F_x = (hu, hu u, hv u),  F_y = (hv, hu v, hv v)
+ *                            B_x dQ/dx = (0, g h d(h + b)/dx, 0)
+ *                            B_y dQ/dy = (0, 0, g h d(h + b)/dy)
+ *                            S = (0, f hv, -f hu)          (Coriolis)
+ *                            lambda_n = |u_n| + sqrt(g h)
+ *                          (the hydrostatic pressure is written as a
+ *                          non-conservative product, so a lake at rest has no
+ *                          momentum change).
+ *   FVO_PDE_ADVECTION      dq/dt + a . grad q = 0, N = 1; prm = {a_x, a_y, a_z};
+ *                          F_n = a_n q, lambda_n = |a_n|.
+ *   FVO_PDE_ACOUSTICS      linear acoustics, Q = (p, u_1 .. u_d), N = 1 + d;
+ *                          prm = {rho0, K0}:  F_n = (K0 u_n, p / rho0 e_n),
+ *                          lambda_n = sqrt(K0 / rho0).
+ *   FVO_PDE_ACOUSTICS_NCP  the same system written as B_n dQ/dx_n with F = 0.
+ * ====================================================================== */
+
+#define FVO_PDE_EULER 0
+#define FVO_PDE_SHALLOW_WATER 1
+#define FVO_PDE_ADVECTION 2
+#define FVO_PDE_ACOUSTICS 3
+#define FVO_PDE_ACOUSTICS_NCP 4
+
+typedef struct {
+    int nq, nv;  /* unknowns per volume; the first nv are evolved */
+    /* F_n(Q) over the evolved unknowns; NULL: no flux */
+    void (*flux)(const double *q, int n, const double *prm, double *f);
+    double (*eig)(const double *q, int n, const double *prm);
+    /* B_n(qbar) dq over the evolved unknowns; NULL: no non-conservative term */
+    void (*ncp)(const double *qbar, const double *dq, int n, const double *prm, double *b);
+    /* S(Q) over the evolved unknowns; NULL: no source */
+    void (*source)(const double *q, const double *prm, double *s);
+} ora_pde;
+
+static void pde_euler_flux(const double *q, int n, const double *prm, double *f)
+{
+    double lam;
+    ora_flux(q, n, 5, prm[0], f, &lam);
+}
+
+static double pde_euler_eig(const double *q, int n, const double *prm)
+{
+    double f[ORA_MAXQ], lam;
+    ora_flux(q, n, 5, prm[0], f, &lam);
+    return lam;
+}
+
+static void pde_swe_flux(const double *q, int n, const double *prm, double *f)
+{
+    double un = q[1 + n] / q[0];
+    f[0] = q[1 + n];
+    f[1] = q[1] * un;
+    f[2] = q[2] * un;
+    (void)prm;
+}
+
+static double pde_swe_eig(const double *q, int n, const double *prm)
+{
+    return fabs(q[1 + n] / q[0]) + sqrt(prm[0] * q[0]);
+}
+
+static void pde_swe_ncp(const double *qbar, const double *dq, int n, const double *prm, double *b)
+{
+    double hydro = prm[0] * qbar[0] * (dq[0] + dq[3]);  /* g h d(h + b) */
+    b[0] = 0.0;
+    b[1] = (n == 0) ? hydro : 0.0;
+    b[2] = (n == 1) ? hydro : 0.0;
+}
+
+static void pde_swe_source(const double *q, const double *prm, double *s)
+{
+    s[0] = 0.0;
+    s[1] = prm[1] * q[2];
+    s[2] = -prm[1] * q[1];
+}
+
+static void pde_adv_flux(const double *q, int n, const double *prm, double *f) { f[0] = prm[n] * q[0]; }
+
+static double pde_adv_eig(const double *q, int n, const double *prm)
+{
+    (void)q;
+    return fabs(prm[n]);
+}
+
+static int ora_acoustic_dim;  /* set per call: the number of velocity components */
+
+static void pde_ac_flux(const double *q, int n, const double *prm, double *f)
+{
+    f[0] = prm[1] * q[1 + n];
+    for (int a = 0; a < ora_acoustic_dim; ++a) f[1 + a] = (a == n) ? q[0] / prm[0] : 0.0;
+}
+
+static double pde_ac_eig(const double *q, int n, const double *prm)
+{
+    (void)q;
+    (void)n;
+    return sqrt(prm[1] / prm[0]);
+}
+
+static void pde_ac_ncp(const double *qbar, const double *dq, int n, const double *prm, double *b)
+{
+    (void)qbar;
+    b[0] = prm[1] * dq[1 + n];
+    for (int a = 0; a < ora_acoustic_dim; ++a) b[1 + a] = (a == n) ? dq[0] / prm[0] : 0.0;
+}
+
+/* The PDE `pde` in `dim` dimensions and the number of parameters it takes;
+ * -1 if there is no such PDE. */
+static int ora_pde_get(int pde, int dim, ora_pde *P, int *nprm)
+{
+    if (!(dim == 2 || dim == 3)) return -1;
+    memset(P, 0, sizeof(*P));
+    switch (pde) {
+    case FVO_PDE_EULER:
+        P->nq = P->nv = 5;
+        P->flux = pde_euler_flux;
+        P->eig = pde_euler_eig;
+        *nprm = 1;
+        return 0;
+    case FVO_PDE_SHALLOW_WATER:
+        if (dim != 2) return -1;
+        P->nq = 4;
+        P->nv = 3;
+        P->flux = pde_swe_flux;
+        P->eig = pde_swe_eig;
+        P->ncp = pde_swe_ncp;
+        P->source = pde_swe_source;
+        *nprm = 2;
+        return 0;
+    case FVO_PDE_ADVECTION:
+        P->nq = P->nv = 1;
+        P->flux = pde_adv_flux;
+        P->eig = pde_adv_eig;
+        *nprm = 3;
+        return 0;
+    case FVO_PDE_ACOUSTICS:
+    case FVO_PDE_ACOUSTICS_NCP:
+        ora_acoustic_dim = dim;
+        P->nq = P->nv = 1 + dim;
+        if (pde == FVO_PDE_ACOUSTICS) P->flux = pde_ac_flux;
+        else P->ncp = pde_ac_ncp;
+        P->eig = pde_ac_eig;
+        *nprm = 2;
+        return 0;
+    default:
+        return -1;
+    }
+}
+
+/* The two face values of Eq. 2 with the non-conservative jump: gplus for the
+ * volume right of the face, gminus for the one left of it. */
+static void ora_pde_face(const ora_pde *P, const double *qL, const double *qR, int n, const double *prm,
+                         double *gplus, double *gminus)
+{
+    double fL[ORA_MAXQ], fR[ORA_MAXQ];
+    for (int q = 0; q < P->nv; ++q) fL[q] = fR[q] = 0.0;
+    if (P->flux) {
+        P->flux(qL, n, prm, fL);
+        P->flux(qR, n, prm, fR);
+    }
+    double s = ora_max(P->eig(qL, n, prm), P->eig(qR, n, prm));
+    double b[ORA_MAXQ];
+    if (P->ncp) {
+        double qbar[ORA_MAXQ], dq[ORA_MAXQ];
+        for (int q = 0; q < P->nq; ++q) {
+            qbar[q] = 0.5 * (qL[q] + qR[q]);
+            dq[q] = qR[q] - qL[q];
+        }
+        P->ncp(qbar, dq, n, prm, b);
+    }
+    for (int q = 0; q < P->nv; ++q) {
+        double fhat = 0.5 * (fL[q] + fR[q]) - 0.5 * s * (qR[q] - qL[q]);
+        gplus[q] = P->ncp ? fhat - 0.5 * b[q] : fhat;
+        gminus[q] = P->ncp ? fhat + 0.5 * b[q] : fhat;
+    }
+}
+
+static void ora_pde_patch_step(const ora_pde *P, const double *Pin, double *Pout, int p, int dim,
+                               double dt, double h, const double *prm)
+{
+    int nq = P->nq;
+    double r = dt / h;
+    int kbeg = (dim == 3) ? 1 : 0, kend = (dim == 3) ? p : 0;
+    for (int k = kbeg; k <= kend; ++k)
+        for (int j = 1; j <= p; ++j)
+            for (int i = 1; i <= p; ++i) {
+                const int c[3] = {i, j, k};
+                const double *qc = Pin + ora_vol(p, dim, i, j, k, nq);
+                double D[ORA_MAXQ];
+                for (int n = 0; n < dim; ++n) {
+                    int lo[3] = {c[0], c[1], c[2]}, hi[3] = {c[0], c[1], c[2]};
+                    lo[n] -= 1;
+                    hi[n] += 1;
+                    const double *ql = Pin + ora_vol(p, dim, lo[0], lo[1], lo[2], nq);
+                    const double *qh = Pin + ora_vol(p, dim, hi[0], hi[1], hi[2], nq);
+                    double lp[ORA_MAXQ], lm[ORA_MAXQ], rp[ORA_MAXQ], rm[ORA_MAXQ];
+                    ora_pde_face(P, ql, qc, n, prm, lp, lm);  /* face c - e_n/2 */
+                    ora_pde_face(P, qc, qh, n, prm, rp, rm);  /* face c + e_n/2 */
+                    for (int q = 0; q < P->nv; ++q) {
+                        double d = lp[q] - rm[q];
+                        D[q] = (n == 0) ? d : D[q] + d;
+                    }
+                }
+                double *qo = Pout + ora_vol(p, dim, i, j, k, nq);
+                double s[ORA_MAXQ];
+                if (P->source) P->source(qc, prm, s);
+                for (int q = 0; q < P->nv; ++q) {
+                    double v = qc[q] + r * D[q];
+                    qo[q] = P->source ? v + dt * s[q] : v;
+                }
+                for (int q = P->nv; q < nq; ++q) qo[q] = qc[q];
+            }
+}
+
+static double ora_pde_patch_lambda(const ora_pde *P, const double *S, int p, int dim, const double *prm)
+{
+    double lmax = 0.0;
+    int kbeg = (dim == 3) ? 1 : 0, kend = (dim == 3) ? p : 0;
+    for (int k = kbeg; k <= kend; ++k)
+        for (int j = 1; j <= p; ++j)
+            for (int i = 1; i <= p; ++i)
+                for (int n = 0; n < dim; ++n)
+                    lmax = ora_max(lmax, P->eig(S + ora_vol(p, dim, i, j, k, P->nq), n, prm));
+    return lmax;
+}
+
+/* Number of unknowns, evolved unknowns and parameters of a PDE in dim
+ * dimensions; -1 if there is no such PDE. */
+int fvo_pde_shape(int32_t pde, int32_t dim, int32_t *nq, int32_t *nv, int32_t *nprm)
+{
+    ora_pde P;
+    int np = 0;
+    if (ora_pde_get(pde, dim, &P, &np) != 0) return -1;
+    *nq = P.nq;
+    *nv = P.nv;
+    *nprm = np;
+    return 0;
+}
+
+/*
+ * One explicit Euler step of every patch for the PDE `pde` (layout, periodic
+ * and lambda_out as in fvo_batch_update; the unknowns per volume are the
+ * PDE's).  prm holds nprm parameters.  Returns -1 for arguments the oracle
+ * does not cover.  Serial (the acoustic PDEs keep their dimension in a
+ * file-scope variable).
+ */
+int fvo_pde_update(int32_t pde, const double *prm, int32_t nprm, const double *in, double *out,
+                   const int32_t *sizes, const int64_t *offsets, int32_t num_patches, int32_t dim,
+                   double dt, double h, int32_t periodic, double *lambda_out)
+{
+    ora_pde P;
+    int np = 0;
+    if (ora_pde_get(pde, dim, &P, &np) != 0 || nprm < np || num_patches < 0) return -1;
+    for (int32_t t = 0; t < num_patches; ++t) {
+        int p = sizes[t];
+        const double *Pin = in + offsets[t];
+        double *Pout = out + offsets[t];
+        ora_pde_patch_step(&P, Pin, Pout, p, dim, dt, h, prm);
+        if (periodic) ora_wrap_faces(Pout, p, dim, P.nq);
+        if (lambda_out) lambda_out[t] = ora_pde_patch_lambda(&P, Pout, p, dim, prm);
+    }
+    return 0;
+}
+
+/*
+ * The user terms of one volume, for tests: f = F_n(q) (zeros without a flux),
+ * lam = lambda_max,n(q), b = B_n(q) dq (zeros without a non-conservative
+ * term), s = S(q) (zeros without a source); f, b, s over the evolved unknowns.
+ */
+int fvo_pde_terms(int32_t pde, int32_t dim, const double *prm, const double *q, int32_t n, const double *dq,
+                  double *f, double *lam, double *b, double *s)
+{
+    ora_pde P;
+    int np = 0;
+    if (ora_pde_get(pde, dim, &P, &np) != 0 || n < 0 || n >= dim) return -1;
+    for (int k = 0; k < P.nv; ++k) f[k] = b[k] = s[k] = 0.0;
+    if (P.flux) P.flux(q, n, prm, f);
+    *lam = P.eig(q, n, prm);
+    if (P.ncp) P.ncp(q, dq, n, prm, b);
+    if (P.source) P.source(q, prm, s);
+    return 0;
+}

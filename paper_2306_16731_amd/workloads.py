@@ -253,3 +253,45 @@ def scatter_to_host(batch: Batch, seed: int = 0) -> list:
         n = int((int(batch.sizes[t]) + 2) ** batch.dim * batch.nq)
         out[t] = batch.data[o:o + n].copy()
     return out
+
+
+# ---------------------------------------------------------------- states of the other PDEs
+PDE_NAMES = ("euler", "shallow_water", "advection", "acoustics", "acoustics_ncp")
+SWE_G = 9.81
+
+
+def pde_unknowns(name: str, dim: int) -> int:
+    """Unknowns per volume of a PDE (the layout the generator writes)."""
+    return {"euler": 5, "shallow_water": 4, "advection": 1, "acoustics": 1 + dim, "acoustics_ncp": 1 + dim}[name]
+
+
+def default_params(name: str) -> list:
+    """Parameters of the synthetic workloads: gamma; g and the Coriolis parameter f; the
+    advection velocity; rho0 and K0 of acoustics."""
+    return {"euler": [GAMMA], "shallow_water": [SWE_G, 0.5], "advection": [0.7, -0.4, 0.25],
+            "acoustics": [1.2, 2.0], "acoustics_ncp": [1.2, 2.0]}[name]
+
+
+def make_pde_batch(name: str, sizes, dim: int = 2, seed: int = 0) -> Batch:
+    """Contiguous batch of padded patches holding random states of the PDE `name`:
+    Euler as make_batch; shallow water (h, hu, hv, b) with depth h in [1, 2], velocities in
+    [-0.5, 0.5] and bathymetry b in [0, 0.3]; advection q in [-1, 1]; acoustics (p, u_1..u_d)
+    in [-1, 1]."""
+    sizes = np.asarray(sizes, dtype=np.int32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if name == "euler":
+        return make_batch(sizes, dim, 5, seed, rng=rng)
+    nq = pde_unknowns(name, dim)
+    nvol = int(np.sum((sizes.astype(np.int64) + 2) ** dim))
+    if name == "shallow_water":
+        if dim != 2:
+            raise ValueError("shallow water is 2D")
+        h = rng.uniform(1.0, 2.0, nvol)
+        u = rng.uniform(-0.5, 0.5, nvol)
+        v = rng.uniform(-0.5, 0.5, nvol)
+        b = rng.uniform(0.0, 0.3, nvol)
+        vols = np.stack([h, h * u, h * v, b], axis=1)
+    else:
+        vols = rng.uniform(-1.0, 1.0, (nvol, nq))
+    return Batch(data=vols.reshape(-1).copy(), sizes=sizes, offsets=contiguous_offsets(sizes, dim, nq), dim=dim,
+                 nq=nq)

@@ -1,0 +1,181 @@
+"""The generic solver of Eq. 1 in the CPU oracle against the pins of
+tests/pde_checks.py, its Euler instance against the Euler oracle, and mutants of
+the new code that the pins must catch."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_16731_amd import workloads as wl
+from tests import pde_checks as pc
+
+IDS = {"euler": oracle.PDE_EULER, "shallow_water": oracle.PDE_SHALLOW_WATER, "advection": oracle.PDE_ADVECTION,
+       "acoustics": oracle.PDE_ACOUSTICS, "acoustics_ncp": oracle.PDE_ACOUSTICS_NCP}
+
+
+def oracle_calls(lib=None):
+    lib = lib or oracle.load()
+
+    def update(name, prm, data, sizes, offsets, dim, dt, h, periodic):
+        return oracle.pde_update(IDS[name], prm, data, sizes, offsets, dim, dt, h, periodic, lib=lib)
+
+    def terms(name, dim, prm, q, n, dq):
+        return oracle.pde_terms(IDS[name], dim, prm, q, n, dq, lib=lib)
+
+    def fill(data, sizes, offsets, nb, dim, nq):
+        out = np.array(data, np.float64, copy=True)
+        rc = lib.fvo_halo_fill(oracle._dptr(out), oracle._dptr(out), *_desc(sizes, offsets, nb), len(sizes), dim, nq)
+        assert rc == 0
+        return out
+
+    return update, terms, fill
+
+
+def _desc(sizes, offsets, nb):
+    import ctypes
+    s = np.ascontiguousarray(sizes, np.int32)
+    o = np.ascontiguousarray(offsets, np.int64)
+    n = np.ascontiguousarray(nb, np.int32).reshape(-1)
+    _desc.keep = (s, o, n)
+    return (s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+UPDATE, TERMS, FILL = oracle_calls()
+
+
+def test_shapes():
+    assert oracle.pde_shape(oracle.PDE_EULER, 3) == (5, 5, 1)
+    assert oracle.pde_shape(oracle.PDE_SHALLOW_WATER, 2) == (4, 3, 2)
+    assert oracle.pde_shape(oracle.PDE_ADVECTION, 3) == (1, 1, 3)
+    assert oracle.pde_shape(oracle.PDE_ACOUSTICS, 2) == (3, 3, 2)
+    assert oracle.pde_shape(oracle.PDE_ACOUSTICS_NCP, 3) == (4, 4, 2)
+    with pytest.raises(ValueError):
+        oracle.pde_shape(oracle.PDE_SHALLOW_WATER, 3)
+    with pytest.raises(ValueError):
+        oracle.pde_shape(7, 2)
+
+
+@pytest.mark.parametrize("dim,periodic", [(2, False), (2, True), (3, False), (3, True)])
+def test_euler_instance_is_the_euler_oracle(dim, periodic):
+    """The generic solver with the Euler user terms is the (pinned) Euler oracle, bit for bit."""
+    b = wl.make_mixed(9, choices=(3, 4, 7), dim=dim, seed=dim)
+    want, wl_ = oracle.batch_update(b.data, b.sizes, b.offsets, dim, 5, 1.3e-3, wl.H_DEFAULT, wl.GAMMA, periodic)
+    got, gl = UPDATE("euler", [wl.GAMMA], b.data, b.sizes, b.offsets, dim, 1.3e-3, wl.H_DEFAULT, periodic)
+    assert np.array_equal(got, want)
+    assert np.array_equal(gl, wl_)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_advection_is_upwind(dim):
+    pc.check_advection_is_upwind(UPDATE, dim)
+
+
+@pytest.mark.parametrize("name", ["advection", "acoustics", "acoustics_ncp"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fourier_mode(name, dim):
+    pc.check_fourier_mode(UPDATE, name, dim)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ncp_form_equals_flux_form(dim):
+    pc.check_ncp_form_equals_flux_form(UPDATE, dim)
+
+
+def test_swe_eigenvalue():
+    pc.check_swe_eigenvalue(TERMS)
+
+
+def test_lake_at_rest():
+    pc.check_lake_at_rest(UPDATE)
+
+
+def test_swe_conservation():
+    pc.check_swe_conservation(UPDATE)
+
+
+def test_swe_swap():
+    pc.check_swe_swap_xy(UPDATE)
+
+
+def test_coriolis():
+    pc.check_coriolis(UPDATE)
+
+
+def test_dam_break_converges_to_stoker():
+    errs = pc.check_dam_break_converges(UPDATE, FILL)
+    print("L1 errors", errs)
+
+
+def test_bathymetry_not_evolved_and_lambda():
+    b = wl.make_pde_batch("shallow_water", [5, 5], dim=2, seed=9)
+    out, lam = UPDATE("shallow_water", pc.PRM["shallow_water"], b.data, b.sizes, b.offsets, 2, 1e-3, 0.05, False)
+    assert np.array_equal(out.reshape(-1, 4)[:, 3], b.data.reshape(-1, 4)[:, 3])
+    for t in range(2):
+        v = out[b.offsets[t]:b.offsets[t] + 49 * 4].reshape(7, 7, 4)[1:-1, 1:-1]
+        c = np.sqrt(wl.SWE_G * v[..., 0])
+        want = max(np.max(np.abs(v[..., 1] / v[..., 0]) + c), np.max(np.abs(v[..., 2] / v[..., 0]) + c))
+        assert lam[t] == want
+
+
+MUTANTS = [
+    ("swe flux: wrong velocity", "f[1] = q[1] * un;", "f[1] = q[2] * un;"),
+    ("swe flux: mass flux along x only", "f[0] = q[1 + n];\n    f[1] = q[1] * un;", "f[0] = q[1];\n    f[1] = q[1] * un;"),
+    ("swe eigenvalue without abs", "return fabs(q[1 + n] / q[0]) + sqrt(prm[0] * q[0]);",
+     "return q[1 + n] / q[0] + sqrt(prm[0] * q[0]);"),
+    ("swe eigenvalue without g", "return fabs(q[1 + n] / q[0]) + sqrt(prm[0] * q[0]);",
+     "return fabs(q[1 + n] / q[0]) + sqrt(q[0]);"),
+    ("swe ncp without the bathymetry", "(dq[0] + dq[3]);", "(dq[0]);"),
+    ("swe ncp on the wrong axis", "b[1] = (n == 0) ? hydro : 0.0;", "b[1] = (n == 1) ? hydro : 0.0;"),
+    ("swe ncp with the left depth", "qbar[q] = 0.5 * (qL[q] + qR[q]);", "qbar[q] = qL[q];"),
+    ("ncp charged with the wrong sign", "gplus[q] = P->ncp ? fhat - 0.5 * b[q] : fhat;",
+     "gplus[q] = P->ncp ? fhat + 0.5 * b[q] : fhat;"),
+    ("ncp charged fully to one side", "gminus[q] = P->ncp ? fhat + 0.5 * b[q] : fhat;",
+     "gminus[q] = P->ncp ? fhat : fhat;"),
+    ("source with the wrong sign", "s[2] = -prm[1] * q[1];", "s[2] = prm[1] * q[1];"),
+    ("source scaled by dt/h", "qo[q] = P->source ? v + dt * s[q] : v;", "qo[q] = P->source ? v + r * s[q] : v;"),
+    ("parameters evolved", "for (int q = P->nv; q < nq; ++q) qo[q] = qc[q];",
+     "for (int q = P->nv; q < nq; ++q) qo[q] = qc[q] + r * D[0];"),
+    ("acoustic flux with rho0 multiplied", "f[1 + a] = (a == n) ? q[0] / prm[0] : 0.0;",
+     "f[1 + a] = (a == n) ? q[0] * prm[0] : 0.0;"),
+    ("acoustic ncp on the wrong unknown", "b[0] = prm[1] * dq[1 + n];", "b[0] = prm[1] * dq[1];"),
+    ("acoustic speed inverted", "return sqrt(prm[1] / prm[0]);", "return sqrt(prm[0] / prm[1]);"),
+    ("advection speed without abs", "return fabs(prm[n]);", "return prm[n];"),
+    ("generic face from one side", "ora_pde_face(P, qc, qh, n, prm, rp, rm);", "ora_pde_face(P, ql, qc, n, prm, rp, rm);"),
+    ("generic lambda over the old state", "lambda_out[t] = ora_pde_patch_lambda(&P, Pout, p, dim, prm);",
+     "lambda_out[t] = ora_pde_patch_lambda(&P, Pin, p, dim, prm);"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pde_mutant_is_caught(name, old, new, tmp_path):
+    src = open(oracle.SOURCE).read()
+    assert src.count(old) == 1, f"mutation site not unique / missing: {old!r}"
+    path = os.path.join(tmp_path, "mutant.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    lib = oracle.load(oracle.build(path, os.path.join(tmp_path, "libmutant.so")))
+    update, terms, fill = oracle_calls(lib)
+    checks = [
+        ("advection upwind 2D", lambda: pc.check_advection_is_upwind(update, 2)),
+        ("advection upwind 3D", lambda: pc.check_advection_is_upwind(update, 3)),
+        ("fourier acoustics 3D", lambda: pc.check_fourier_mode(update, "acoustics", 3)),
+        ("fourier acoustics ncp 2D", lambda: pc.check_fourier_mode(update, "acoustics_ncp", 2)),
+        ("ncp form = flux form", lambda: pc.check_ncp_form_equals_flux_form(update, 2)),
+        ("swe eigenvalue", lambda: pc.check_swe_eigenvalue(terms)),
+        ("lake at rest", lambda: pc.check_lake_at_rest(update)),
+        ("swe conservation", lambda: pc.check_swe_conservation(update)),
+        ("swe swap", lambda: pc.check_swe_swap_xy(update)),
+        ("coriolis", lambda: pc.check_coriolis(update)),
+        ("dam break", lambda: pc.check_dam_break_converges(update, fill, resolutions=(64, 128, 256))),
+    ]
+    for check_name, check in checks:
+        try:
+            check()
+        except (AssertionError, ValueError, FloatingPointError):
+            print(f"mutant '{name}' caught by: {check_name}")
+            return
+    pytest.fail(f"mutant '{name}' passes every pin")
