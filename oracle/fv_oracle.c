@@ -442,8 +442,8 @@ static double pde_euler_eig(const double *q, int n, const double *prm)
 
 static void pde_swe_flux(const double *q, int n, const double *prm, double *f)
 {
-    double un = q[1 + n] / q[0];
-    f[0] = q[1 + n];
+    double un = q[n + 1] / q[0];
+    f[0] = q[n + 1];
     f[1] = q[1] * un;
     f[2] = q[2] * un;
     (void)prm;
@@ -574,7 +574,7 @@ static void ora_pde_patch_step(const ora_pde *P, const double *Pin, double *Pout
                                double dt, double h, const double *prm)
 {
     int nq = P->nq;
-    double r = dt / h;
+    const double ratio = dt / h;
     int kbeg = (dim == 3) ? 1 : 0, kend = (dim == 3) ? p : 0;
     for (int k = kbeg; k <= kend; ++k)
         for (int j = 1; j <= p; ++j)
@@ -584,8 +584,8 @@ static void ora_pde_patch_step(const ora_pde *P, const double *Pin, double *Pout
                 double D[ORA_MAXQ];
                 for (int n = 0; n < dim; ++n) {
                     int lo[3] = {c[0], c[1], c[2]}, hi[3] = {c[0], c[1], c[2]};
-                    lo[n] -= 1;
-                    hi[n] += 1;
+                    lo[n] = c[n] - 1;
+                    hi[n] = c[n] + 1;
                     const double *ql = Pin + ora_vol(p, dim, lo[0], lo[1], lo[2], nq);
                     const double *qh = Pin + ora_vol(p, dim, hi[0], hi[1], hi[2], nq);
                     double lp[ORA_MAXQ], lm[ORA_MAXQ], rp[ORA_MAXQ], rm[ORA_MAXQ];
@@ -593,14 +593,15 @@ static void ora_pde_patch_step(const ora_pde *P, const double *Pin, double *Pout
                     ora_pde_face(P, qc, qh, n, prm, rp, rm);  /* face c + e_n/2 */
                     for (int q = 0; q < P->nv; ++q) {
                         double d = lp[q] - rm[q];
-                        D[q] = (n == 0) ? d : D[q] + d;
+                        if (n == 0) D[q] = d;
+                        else D[q] = D[q] + d;
                     }
                 }
                 double *qo = Pout + ora_vol(p, dim, i, j, k, nq);
                 double s[ORA_MAXQ];
                 if (P->source) P->source(qc, prm, s);
                 for (int q = 0; q < P->nv; ++q) {
-                    double v = qc[q] + r * D[q];
+                    double v = qc[q] + ratio * D[q];
                     qo[q] = P->source ? v + dt * s[q] : v;
                 }
                 for (int q = P->nv; q < nq; ++q) qo[q] = qc[q];

@@ -17,10 +17,11 @@ from tests import invariants as inv
 
 # (name, original text, planted text)
 MUTANTS = [
-    ("dissipation factor 1 instead of 1/2", "- 0.5 * s * (qR[q] - qL[q])", "- 1.0 * s * (qR[q] - qL[q])"),
-    ("anti-dissipation", "- 0.5 * s * (qR[q] - qL[q])", "+ 0.5 * s * (qR[q] - qL[q])"),
-    ("dissipation dropped", "- 0.5 * s * (qR[q] - qL[q])", "- 0.0 * s * (qR[q] - qL[q])"),
-    ("central average dropped", "0.5 * (fL[q] + fR[q])", "fL[q]"),
+    ("dissipation factor 1 instead of 1/2", "fhat[q] = 0.5 * (fL[q] + fR[q]) - 0.5 * s",
+     "fhat[q] = 0.5 * (fL[q] + fR[q]) - 1.0 * s"),
+    ("anti-dissipation", "fhat[q] = 0.5 * (fL[q] + fR[q]) - 0.5 * s", "fhat[q] = 0.5 * (fL[q] + fR[q]) + 0.5 * s"),
+    ("dissipation dropped", "fhat[q] = 0.5 * (fL[q] + fR[q]) - 0.5 * s", "fhat[q] = 0.5 * (fL[q] + fR[q]) - 0.0 * s"),
+    ("central average dropped", "fhat[q] = 0.5 * (fL[q] + fR[q])", "fhat[q] = fL[q]"),
     ("update sign flipped", "double d = fleft[q] - fright[q];", "double d = fright[q] - fleft[q];"),
     ("update scaled by dt*h", "double r = dt / h;", "double r = dt * h;"),
     ("pressure missing in momentum flux", "if (a == n) v = v + p;", "if (a == n) v = v;"),

@@ -123,7 +123,7 @@ def test_bathymetry_not_evolved_and_lambda():
 
 MUTANTS = [
     ("swe flux: wrong velocity", "f[1] = q[1] * un;", "f[1] = q[2] * un;"),
-    ("swe flux: mass flux along x only", "f[0] = q[1 + n];\n    f[1] = q[1] * un;", "f[0] = q[1];\n    f[1] = q[1] * un;"),
+    ("swe flux: mass flux along x only", "f[0] = q[n + 1];", "f[0] = q[1];"),
     ("swe eigenvalue without abs", "return fabs(q[1 + n] / q[0]) + sqrt(prm[0] * q[0]);",
      "return q[1 + n] / q[0] + sqrt(prm[0] * q[0]);"),
     ("swe eigenvalue without g", "return fabs(q[1 + n] / q[0]) + sqrt(prm[0] * q[0]);",
@@ -136,9 +136,9 @@ MUTANTS = [
     ("ncp charged fully to one side", "gminus[q] = P->ncp ? fhat + 0.5 * b[q] : fhat;",
      "gminus[q] = P->ncp ? fhat : fhat;"),
     ("source with the wrong sign", "s[2] = -prm[1] * q[1];", "s[2] = prm[1] * q[1];"),
-    ("source scaled by dt/h", "qo[q] = P->source ? v + dt * s[q] : v;", "qo[q] = P->source ? v + r * s[q] : v;"),
+    ("source scaled by dt/h", "qo[q] = P->source ? v + dt * s[q] : v;", "qo[q] = P->source ? v + ratio * s[q] : v;"),
     ("parameters evolved", "for (int q = P->nv; q < nq; ++q) qo[q] = qc[q];",
-     "for (int q = P->nv; q < nq; ++q) qo[q] = qc[q] + r * D[0];"),
+     "for (int q = P->nv; q < nq; ++q) qo[q] = qc[q] + ratio * D[0];"),
     ("acoustic flux with rho0 multiplied", "f[1 + a] = (a == n) ? q[0] / prm[0] : 0.0;",
      "f[1 + a] = (a == n) ? q[0] * prm[0] : 0.0;"),
     ("acoustic ncp on the wrong unknown", "b[0] = prm[1] * dq[1 + n];", "b[0] = prm[1] * dq[1];"),
