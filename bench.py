@@ -90,7 +90,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patches", type=int, default=4096,
                     help="patches the CPU oracle advances through all warmup + timed steps")
-    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer", "pde"], default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
                          "plans and captured graphs (one line each).  serving: the request loop (config 5)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
@@ -121,6 +121,8 @@ def main() -> int:
         return bench_flavours(args)
     if args.form == "transfer":
         return bench_transfer(args)
+    if args.form == "pde":
+        return bench_pde(args)
     if args.form == "batching":
         return bench_batching(args)
     if args.form == "serving":
@@ -334,6 +336,76 @@ def bench_flavours(args) -> int:
                     print(json.dumps(line), flush=True)
                 del a, c, lam
                 torch.cuda.empty_cache()
+    return 0
+
+
+def bench_pde(args) -> int:
+    """The generic solver of Eq. 1 (fv_pde_batch_update) on the shapes of the headline
+    workloads: 2D shallow water (flux + non-conservative product + source, 4 unknowns with the
+    bathymetry carried), 2D and 3D acoustics in flux and non-conservative form, 3D advection,
+    and the Euler equations through the same generic plane-marching kernel next to the tuned
+    fixed-size kernel.  HIP events around the timed steps (ping-pong buffers, periodic face
+    halos written, eigenvalue reduction on), per-step algorithmic bytes as in the headline."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    cases = [("shallow_water", 2, 16, 65536), ("acoustics", 2, 16, 65536), ("acoustics_ncp", 2, 16, 65536),
+             ("euler", 2, 16, 65536), ("advection", 3, 8, 32768), ("acoustics", 3, 8, 32768),
+             ("euler", 3, 8, 32768)]
+    for name, dim, p, T in cases:
+        b = wl.make_pde_batch(name, np.full(T, p), dim=dim, seed=args.seed)
+        nq = b.nq
+        prm = wl.default_params(name)
+        a = torch.from_numpy(b.data).to("cuda")
+        c = a.clone()
+        lam = torch.empty(T, dtype=torch.float64, device="cuda")
+        dt, h = 1e-4, wl.H_DEFAULT
+        res = {}
+        variants = [("generic", None)]
+        if name == "euler":
+            variants.append(("tuned", fvpatch.fv_get_tuning(dim, 5, p)))
+        for label, tuned in variants:
+            if name == "euler" and label == "generic":
+                fvpatch.fv_set_tuning(dim, 5, p, {"kernel": fvpatch.FV_KERNEL_BLOCK})
+            bufs = [a, c]
+
+            def step():
+                fvpatch.fv_pde_batch_update(fvpatch.PDE_IDS[name], prm, bufs[0], bufs[1], b.sizes, None, T, dim, dt,
+                                            h, fvpatch.FV_HALO_PERIODIC, lam)
+                bufs.reverse()
+
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            res[label] = e0.elapsed_time(e1) / args.steps
+            if name == "euler" and label == "generic":
+                fvpatch.fv_set_tuning(dim, 5, p, None)
+        alg = T * alg_bytes_per_patch(p, dim, nq, True, True)
+        ms = res["generic"]
+        gbs = alg / (ms / 1e3) / 1e9
+        line = {"metric": "cell-updates/s", "form": "pde", "pde": name, "value": round(T * p ** dim / (ms / 1e3), 1),
+                "unit": "cell-updates/s", "ms_per_step": round(ms, 5), "alg_GBs": round(gbs, 1),
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": alg,
+                "kernel": "generic plane-marching kernel", "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"{dim}D {name} {T} x {p}^{dim}", "patches": T, "p": p, "dim": dim,
+                           "unknowns": nq, "params": prm, "periodic_halo": True, "eigenvalue_reduction": True,
+                           "steps": args.steps}}
+        if "tuned" in res:
+            line["tuned_kernel_ms_per_step"] = round(res["tuned"], 5)
+            line["generic_over_tuned"] = round(ms / res["tuned"], 3)
+        print(json.dumps(line), flush=True)
+        del a, c, lam
+        torch.cuda.empty_cache()
     return 0
 
 

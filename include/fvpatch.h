@@ -358,6 +358,55 @@ fv_status fv_local_dt(const double *lambda, const double *h, int32_t num_patches
 fv_status fv_mesh_destroy(fv_mesh *mesh);
 
 /* ------------------------------------------------------------------------
+ * Other PDEs: the generic solver of Eq. 1.  The paper's engine assembles its
+ * solver from user terms -- flux F_n, non-conservative product
+ * B_n(Q) dQ/dx_n, source S, largest wave speed lambda_max,n (Sec. 2.2) -- and
+ * this call runs the same step for one of the built-in PDEs, each a set of
+ * such terms (a device type in the library's csrc/fv_pde.h; a new PDE is a
+ * new type of that shape).  The step, with B read as a central jump at every
+ * face (the paper omits its treatment) and S as explicit Euler:
+ *   Fhat = 1/2 (F_n(Q_L) + F_n(Q_R)) - 1/2 max(l_n(Q_L), l_n(Q_R)) (Q_R - Q_L)
+ *   G+ / G- = Fhat -/+ 1/2 B_n((Q_L + Q_R) / 2) (Q_R - Q_L)
+ *   Q_new = Q + (dt/h) sum_n [G+(c - e_n/2) - G-(c + e_n/2)] + dt S(Q)
+ * over the evolved unknowns; a PDE's parameter unknowns keep their values.
+ *
+ *   FV_PDE_EULER           the Euler equations (N = 5); params {gamma}: the
+ *                          same as fv_patch_batch_update with unknowns = 5.
+ *   FV_PDE_SHALLOW_WATER   2D only.  Q = (h, hu, hv, b), the bathymetry b not
+ *                          evolved; F_x = (hu, hu u, hv u), F_y = (hv, hu v,
+ *                          hv v); B: the hydrostatic pressure g h d(h+b)/dx_n
+ *                          in the n-momentum; S = (0, f hv, -f hu) (Coriolis);
+ *                          l_n = |u_n| + sqrt(g h).  params {g > 0, f}.
+ *   FV_PDE_ADVECTION       dq/dt + a . grad q = 0, N = 1; params {a_x, a_y,
+ *                          a_z} (a_z ignored in 2D).
+ *   FV_PDE_ACOUSTICS       linear acoustics, Q = (p, u_1 .. u_d), N = 1 + d:
+ *                          F_n = (K0 u_n, p / rho0 e_n), l_n = sqrt(K0 / rho0);
+ *                          params {rho0 > 0, K0 > 0}.
+ *   FV_PDE_ACOUSTICS_NCP   the same system written as B_n dQ/dx_n with F = 0.
+ *
+ * Layout, offsets, flags (FV_HALO_PERIODIC), lambda_out (per-patch max of l_n
+ * over the new interior), streams and errors as fv_patch_batch_update, with N
+ * the PDE's unknowns; params: host [num_params], all finite.  The Euler
+ * equations take every tuned kernel; the other PDEs run on the plane-marching
+ * kernel (any p up to FV_MAX_P_2D / FV_MAX_P_3D).
+ * Errors also: FV_ERR_INVALID_ARG (unknown PDE, wrong num_params, a parameter
+ * out of range), FV_ERR_UNSUPPORTED (shallow water in 3D).
+ * ------------------------------------------------------------------------ */
+#define FV_PDE_EULER 0
+#define FV_PDE_SHALLOW_WATER 1
+#define FV_PDE_ADVECTION 2
+#define FV_PDE_ACOUSTICS 3
+#define FV_PDE_ACOUSTICS_NCP 4
+
+/* Unknowns per volume and number of parameters of a PDE in dim dimensions. */
+fv_status fv_pde_unknowns(int32_t pde, int32_t dim, int32_t *unknowns, int32_t *num_params);
+
+fv_status fv_pde_batch_update(int32_t pde, const double *params, int32_t num_params, const double *patches_in,
+                              double *patches_out, const int32_t *sizes, const int64_t *offsets,
+                              int32_t num_patches, int32_t dim, double dt, double h, uint32_t flags,
+                              double *lambda_out, void *stream);
+
+/* ------------------------------------------------------------------------
  * The paper's three kernel realisations (Sec. 3) as comparison variants of
  * the fused update: the same step, the same microkernels in the same order
  * per volume (results equal to fv_patch_batch_update's bit for bit), mapped

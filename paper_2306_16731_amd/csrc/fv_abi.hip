@@ -272,11 +272,25 @@ void apply_tuning(UpdateLaunch &L) {
 fv_status plain_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets,
                        int32_t T, int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags,
                        double *lambda_out, hipStream_t stream, const BatchShape &shape,
-                       const int64_t *out_offsets) {
+                       const int64_t *out_offsets, const PdeArgs *pde) {
     DeviceContext *ctx = nullptr;
     fv_status st = current_context(&ctx);
     if (st != FV_OK) return st;
     UpdateLaunch L;
+    if (pde) {
+        L.pde = pde->pde;
+        for (int k = 0; k < 4; ++k) L.pde_prm[k] = pde->prm[k];
+    }
+    L.dt = dt;
+    // Euler classes take their tuned kernel; the other PDEs run on the generic block kernel
+    auto tune = [](UpdateLaunch &X) {
+        if (X.pde == kPdeEuler) {
+            apply_tuning(X);
+        } else {
+            X.kernel = FV_KERNEL_BLOCK;
+            X.block = 0;
+        }
+    };
     L.in = in;
     L.out = out;
     L.dim = dim;
@@ -290,7 +304,7 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         L.p = shape.uniform_p;
         L.stride = patch_doubles(L.p, dim, nq);
         L.vec2 = (L.stride % 2 == 0) && aligned16(in) && aligned16(out);
-        apply_tuning(L);
+        tune(L);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
         return FV_OK;
@@ -338,7 +352,7 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         L.out_offsets = dout ? dout + start[p] : nullptr;
         L.ids = did + start[p];
         L.vec2 = bufs16 && !odd[p] && patch_doubles(p, dim, nq) % 2 == 0;
-        apply_tuning(L);
+        tune(L);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) {
             (void)release_slot(slot, stream);
@@ -346,6 +360,21 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         }
     }
     return release_slot(slot, stream);
+}
+
+// Unknowns and parameters of a built-in PDE in dim dimensions.
+fv_status pde_shape(int32_t pde, int32_t dim, int32_t *nq, int32_t *nprm) {
+    if (dim != 2 && dim != 3) return fail(FV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", dim);
+    switch (pde) {
+        case FV_PDE_EULER: *nq = 5; *nprm = 1; return FV_OK;
+        case FV_PDE_SHALLOW_WATER:
+            if (dim != 2) return fail(FV_ERR_UNSUPPORTED, "the shallow water equations are 2D");
+            *nq = 4; *nprm = 2; return FV_OK;
+        case FV_PDE_ADVECTION: *nq = 1; *nprm = 3; return FV_OK;
+        case FV_PDE_ACOUSTICS:
+        case FV_PDE_ACOUSTICS_NCP: *nq = 1 + dim; *nprm = 2; return FV_OK;
+        default: return fail(FV_ERR_INVALID_ARG, "unknown PDE %d", pde);
+    }
 }
 
 }  // namespace fv
@@ -368,6 +397,58 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out, c
     if (st != FV_OK) return st;
     return plain_update(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, dt, h, gamma, flags,
                         lambda_out, static_cast<hipStream_t>(stream), shape, nullptr);
+}
+
+fv_status fv_pde_unknowns(int32_t pde, int32_t dim, int32_t *unknowns, int32_t *num_params) {
+    clear_error();
+    if (!unknowns || !num_params) return fail(FV_ERR_INVALID_ARG, "unknowns and num_params must be non-null");
+    return pde_shape(pde, dim, unknowns, num_params);
+}
+
+fv_status fv_pde_batch_update(int32_t pde, const double *params, int32_t num_params, const double *patches_in,
+                              double *patches_out, const int32_t *sizes, const int64_t *offsets,
+                              int32_t num_patches, int32_t dim, double dt, double h, uint32_t flags,
+                              double *lambda_out, void *stream) {
+    clear_error();
+    int32_t nq = 0, nprm = 0;
+    fv_status st = pde_shape(pde, dim, &nq, &nprm);
+    if (st != FV_OK) return st;
+    if (num_params != nprm) return fail(FV_ERR_INVALID_ARG, "PDE %d takes %d parameters (got %d)", pde, nprm, num_params);
+    if (!params) return fail(FV_ERR_INVALID_ARG, "params must be non-null");
+    for (int k = 0; k < nprm; ++k)
+        if (!std::isfinite(params[k])) return fail(FV_ERR_INVALID_ARG, "params[%d] is not finite", k);
+    if (pde == FV_PDE_EULER)
+        return fv_patch_batch_update(patches_in, patches_out, sizes, offsets, num_patches, dim, 5, dt, h, params[0],
+                                     flags, lambda_out, stream);
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (!std::isfinite(h) || !(h > 0.0)) return fail(FV_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (flags & ~FV_HALO_PERIODIC) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~FV_HALO_PERIODIC);
+    PdeArgs args;
+    args.pde = pde;
+    for (int k = 0; k < nprm; ++k) args.prm[k] = params[k];
+    if (pde == FV_PDE_SHALLOW_WATER && !(params[0] > 0.0)) return fail(FV_ERR_INVALID_ARG, "g must be > 0");
+    if (pde == FV_PDE_ACOUSTICS || pde == FV_PDE_ACOUSTICS_NCP) {
+        if (!(params[0] > 0.0) || !(params[1] > 0.0)) return fail(FV_ERR_INVALID_ARG, "rho0 and K0 must be > 0");
+        args.prm[2] = std::sqrt(params[1] / params[0]);  // the sound speed, a kernel parameter
+    }
+    if (num_patches < 0) return fail(FV_ERR_INVALID_ARG, "num_patches must be >= 0");
+    if (num_patches == 0) return FV_OK;
+    BatchShape shape;
+    st = check_batch(patches_in, patches_out, sizes, offsets, num_patches, dim, nq, lambda_out, &shape);
+    if (st != FV_OK) return st;
+    DeviceContext *ctx = nullptr;
+    st = current_context(&ctx);
+    if (st != FV_OK) return st;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return fail(FV_ERR_NO_DEVICE, "device attributes unavailable");
+    const int32_t pmax = *std::max_element(sizes, sizes + num_patches);  // LDS grows with p
+    if (pde_min_lds_bytes(pde, dim, pmax) > (size_t)lds_max)
+        return fail(FV_ERR_UNSUPPORTED, "a patch of size %d needs more LDS than a block has for PDE %d in %dD", pmax,
+                    pde, dim);
+    return plain_update(patches_in, patches_out, sizes, offsets, num_patches, dim, nq, dt, h, 0.0, flags, lambda_out,
+                        static_cast<hipStream_t>(stream), shape, nullptr, &args);
 }
 
 static fv_status check_class(int32_t dim, int32_t nq, int32_t p) {

@@ -38,11 +38,20 @@ struct UpdateLaunch;
 fv_tuning tuning_for(int dim, int nq, int p);
 void apply_tuning(UpdateLaunch &L);
 
+// A PDE other than Euler for the generic block kernel: its FV_PDE_* id and
+// parameters as the kernel takes them.
+struct PdeArgs {
+    int32_t pde = 0;
+    double prm[4] = {0.0, 0.0, 0.0, 0.0};
+};
+
 // Plain per-batch launch on validated arguments (out_offsets: optional host
-// array of output offsets; NULL = output at the input offsets).
+// array of output offsets; NULL = output at the input offsets; pde: NULL =
+// the Euler equations with `gamma`, else the generic kernel for that PDE).
 fv_status plain_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets, int32_t T,
                        int32_t dim, int32_t nq, double dt, double h, double gamma, uint32_t flags, double *lambda_out,
-                       hipStream_t stream, const BatchShape &shape, const int64_t *out_offsets);
+                       hipStream_t stream, const BatchShape &shape, const int64_t *out_offsets,
+                       const PdeArgs *pde = nullptr);
 
 struct DeviceContext;
 // Context of the current HIP device; FV_ERR_NO_DEVICE / FV_ERR_UNSUPPORTED

@@ -39,7 +39,17 @@ struct UpdateLaunch {
     bool vec2 = false;                 // every patch (and both buffers) 16-byte aligned: 16-byte loads
     int32_t rows = 0;                  // output rows staged per flush (2D wave kernel), 0 = default
     MeshArgs mesh;                     // set: the mesh form (fixed-size kernels only)
+    int32_t pde = 0;                   // kPde*: 0 = Euler (every kernel); others: the generic block kernel
+    double pde_prm[4] = {0.0, 0.0, 0.0, 0.0};  // the PDE's parameters (Euler: gamma above)
+    double dt = 0.0;                   // step size for source terms (with r = dt / h)
 };
+
+// PDEs of the generic kernel (the FV_PDE_* values of include/fvpatch.h).
+constexpr int32_t kPdeEuler = 0;
+constexpr int32_t kPdeShallowWater = 1;
+constexpr int32_t kPdeAdvection = 2;
+constexpr int32_t kPdeAcoustics = 3;
+constexpr int32_t kPdeAcousticsNcp = 4;
 
 // One wave's work in a task-list launch: `count` (<= 64 / (p + 2)) patches of
 // size p, at entries first .. first + count - 1 of the offsets / ids lists;
@@ -85,6 +95,8 @@ size_t update_lds_bytes(int dim, int nq, int block);
 
 // Enqueue one update launch; returns hipSuccess or the launch error.
 hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream);
+// LDS of the generic kernel's smallest block for one patch of size p of a PDE (kPde*).
+size_t pde_min_lds_bytes(int pde, int dim, int p);
 
 // 2D kernel with each padded patch row inside one wavefront (p + 2 <= 64).
 bool wave2d_fits(int p);

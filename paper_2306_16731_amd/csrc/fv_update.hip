@@ -35,6 +35,7 @@
 #include <stdint.h>
 
 #include "fv_internal.h"
+#include "fv_pde.h"
 #include "fv_physics.h"
 
 namespace fv {
@@ -52,27 +53,33 @@ __device__ __forceinline__ void lds_barrier() {
 
 // LDS per lane (structure of arrays over the block's lanes, so consecutive
 // lanes hit consecutive 8-byte words):
-//   XQ[NQ], XF[D-1][NQ], XL[D-1]   the volume's state and in-plane user terms
-//   FH[D-1][NQ]                    the in-plane face flux to the lane's left
-template <int D, int NQ>
+//   XQ[NQ], XF[D-1][NV], XL[D-1]   the volume's state and in-plane user terms
+//   FP[D-1][NV]                    G+ of the in-plane face to the lane's left
+//   FM[D-1][NV]                    G- of that face (PDEs with a non-conservative
+//                                  product; otherwise G- = G+ and FP serves both)
+template <int D, class PDE>
 struct Lds {
     static constexpr int kXQ = 0;
-    static constexpr int kXF = NQ;
-    static constexpr int kXL = kXF + (D - 1) * NQ;
-    static constexpr int kFH = kXL + (D - 1);
-    static constexpr int kWords = kFH + (D - 1) * NQ;
+    static constexpr int kXF = PDE::NQ;
+    static constexpr int kXL = kXF + (D - 1) * PDE::NV;
+    static constexpr int kFP = kXL + (D - 1);
+    static constexpr int kFM = kFP + (D - 1) * PDE::NV;
+    static constexpr int kWords = kFM + (PDE::kNcp ? (D - 1) * PDE::NV : 0);
 };
 
-template <int D, int NQ, int MAXB>
+// The kernel for any PDE type of fv_pde.h (the generic solver of Eq. 1); the
+// Euler instance is the Euler block kernel.
+template <int D, class PDE, int MAXB>
 __global__ void __launch_bounds__(MAXB)
 update_kernel(const double *__restrict__ in, double *__restrict__ out,
               const int64_t *__restrict__ offsets, const int64_t *__restrict__ out_offsets,
               const int32_t *__restrict__ ids,
               int32_t num_items, int32_t P, int64_t stride, double r_host, const double *__restrict__ r_dev,
-              double gamma, uint32_t flags, double *__restrict__ lambda_out) {
+              typename PDE::Params prm, double dt, uint32_t flags, double *__restrict__ lambda_out) {
+    constexpr int NQ = PDE::NQ, NV = PDE::NV;
     extern __shared__ double lds[];
     const double r = r_dev ? *r_dev : r_host;
-    using L = Lds<D, NQ>;
+    using L = Lds<D, PDE>;
     const int B = blockDim.x;
     const int W = P + 2;
     const int S = (D == 2) ? W : W * W;
@@ -101,9 +108,11 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
     const bool periodic = (flags & kPeriodic) != 0;
 
     // Registers carried from one layer to the next (marching axis m = D-1).
-    double qprev[NQ], fmprev[NQ], lmprev = 0.0, fhprev[NQ], dinprev[NQ];
+    double qprev[NQ], fmprev[NV], lmprev = 0.0, gpprev[NV], dinprev[NV];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) { qprev[k] = fmprev[k] = fhprev[k] = dinprev[k] = 0.0; }
+    for (int k = 0; k < NQ; ++k) qprev[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { fmprev[k] = gpprev[k] = dinprev[k] = 0.0; }
     double lmax = 0.0;
 
     double qnext[NQ];
@@ -121,10 +130,10 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
             if (live1) load_volume<NQ>(src + (k + 1) * layer, qnext);
         }
 
-        Prim a;
-        double fm[NQ], lm = 0.0;
+        typename PDE::Cache a;
+        double fm[NV], lm = 0.0;
         if (live) {
-            a = primitives<NQ>(q, gamma);
+            a = PDE::prepare(q, prm);
             // in-plane user terms, published for the neighbours
             if (inner) {
 #pragma unroll
@@ -133,15 +142,15 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
                 for (int n = 0; n < D - 1; ++n) {
                     const bool need = pint || (n == 0 ? xhalo : yhalo);
                     if (need) {
-                        double f[NQ], lam;
-                        euler_flux<NQ>(q, a, n, f, lam);
+                        double f[NV], lam;
+                        PDE::flux(q, a, n, f, lam, prm);
 #pragma unroll
-                        for (int c = 0; c < NQ; ++c) lds[(L::kXF + n * NQ + c) * B + tid] = f[c];
+                        for (int c = 0; c < NV; ++c) lds[(L::kXF + n * NV + c) * B + tid] = f[c];
                         lds[(L::kXL + n) * B + tid] = lam;
                     }
                 }
             }
-            if (pint) euler_flux<NQ>(q, a, D - 1, fm, lm);
+            if (pint) PDE::flux(q, a, D - 1, fm, lm, prm);
         }
         lds_barrier();
 
@@ -154,18 +163,23 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
                 const bool other_in = (n == 0) ? yin : xin;
                 if (other_in && cn >= 1 && cn <= P + 1) {
                     const int nb = tid - ((n == 0) ? 1 : W);
-                    double qL[NQ], fL[NQ], fR[NQ], lR, fh[NQ];
+                    double qL[NQ], fL[NV], fR[NV], lR, gp[NV], gm[NV];
 #pragma unroll
-                    for (int c = 0; c < NQ; ++c) {
-                        qL[c] = lds[(L::kXQ + c) * B + nb];
-                        fL[c] = lds[(L::kXF + n * NQ + c) * B + nb];
-                        fR[c] = lds[(L::kXF + n * NQ + c) * B + tid];
+                    for (int c = 0; c < NQ; ++c) qL[c] = lds[(L::kXQ + c) * B + nb];
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) {
+                        fL[c] = lds[(L::kXF + n * NV + c) * B + nb];
+                        fR[c] = lds[(L::kXF + n * NV + c) * B + tid];
                     }
                     const double lL = lds[(L::kXL + n) * B + nb];
                     lR = lds[(L::kXL + n) * B + tid];
-                    rusanov<NQ>(qL, fL, lL, q, fR, lR, fh);
+                    face_terms<PDE>(qL, fL, lL, q, fR, lR, n, prm, gp, gm);
 #pragma unroll
-                    for (int c = 0; c < NQ; ++c) lds[(L::kFH + n * NQ + c) * B + tid] = fh[c];
+                    for (int c = 0; c < NV; ++c) lds[(L::kFP + n * NV + c) * B + tid] = gp[c];
+                    if constexpr (PDE::kNcp) {
+#pragma unroll
+                        for (int c = 0; c < NV; ++c) lds[(L::kFM + n * NV + c) * B + tid] = gm[c];
+                    }
                 }
             }
         }
@@ -173,29 +187,30 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
 
         if (active && pint) {
             // in-plane differences of this layer's volume: D_x (+ D_y)
-            double din[NQ];
+            double din[NV];
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) din[c] = 0.0;
+            for (int c = 0; c < NV; ++c) din[c] = 0.0;
             if (inner) {
+                constexpr int kRight = PDE::kNcp ? L::kFM : L::kFP;  // G- of the face to the right
 #pragma unroll
                 for (int n = 0; n < D - 1; ++n) {
                     const int nb = tid + ((n == 0) ? 1 : W);
 #pragma unroll
-                    for (int c = 0; c < NQ; ++c) {
-                        const double d = lds[(L::kFH + n * NQ + c) * B + tid] - lds[(L::kFH + n * NQ + c) * B + nb];
+                    for (int c = 0; c < NV; ++c) {
+                        const double d = lds[(L::kFP + n * NV + c) * B + tid] - lds[(kRight + n * NV + c) * B + nb];
                         din[c] = (n == 0) ? d : din[c] + d;
                     }
                 }
             }
             // marching-axis face between layers k-1 and k
-            double fh[NQ];
-            if (k >= 1) rusanov<NQ>(qprev, fmprev, lmprev, q, fm, lm, fh);
+            double gp[NV], gm[NV];
+            if (k >= 1) face_terms<PDE>(qprev, fmprev, lmprev, q, fm, lm, D - 1, prm, gp, gm);
             // complete the volume of layer k-1
             if (k >= 2) {
-                double qn[NQ], dsum[NQ];
+                double qn[NQ], dsum[NV];
 #pragma unroll
-                for (int c = 0; c < NQ; ++c) dsum[c] = dinprev[c] + (fhprev[c] - fh[c]);
-                advance<NQ>(qprev, dsum, r, qn);
+                for (int c = 0; c < NV; ++c) dsum[c] = dinprev[c] + (gpprev[c] - gm[c]);
+                advance_pde<PDE>(qprev, dsum, r, dt, prm, qn);
                 const int kk = k - 1;
                 store_volume<NQ>(dst + kk * layer, qn);
                 if (periodic) {
@@ -208,13 +223,14 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
                     if (kk == P) store_volume<NQ>(dst, qn);
                     if (kk == 1) store_volume<NQ>(dst + (int64_t)(P + 1) * layer, qn);
                 }
-                if (lambda_out) lmax = nanmax(lmax, volume_lambda<D, NQ>(qn, gamma));
+                if (lambda_out) lmax = nanmax(lmax, PDE::template max_lambda<D>(qn, prm));
             }
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                qprev[c] = q[c];
+            for (int c = 0; c < NQ; ++c) qprev[c] = q[c];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
                 fmprev[c] = fm[c];
-                fhprev[c] = fh[c];
+                gpprev[c] = gp[c];
                 dinprev[c] = din[c];
             }
             lmprev = lm;
@@ -233,37 +249,86 @@ update_kernel(const double *__restrict__ in, double *__restrict__ out,
     }
 }
 
-template <int D, int NQ>
-hipError_t launch_typed(const UpdateLaunch &L, hipStream_t stream) {
+template <int D, class PDE>
+size_t pde_lds_bytes(int block) {
+    return sizeof(double) * (size_t)Lds<D, PDE>::kWords * (size_t)block;
+}
+
+// Threads per block for the PDE's LDS footprint: the multiple of 64 that wastes the
+// fewest lanes on partial patches while the block's LDS stays within 64 KiB.
+template <int D, class PDE>
+int pde_default_block(int p) {
+    const int S = plane_lanes(p, D);
+    int best = 0;
+    double best_u = -1.0;
+    for (int B = 64; B <= 1024; B += 64) {
+        if (B < S) continue;
+        if (pde_lds_bytes<D, PDE>(B) > 64 * 1024) break;
+        const double u = (double)((B / S) * S) / B;
+        if (u > best_u + 1e-9) { best_u = u; best = B; }
+    }
+    if (best == 0) best = ((S + 63) / 64) * 64;
+    return best;
+}
+
+template <int D, class PDE>
+hipError_t launch_typed(const UpdateLaunch &L, const typename PDE::Params &prm, hipStream_t stream) {
     const int S = plane_lanes(L.p, L.dim);
-    const int B = L.block > 0 ? L.block : default_block(L.p, L.dim);
+    const int B = L.block > 0 ? L.block
+                              : (L.pde == 0 ? default_block(L.p, L.dim) : pde_default_block<D, PDE>(L.p));
     if (B % 64 != 0 || B > 1024 || B < S) return hipErrorInvalidConfiguration;
     const int ppb = B / S;
     const int64_t blocks = ((int64_t)L.num_items + ppb - 1) / ppb;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const size_t lds = update_lds_bytes(L.dim, L.nq, B);
+    const size_t lds = pde_lds_bytes<D, PDE>(B);
     int dev = 0, lds_max = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return hipErrorInvalidDevice;
     if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
     if (lds > 64 * 1024) {
-        const void *fn = B <= 256 ? reinterpret_cast<const void *>(&update_kernel<D, NQ, 256>)
-                                  : reinterpret_cast<const void *>(&update_kernel<D, NQ, 1024>);
+        const void *fn = B <= 256 ? reinterpret_cast<const void *>(&update_kernel<D, PDE, 256>)
+                                  : reinterpret_cast<const void *>(&update_kernel<D, PDE, 1024>);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     if (B <= 256)
-        hipLaunchKernelGGL((update_kernel<D, NQ, 256>), dim3((unsigned)blocks), dim3(B), lds, stream,
+        hipLaunchKernelGGL((update_kernel<D, PDE, 256>), dim3((unsigned)blocks), dim3(B), lds, stream,
                            L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev,
-                           L.gamma,
-                           L.flags, L.lambda_out);
+                           prm, L.dt, L.flags, L.lambda_out);
     else
-        hipLaunchKernelGGL((update_kernel<D, NQ, 1024>), dim3((unsigned)blocks), dim3(B), lds, stream,
+        hipLaunchKernelGGL((update_kernel<D, PDE, 1024>), dim3((unsigned)blocks), dim3(B), lds, stream,
                            L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.p, L.stride, L.r, L.r_dev,
-                           L.gamma,
-                           L.flags, L.lambda_out);
+                           prm, L.dt, L.flags, L.lambda_out);
     return hipGetLastError();
+}
+
+template <int D, int NQ>
+hipError_t launch_euler(const UpdateLaunch &L, hipStream_t stream) {
+    return launch_typed<D, EulerPDE<NQ>>(L, typename EulerPDE<NQ>::Params{L.gamma}, stream);
+}
+
+// The other built-in PDEs (FV_PDE_* of include/fvpatch.h; block kernel only).
+hipError_t launch_pde(const UpdateLaunch &L, hipStream_t stream) {
+    const double *c = L.pde_prm;
+    switch (L.pde) {
+        case kPdeShallowWater:
+            if (L.dim != 2) return hipErrorInvalidValue;
+            return launch_typed<2, ShallowWaterPDE>(L, ShallowWaterPDE::Params{c[0], c[1]}, stream);
+        case kPdeAdvection:
+            if (L.dim == 2) return launch_typed<2, AdvectionPDE>(L, AdvectionPDE::Params{{c[0], c[1], c[2]}}, stream);
+            return launch_typed<3, AdvectionPDE>(L, AdvectionPDE::Params{{c[0], c[1], c[2]}}, stream);
+        case kPdeAcoustics:
+            if (L.dim == 2)
+                return launch_typed<2, AcousticsPDE<2, false>>(L, {c[0], c[1], c[2]}, stream);
+            return launch_typed<3, AcousticsPDE<3, false>>(L, {c[0], c[1], c[2]}, stream);
+        case kPdeAcousticsNcp:
+            if (L.dim == 2)
+                return launch_typed<2, AcousticsPDE<2, true>>(L, {c[0], c[1], c[2]}, stream);
+            return launch_typed<3, AcousticsPDE<3, true>>(L, {c[0], c[1], c[2]}, stream);
+        default:
+            return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -283,12 +348,27 @@ int default_block(int p, int dim) {
 }
 
 size_t update_lds_bytes(int dim, int nq, int block) {
-    const int words = (dim == 2) ? (nq == 5 ? Lds<2, 5>::kWords : Lds<2, 4>::kWords) : Lds<3, 5>::kWords;
+    const int words = (dim == 2) ? (nq == 5 ? Lds<2, EulerPDE<5>>::kWords : Lds<2, EulerPDE<4>>::kWords)
+                                 : Lds<3, EulerPDE<5>>::kWords;
     return sizeof(double) * (size_t)words * (size_t)block;
+}
+
+size_t pde_min_lds_bytes(int pde, int dim, int p) {
+    const int B = ((plane_lanes(p, dim) + 63) / 64) * 64;  // the smallest block holding one patch
+    switch (pde) {
+        case kPdeShallowWater: return pde_lds_bytes<2, ShallowWaterPDE>(B);
+        case kPdeAdvection: return dim == 2 ? pde_lds_bytes<2, AdvectionPDE>(B) : pde_lds_bytes<3, AdvectionPDE>(B);
+        case kPdeAcoustics:
+            return dim == 2 ? pde_lds_bytes<2, AcousticsPDE<2, false>>(B) : pde_lds_bytes<3, AcousticsPDE<3, false>>(B);
+        case kPdeAcousticsNcp:
+            return dim == 2 ? pde_lds_bytes<2, AcousticsPDE<2, true>>(B) : pde_lds_bytes<3, AcousticsPDE<3, true>>(B);
+        default: return update_lds_bytes(dim, 5, B);
+    }
 }
 
 hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream) {
     if (L.num_items <= 0) return hipSuccess;
+    if (L.pde != kPdeEuler) return launch_pde(L, stream);
     // kernel: 0 default, 1 block, 2 wave, 3 tile, 4 fixed-size wave (2D and 3D)
     if (L.dim == 2 && L.kernel == 2) return wave2d_fits(L.p) ? launch_update2d(L, stream) : hipErrorInvalidConfiguration;
     if (L.dim == 2 && L.kernel == 3) return tile2d_fits(L.p) ? launch_update2d_tile(L, stream) : hipErrorInvalidConfiguration;
@@ -299,9 +379,9 @@ hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream) {
     if (L.dim == 2 && L.kernel == 0 && wave2d_fixed(L.p, L.nq)) return launch_update2d_fixed(L, stream);
     if (L.dim == 3 && L.kernel == 0 && wave3d_fixed(L.p, L.nq)) return launch_update3d_fixed(L, stream);
     if (L.dim == 2 && L.kernel == 0 && wave2d_fits(L.p)) return launch_update2d(L, stream);
-    if (L.dim == 2 && L.nq == 5) return launch_typed<2, 5>(L, stream);
-    if (L.dim == 2 && L.nq == 4) return launch_typed<2, 4>(L, stream);
-    if (L.dim == 3 && L.nq == 5) return launch_typed<3, 5>(L, stream);
+    if (L.dim == 2 && L.nq == 5) return launch_euler<2, 5>(L, stream);
+    if (L.dim == 2 && L.nq == 4) return launch_euler<2, 4>(L, stream);
+    if (L.dim == 3 && L.nq == 5) return launch_euler<3, 5>(L, stream);
     return hipErrorInvalidValue;
 }
 

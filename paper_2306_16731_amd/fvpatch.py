@@ -39,7 +39,7 @@ EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_c
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
            "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_mesh_create",
            "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_flavour_update",
-           "fv_host_patches_update", "fv_status_string",
+           "fv_host_patches_update", "fv_pde_unknowns", "fv_pde_batch_update", "fv_status_string",
            "fv_last_error", "fv_version"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
@@ -52,6 +52,13 @@ FV_KERNEL_FIXED = 4
 FV_FLAVOUR_BATCHED = 1
 FV_FLAVOUR_PATCH_WISE = 2
 FV_FLAVOUR_TASK_GRAPH = 3
+FV_PDE_EULER = 0
+FV_PDE_SHALLOW_WATER = 1
+FV_PDE_ADVECTION = 2
+FV_PDE_ACOUSTICS = 3
+FV_PDE_ACOUSTICS_NCP = 4
+PDE_IDS = {"euler": FV_PDE_EULER, "shallow_water": FV_PDE_SHALLOW_WATER, "advection": FV_PDE_ADVECTION,
+           "acoustics": FV_PDE_ACOUSTICS, "acoustics_ncp": FV_PDE_ACOUSTICS_NCP}
 FV_TRANSFER_PIPELINED = 0
 FV_TRANSFER_PER_PATCH = 1
 FV_TRANSFER_STAGED = 2
@@ -186,6 +193,10 @@ def load(path: str = LIBRARY):
     lib.fv_host_patches_update.argtypes = [vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp,
                                            ctypes.POINTER(fv_transfer_config), ctypes.POINTER(fv_transfer_stats)]
     lib.fv_host_patches_update.restype = ctypes.c_int
+    lib.fv_pde_unknowns.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.fv_pde_unknowns.restype = ctypes.c_int
+    lib.fv_pde_batch_update.argtypes = [i32, vp, i32, vp, vp, vp, vp, i32, i32, f64, f64, u32, vp, vp]
+    lib.fv_pde_batch_update.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -373,6 +384,28 @@ def fv_flavour_update(flavour: int, patches_in, patches_out, sizes, offsets, num
                                   int(num_patches), int(dim), int(unknowns), float(dt), float(h), float(gamma),
                                   int(flags), _dev_ptr(lambda_out), _stream_handle(stream))
     del sz, of
+    return _check(st) if raise_on_error else st
+
+
+# ---------------------------------------------------------------- other PDEs (the generic solver)
+def fv_pde_unknowns(pde: int, dim: int) -> tuple[int, int]:
+    """(unknowns per volume, number of parameters) of a built-in PDE."""
+    nq, npr = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().fv_pde_unknowns(int(pde), int(dim), ctypes.byref(nq), ctypes.byref(npr)))
+    return nq.value, npr.value
+
+
+def fv_pde_batch_update(pde: int, params, patches_in, patches_out, sizes, offsets, num_patches: int, dim: int,
+                        dt: float, h: float, flags: int = 0, lambda_out=None, stream=None,
+                        raise_on_error: bool = True) -> int:
+    """One explicit Euler step of every patch for the PDE `pde` (see include/fvpatch.h)."""
+    pr, pr_p = _host_array(params, np.float64)
+    sz, sz_p = _host_array(sizes, np.int32)
+    of, of_p = _host_array(offsets, np.int64)
+    st = load().fv_pde_batch_update(int(pde), pr_p, 0 if pr is None else len(pr), _dev_ptr(patches_in),
+                                    _dev_ptr(patches_out), sz_p, of_p, int(num_patches), int(dim), float(dt),
+                                    float(h), int(flags), _dev_ptr(lambda_out), _stream_handle(stream))
+    del pr, sz, of
     return _check(st) if raise_on_error else st
 
 

@@ -305,3 +305,39 @@ def test_host_patches_alignment():
     odd = np.array([raw.ctypes.data + 4, raw.ctypes.data + 8 * n + 8], np.uintp)   # 4 bytes off
     assert F.fv_host_patches_update(src, odd, [4, 4], 2, 2, 5, 1e-3, 0.1, 1.4,
                                     raise_on_error=False) == F.FV_ERR_INVALID_ARG
+
+
+def test_pde_shapes_and_validation_before_device():
+    assert F.fv_pde_unknowns(F.FV_PDE_EULER, 3) == (5, 1)
+    assert F.fv_pde_unknowns(F.FV_PDE_SHALLOW_WATER, 2) == (4, 2)
+    assert F.fv_pde_unknowns(F.FV_PDE_ADVECTION, 3) == (1, 3)
+    assert F.fv_pde_unknowns(F.FV_PDE_ACOUSTICS, 2) == (3, 2)
+    assert F.fv_pde_unknowns(F.FV_PDE_ACOUSTICS_NCP, 3) == (4, 2)
+    with pytest.raises(F.FvError):
+        F.fv_pde_unknowns(F.FV_PDE_SHALLOW_WATER, 3)
+    with pytest.raises(F.FvError):
+        F.fv_pde_unknowns(5, 2)
+
+    def call(pde, prm, dim=2, n=1, **kw):
+        a = dict(patches_in=IN, patches_out=OUT, sizes=[4] * n, offsets=None, num_patches=n, dim=dim, dt=1e-3,
+                 h=0.1, lambda_out=None, stream=0)
+        a.update(kw)
+        return F.fv_pde_batch_update(pde, prm, raise_on_error=False, **a)
+
+    assert call(F.FV_PDE_SHALLOW_WATER, [9.81, 0.0], dim=3) == F.FV_ERR_UNSUPPORTED
+    assert call(F.FV_PDE_SHALLOW_WATER, [9.81, 0.0, 1.0]) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_SHALLOW_WATER, [0.0, 0.0]) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_ACOUSTICS, [1.0, -2.0]) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, np.inf]) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0], dt=0.0) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0], flags=8) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0], patches_out=IN) == F.FV_ERR_OVERLAP
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0], sizes=[0]) == F.FV_ERR_INVALID_ARG
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0], n=0, sizes=None) == F.FV_OK
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0]) == F.FV_ERR_NO_DEVICE
