@@ -1,5 +1,8 @@
 // fv_update3d.hip -- 3D patch update with a whole patch cross-section in one wavefront.
 //
+// Two lane mappings: the interior-mapped form (p = 4, 8; described at
+// wave_update3d_i) and the pair-mapped form below (p = 6).
+//
 // The same step as the other kernels (conservative update of Sec. 2.2 with
 // the Rusanov flux of Eq. 2 and the Euler user terms; per-patch eigenvalue
 // of the new state), for small 3D patches: compile-time p with p + 2 even and
@@ -394,6 +397,304 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
     }
 }
 
+// Interior-mapped form for p with p^2 dividing 64 (p = 4, 8): a lane owns ONE
+// interior volume (i, j) of the cross-section, so a patch takes p^2 lanes
+// (all 64 for p = 8, four patches per wave for p = 4) and no lane works on a
+// halo or corner slot.  The face halos enter through the boundary lanes: a
+// lane with i = 1 or i = p also reads the x face-halo volume beside it and
+// forms that boundary face itself, likewise in y; z halos are the first and
+// last layer of the march.  Per layer a lane evaluates its volume's user
+// terms, its x face to the left (from the lane to the left by DPP, or from
+// its halo volume) and its y face below (from the lane p positions down by
+// ds_bpermute, or from its halo volume); the faces to the right and above
+// come back from the neighbouring lanes, or from the boundary face.  Each
+// face is the same Rusanov evaluation of the same two states as in the other
+// kernels, so results are equal bit for bit.  The output goes through the
+// same LDS ring and bursts as the pair-mapped form.
+template <int P>
+struct Shape3i {
+    static constexpr int W = P + 2;
+    static constexpr int LP = P * P;         // lanes per patch
+    static constexpr int ppw = 64 / LP;      // patches per wave
+    static constexpr int PLANE = W * W * 5;  // doubles per layer
+    static constexpr int PF = 1;             // layers in flight per lane (halos included: 15 doubles)
+    static constexpr int R = 2;              // layers per burst
+    static constexpr int ring_words = ppw * R * PLANE + ppw;
+    // a burst of R interior layers without halos, in 8-byte chunks: per lane
+    static constexpr int CHUNKS = ppw * R * P * P * 5;
+    static constexpr int ITERS = (CHUNKS + 63) / 64;
+    static_assert(64 % LP == 0, "needs p^2 dividing 64");
+    static_assert(P % R == 0, "bursts of whole rings");
+};
+
+template <int P, int VEC, bool PERIODIC, bool MESH = false>
+__device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, double *__restrict__ out,
+                                                const int64_t *__restrict__ offsets,
+                                                const int64_t *__restrict__ out_offsets,
+                                                const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
+                                                int64_t stride, double r, double gamma,
+                                                double *__restrict__ lambda_out, double *ring,
+                                                MeshArgs mesh = MeshArgs{}) {
+    static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
+    using S = Shape3i<P>;
+    constexpr int NQ = 5;
+    constexpr int W = S::W, LP = S::LP, ppw = S::ppw, PLANE = S::PLANE, PF = S::PF, R = S::R;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int slot = lane / LP;
+    const int l = lane - slot * LP;
+    const int j = 1 + l / P;
+    const int i = 1 + (l - (j - 1) * P);
+    const int64_t item = item0 + slot;
+    const bool active = item < num_items;
+    const int64_t self = active ? item : item0;
+    const int64_t off = offsets ? offsets[self] : self * stride;
+    const int64_t off_out = out_offsets ? out_offsets[self] : off;
+    const bool xlo = i == 1, xhi = i == P, ylo = j == 1, yhi = j == P;
+    // the lane's volume, its x and y face-halo volumes (its own volume where it has none), and
+    // (mesh form) its volume's z neighbours in layers 0 and p + 1
+    const double *own = in + off + (int64_t)(j * W + i) * NQ;
+    const double *xh = in + off + (int64_t)(j * W + (xlo ? 0 : (xhi ? P + 1 : i))) * NQ;
+    const double *yh = in + off + (int64_t)((ylo ? 0 : (yhi ? P + 1 : j)) * W + i) * NQ;
+    const double *z0 = own, *zw = own + (int64_t)(W - 1) * PLANE;
+    double ratio = r;  // dt / h of the lane's patch
+    if constexpr (MESH) {
+        const int32_t *nb = mesh.neighbors + 6 * self;
+        auto base = [&](int32_t q) { return in + (offsets ? offsets[q >= 0 ? q : self] : (q >= 0 ? q : self) * stride); };
+        if (xlo && nb[0] >= 0) xh = base(nb[0]) + (int64_t)(j * W + P) * NQ;
+        if (xhi && nb[1] >= 0) xh = base(nb[1]) + (int64_t)(j * W + 1) * NQ;
+        if (ylo && nb[2] >= 0) yh = base(nb[2]) + (int64_t)(P * W + i) * NQ;
+        if (yhi && nb[3] >= 0) yh = base(nb[3]) + (int64_t)(W + i) * NQ;
+        if (nb[4] >= 0) z0 = base(nb[4]) + (int64_t)P * PLANE + (int64_t)(j * W + i) * NQ;
+        if (nb[5] >= 0) zw = base(nb[5]) + (int64_t)PLANE + (int64_t)(j * W + i) * NQ;
+        ratio = mesh.dt[self] / mesh.h[self];
+    }
+    // layer k: the lane's volume (x = 0), its x halo (x = 1) and its y halo (x = 2); the halos
+    // only for the interior layers 1 .. p
+    auto load_layer = [&](int k, double (&q)[3][NQ]) {
+        load_volume<NQ>(k == 0 ? z0 : (k == W - 1 ? zw : own + (int64_t)k * PLANE), q[0]);
+        if (k >= 1 && k <= P) {
+            load_volume<NQ>(xh + (int64_t)k * PLANE, q[1]);
+            load_volume<NQ>(yh + (int64_t)k * PLANE, q[2]);
+        }
+    };
+    const int below = lane >= P ? lane - P : lane;    // row j - 1 (used for j >= 2)
+    const int above = lane + P < 64 ? lane + P : lane;  // row j + 1 (used for j <= p - 1)
+
+    int64_t *bases = reinterpret_cast<int64_t *>(ring + ppw * R * PLANE);
+    wave_fence();
+    if (l == 0) bases[slot] = off_out;
+    wave_fence();
+
+    // Store table of the bursts without periodic halos: the ring holds layers in the patch's
+    // own layout, so chunk c of a burst sits at the same offset q from the burst's first layer
+    // in LDS and in the patch; entry jj = (slot << 12) | q for chunk lane + 64 jj (spare lanes
+    // repeat the last chunk), two 16-bit entries per register.  Built once, it replaces the
+    // per-burst index arithmetic.
+    static_assert(2 * PLANE <= 4096 && ppw <= 16, "table entries take 12 + 4 bits");
+    int tab[(S::ITERS + 1) / 2];
+#pragma unroll
+    for (int t = 0; t < (S::ITERS + 1) / 2; ++t) tab[t] = 0;
+    if constexpr (!PERIODIC) {
+        constexpr int per_row = P * NQ, per_layer = P * per_row, per_slot = R * per_layer;
+#pragma unroll
+        for (int jj = 0; jj < S::ITERS; ++jj) {
+            const int c = lane + 64 * jj < S::CHUNKS ? lane + 64 * jj : S::CHUNKS - 1;
+            const int sl = c / per_slot;
+            int rem = c - sl * per_slot;
+            const int ly = rem / per_layer;
+            rem -= ly * per_layer;
+            const int row = rem / per_row;
+            const int e = rem - row * per_row;
+            tab[jj >> 1] |= ((sl << 12) | (ly * PLANE + ((row + 1) * W + 1) * NQ + e)) << (16 * (jj & 1));
+        }
+    }
+
+    double qprev[NQ], fzprev[NQ], fhzprev[NQ], dprev[NQ], lzprev = 0.0;
+    rest_state<NQ>(qprev);
+    rest_state<NQ>(fzprev);
+    rest_state<NQ>(fhzprev);
+    rest_state<NQ>(dprev);
+    double lmax = 0.0;
+
+    double qbuf[PF][3][NQ];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) load_layer(t, qbuf[t]);
+
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double q[NQ], qx[NQ], qy[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            q[c] = qbuf[k % PF][0][c];
+            qx[c] = qbuf[k % PF][1][c];
+            qy[c] = qbuf[k % PF][2][c];
+        }
+        if (k + PF < W) load_layer(k + PF, qbuf[k % PF]);
+
+        const Prim a = primitives<NQ>(q, gamma);
+        // z: the face between layers k - 1 and k
+        double fz[NQ], lz, fhz[NQ];
+        euler_flux<NQ>(q, a, 2, fz, lz);
+        rusanov<NQ>(qprev, fzprev, lzprev, q, fz, lz, fhz);
+        if (k >= 2) {
+            const int kk = k - 1;         // layer completed now
+            const int rr = (kk - 1) % R;  // its place in the ring
+            double *lay = ring + (slot * R + rr) * PLANE;
+            if (active) {
+                double dsum[NQ], qn[NQ];
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) dsum[c] = dprev[c] + (fhzprev[c] - fhz[c]);
+                advance<NQ>(qprev, dsum, ratio, qn);
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) lay[(j * W + i) * NQ + c] = qn[c];
+                if (PERIODIC) {
+                    // face-halo copies inside the layer (edges never)
+                    if (xhi)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lay[(j * W) * NQ + c] = qn[c];
+                    if (xlo)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lay[(j * W + P + 1) * NQ + c] = qn[c];
+                    if (yhi)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lay[i * NQ + c] = qn[c];
+                    if (ylo)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lay[((P + 1) * W + i) * NQ + c] = qn[c];
+                }
+                if (lambda_out) lmax = nanmax(lmax, volume_lambda<3, NQ>(qn, gamma));
+            }
+            if (rr == R - 1 || kk == P) {
+                const int nl = rr + 1;
+                const int k0 = kk - rr;  // first layer in the ring
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+                wave_fence();
+                auto ring_layer = [&](int sl, int ly) { return (sl * R + ly) * PLANE; };
+                if (PERIODIC) {
+                    auto body = [&](auto NLc) {
+                        constexpr int NL = decltype(NLc)::value;
+                        burst<VEC, ppw, NL, 1, P * W * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int ly, int) { return ring_layer(sl, ly) + W * NQ; },
+                            [&](int ly, int) { return (int64_t)(k0 + ly) * PLANE + W * NQ; });
+                        burst<1, ppw, NL, 2, P * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int ly, int run) { return ring_layer(sl, ly) + (run * (P + 1) * W + 1) * NQ; },
+                            [&](int ly, int run) { return (int64_t)(k0 + ly) * PLANE + (run * (P + 1) * W + 1) * NQ; });
+                    };
+                    if (nl == R) body(std::integral_constant<int, R>{});
+                    else body(std::integral_constant<int, 1>{});
+#pragma unroll
+                    for (int hz = 0; hz < 2; ++hz) {
+                        if (hz == 0 ? k0 != 1 : kk != P) continue;
+                        const int from = hz == 0 ? 0 : rr;
+                        const int dest = hz == 0 ? P + 1 : 0;
+                        burst<1, ppw, 1, P, P * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int, int run) { return ring_layer(sl, from) + ((run + 1) * W + 1) * NQ; },
+                            [&](int, int run) { return (int64_t)dest * PLANE + ((run + 1) * W + 1) * NQ; });
+                    }
+                } else {
+                    // every burst holds R layers (p is a multiple of R): the table's chunks
+                    (void)nl;
+                    const int64_t layer0 = (int64_t)k0 * PLANE;
+#pragma unroll
+                    for (int jj = 0; jj < S::ITERS; ++jj) {
+                        const int ent = (tab[jj >> 1] >> (16 * (jj & 1))) & 0xFFFF;
+                        const int qoff = ent & 0xFFF;
+                        int sl = ent >> 12;
+                        sl = item0 + sl < num_items ? sl : 0;
+                        const int64_t base = ppw == 1 ? off_out : bases[sl];
+                        __builtin_nontemporal_store(ring[sl * R * PLANE + qoff], out + base + layer0 + qoff);
+                    }
+                }
+                wave_fence();
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            qprev[c] = q[c];
+            fzprev[c] = fz[c];
+            fhzprev[c] = fhz[c];
+        }
+        lzprev = lz;
+        if (k == 0 || k == W - 1) continue;  // z halo layers: no in-plane faces
+        __builtin_amdgcn_sched_barrier(0);
+
+        // x: the face to the left from the lane to the left, or (i = 1) from the halo; the face
+        // to the right from the lane to the right, or (i = p) the boundary face with the halo
+        double din[NQ];
+        {
+            double fx[NQ], lx, fh[NQ], lh, qL[NQ], fL[NQ], fleft[NQ], fbound[NQ];
+            euler_flux<NQ>(q, a, 0, fx, lx);
+            const Prim ah = primitives<NQ>(qx, gamma);
+            euler_flux<NQ>(qx, ah, 0, fh, lh);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                const double ql = lane_left(q[c]), fl = lane_left(fx[c]);
+                qL[c] = xlo ? qx[c] : ql;
+                fL[c] = xlo ? fh[c] : fl;
+            }
+            const double ll = lane_left(lx);
+            rusanov<NQ>(qL, fL, xlo ? lh : ll, q, fx, lx, fleft);
+            rusanov<NQ>(q, fx, lx, qx, fh, lh, fbound);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                const double fr = lane_right(fleft[c]);
+                din[c] = fleft[c] - (xhi ? fbound[c] : fr);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // y: the face below from row j - 1, or (j = 1) from the halo; the face above from
+        // row j + 1, or (j = p) the boundary face with the halo
+        {
+            double fy[NQ], ly, fh[NQ], lh, qS[NQ], fS[NQ], fbelow[NQ], fbound[NQ];
+            euler_flux<NQ>(q, a, 1, fy, ly);
+            const Prim ah = primitives<NQ>(qy, gamma);
+            euler_flux<NQ>(qy, ah, 1, fh, lh);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                const double qs = lane_from(q[c], below), fs = lane_from(fy[c], below);
+                qS[c] = ylo ? qy[c] : qs;
+                fS[c] = ylo ? fh[c] : fs;
+            }
+            const double ls = lane_from(ly, below);
+            rusanov<NQ>(qS, fS, ylo ? lh : ls, q, fy, ly, fbelow);
+            rusanov<NQ>(q, fy, ly, qy, fh, lh, fbound);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                const double fa = lane_from(fbelow[c], above);
+                dprev[c] = din[c] + (fbelow[c] - (yhi ? fbound[c] : fa));
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    if (lambda_out) {
+        // segmented maximum over the lanes of each patch (LP a power of two, patches aligned)
+        for (int o = LP / 2; o >= 1; o >>= 1) lmax = nanmax(lmax, __shfl_xor(lmax, o, 64));
+        if (active && l == 0) lambda_out[ids ? ids[item] : item] = lmax;
+    }
+}
+
+// p = 4 and 8 take the interior-mapped form, p = 6 (36 lanes: a wave would idle 28) the pair-mapped one.
+template <int P>
+constexpr bool kInteriorMapped = (P == 4 || P == 8);
+
+template <int P>
+constexpr int wave3d_ppw() {
+    if constexpr (kInteriorMapped<P>) return Shape3i<P>::ppw;
+    else return Shape3<P>::ppw;
+}
+
+template <int P>
+constexpr int wave3d_ring_words() {
+    if constexpr (kInteriorMapped<P>) return Shape3i<P>::ring_words;
+    else return Shape3<P>::ring_words;
+}
+
 template <int P, int VEC, bool PERIODIC, bool MESH>
 __global__ void __launch_bounds__(kBlock3)
 update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
@@ -401,19 +702,27 @@ update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
                       int64_t stride, double r, const double *__restrict__ r_dev, double gamma,
                       double *__restrict__ lambda_out, MeshArgs mesh) {
     extern __shared__ double lds[];
-    const int64_t item0 = (int64_t)blockIdx.x * Shape3<P>::ppw;
-    if (item0 >= num_items) return;
     const double rr = r_dev ? *r_dev : r;
-    wave_update3d<P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
-                                          lambda_out, lds, mesh);
+    if constexpr (kInteriorMapped<P>) {
+        const int64_t item0 = (int64_t)blockIdx.x * Shape3i<P>::ppw;
+        if (item0 >= num_items) return;
+        wave_update3d_i<P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr,
+                                                gamma, lambda_out, lds, mesh);
+    } else {
+        const int64_t item0 = (int64_t)blockIdx.x * Shape3<P>::ppw;
+        if (item0 >= num_items) return;
+        wave_update3d<P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, gamma,
+                                              lambda_out, lds, mesh);
+    }
 }
 
 template <int P, int VEC, bool PERIODIC, bool MESH = false>
 hipError_t launch3d(const UpdateLaunch &L, hipStream_t stream) {
-    using S = Shape3<P>;
-    const int64_t blocks = ((int64_t)L.num_items + S::ppw - 1) / S::ppw;
+    constexpr int ppw = wave3d_ppw<P>();
+    constexpr int words = wave3d_ring_words<P>();
+    const int64_t blocks = ((int64_t)L.num_items + ppw - 1) / ppw;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const size_t lds = sizeof(double) * (size_t)S::ring_words;
+    const size_t lds = sizeof(double) * (size_t)words;
     hipLaunchKernelGGL((update3d_fixed_kernel<P, VEC, PERIODIC, MESH>), dim3((unsigned)blocks), dim3(kBlock3), lds,
                        stream, L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev,
                        L.gamma, L.lambda_out, L.mesh);
