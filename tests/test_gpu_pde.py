@@ -74,6 +74,8 @@ CASES = [  # (name, dim, sizes)
     ("shallow_water", 2, [16] * 9),
     ("shallow_water", 2, [3, 17, 5, 64, 9, 1, 31]),
     ("advection", 2, [8] * 11),
+    ("advection", 2, [16] * 7),                 # the 2D wave form (p = 16)
+    ("acoustics", 2, [16] * 4 + [7]),           # wave form and plane-marching kernel in one batch
     ("advection", 3, [4, 7, 12, 24, 1, 5]),
     ("acoustics", 2, [9, 33, 2, 62]),
     ("acoustics", 3, [6] * 7 + [13]),
@@ -146,12 +148,19 @@ def test_ncp_form_equals_flux_form(dim):
     pc.check_ncp_form_equals_flux_form(gpu_update, dim)
 
 
-def test_shallow_water_pins():
-    _announce("lake at rest / conservation / swap / coriolis")
-    pc.check_lake_at_rest(gpu_update)
-    pc.check_swe_conservation(gpu_update)
-    pc.check_swe_swap_xy(gpu_update)
-    pc.check_coriolis(gpu_update)
+@pytest.mark.parametrize("p", [16, 10])   # the 2D wave form and the plane-marching kernel
+def test_shallow_water_pins(p):
+    _announce(f"lake at rest / conservation / swap / coriolis p={p}")
+    pc.check_lake_at_rest(gpu_update, p=p)
+    pc.check_swe_conservation(gpu_update, p=p)
+    pc.check_swe_swap_xy(gpu_update, p=p)
+    pc.check_coriolis(gpu_update, p=p)
+
+
+@pytest.mark.parametrize("name", ["advection", "acoustics", "acoustics_ncp"])
+def test_fourier_mode_wave_form(name):
+    _announce(f"fourier {name} 2D p=16")
+    pc.check_fourier_mode(gpu_update, name, 2, p=16, modes=((1, 2, 0), (5, 3, 0), (8, 8, 0)))
 
 
 def test_dam_break_converges_to_stoker():
