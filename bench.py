@@ -415,8 +415,9 @@ def bench_transfer(args) -> int:
     heap) through one step on the GPU and back: per-patch synchronous copies into recycled
     device memory, the pipelined form (host threads each carrying chunks through gather into
     pinned staging, async copies, update, copy back and scatter, overlapped), and the staged
-    form (threaded gather of the whole batch, one copy each way, no overlap); against the
-    device-resident step (no transfers) and the
+    form (threaded gather of the whole batch, one copy each way, no overlap), and zero copy (the
+    same patches in pinned memory from fv_host_alloc, read and written over PCIe by gather /
+    scatter kernels); against the device-resident step (no transfers) and the
     copy engines' own ceiling (pinned host <-> device copies of the same bytes, each
     direction alone and both at once).  Wall time per step between synchronisations."""
     import numpy as np
@@ -501,6 +502,33 @@ def bench_transfer(args) -> int:
                                            config={"mode": fvpatch.FV_TRANSFER_PER_PATCH})
 
         res["per_patch_ms_full_batch"] = wall(per_patch, 1, 2) * T / pp_T
+        # zero copy: the same patches in pinned memory from fv_host_alloc (shuffled placement)
+        a_in, a_out = fvpatch.fv_host_alloc(nbytes), fvpatch.fv_host_alloc(nbytes)
+        try:
+            big_in, big_out = fvpatch.pinned_array(a_in, nbytes // 8), fvpatch.pinned_array(a_out, nbytes // 8)
+            n = nbytes // 8 // T
+            place = np.random.Generator(np.random.PCG64(args.seed + 1)).permutation(T)
+            zsrc = [big_in[place[t] * n:(place[t] + 1) * n] for t in range(T)]
+            zdst = [big_out[place[t] * n:(place[t] + 1) * n] for t in range(T)]
+            for t in range(T):
+                zsrc[t][:] = src[t]
+            zin, zout = fvpatch.host_pointer_table(zsrc), fvpatch.host_pointer_table(zdst)
+
+            def zero_copy(cfg):
+                fvpatch.fv_host_patches_update(zin, zout, b.sizes, T, dim, nq, dt, h, gamma, 0, lam,
+                                               config=dict(cfg, mode=fvpatch.FV_TRANSFER_ZERO_COPY))
+
+            res["zero_copy_ms"] = wall(lambda: zero_copy({}), 3, 11)
+            zsweep = []
+            for chunk_mb, slots in ((4, 2), (16, 2), (32, 2), (8, 4), (8, 8), (32, 4)):
+                cfg = {"chunk_bytes": chunk_mb << 20, "slots": slots}
+                zsweep.append({"chunk_MiB": chunk_mb, "slots": slots,
+                               "ms": round(wall(lambda cfg=cfg: zero_copy(cfg), 1, 5), 3)})
+            res["zero_copy_sweep"] = zsweep
+            del zsrc, zdst, big_in, big_out
+        finally:
+            fvpatch.fv_host_free(a_in)
+            fvpatch.fv_host_free(a_out)
         moved = 2 * nbytes + 8 * T
         ms = res["pipelined_ms"]
         line = {"metric": "cell-updates/s", "form": "transfer", "value": round(cells / (ms / 1e3), 1),
@@ -516,6 +544,9 @@ def bench_transfer(args) -> int:
                 "host_copy_ms": round(res["pipelined_host_copy_ms"], 3),
                 "pinned_h2d_GBs": res["pinned_h2d_GBs"], "pinned_d2h_GBs": res["pinned_d2h_GBs"],
                 "pinned_both_GBs": res["pinned_both_GBs"], "sweep": sweep,
+                "zero_copy_ms_per_step": round(res["zero_copy_ms"], 3),
+                "zero_copy_GBs": round(moved / (res["zero_copy_ms"] / 1e3) / 1e9, 2),
+                "zero_copy_sweep": res["zero_copy_sweep"],
                 "dtype": "f64", "data": "synthetic",
                 "config": {"workload": name, "patches": T, "p": p, "dim": dim,
                            "host_layout": "one allocation per patch, shuffled allocation order",

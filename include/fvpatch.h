@@ -58,6 +58,7 @@
 #ifndef FVPATCH_H
 #define FVPATCH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -450,6 +451,14 @@ fv_status fv_flavour_update(int32_t flavour, const double *patches_in, double *p
  *   FV_TRANSFER_STAGED     host_threads threads gather all patches into one
  *                          pinned buffer, one copy to the device, one launch,
  *                          one copy back, threaded scatter (bulk, no overlap);
+ *   FV_TRANSFER_ZERO_COPY  patches in pinned memory from fv_host_alloc (every
+ *                          patch, input and output, must lie in such a block;
+ *                          FV_ERR_INVALID_ARG otherwise): chunks of about
+ *                          chunk_bytes with `slots` in flight on the library's
+ *                          streams; per chunk a gather kernel reads the
+ *                          patches over PCIe into device memory, the update
+ *                          runs, a scatter kernel writes them back; no host
+ *                          copies (host_threads unused);
  *   FV_TRANSFER_PIPELINED  the batch cut into chunks of whole patches of about
  *                          chunk_bytes; each of host_threads threads takes
  *                          chunks in turn and carries each through gather into
@@ -467,7 +476,7 @@ fv_status fv_flavour_update(int32_t flavour, const double *patches_in, double *p
  * lambda_out: host [num_patches] or NULL.  dt, h, gamma, flags as in
  * fv_patch_batch_update; results equal its results bit for bit.
  * config: NULL = pipelined with the defaults; a 0 field = its default
- * (chunk_bytes 8 MiB, slots 2, host_threads 8).  Pinned staging and device
+ * (chunk_bytes 8 MiB, slots 2, host_threads 8; zero copy: 32 MiB, 4 slots).  Pinned staging and device
  * buffers are kept per device, grow-only, until the process ends: pipelined
  * 2 * host_threads * slots chunks of each kind, staged 2 batches of each.
  * stats: NULL or filled on success (bytes moved each way, wall time of the
@@ -484,12 +493,13 @@ fv_status fv_flavour_update(int32_t flavour, const double *patches_in, double *p
 #define FV_TRANSFER_PIPELINED 0
 #define FV_TRANSFER_PER_PATCH 1
 #define FV_TRANSFER_STAGED 2
+#define FV_TRANSFER_ZERO_COPY 3
 #define FV_TRANSFER_MAX_SLOTS 8
 #define FV_TRANSFER_MAX_THREADS 64
 
 typedef struct fv_transfer_config {
-    int64_t chunk_bytes;  /* staging chunk (pipelined), >= one patch; 0 = 8 MiB */
-    int32_t slots;        /* chunks in flight per thread (pipelined), 1 .. FV_TRANSFER_MAX_SLOTS; 0 = 2 */
+    int64_t chunk_bytes;  /* chunk (pipelined, zero copy), >= one patch; 0 = 8 MiB (zero copy 32 MiB) */
+    int32_t slots;        /* chunks in flight per thread (pipelined; zero copy: in all), 1 .. FV_TRANSFER_MAX_SLOTS; 0 = 2 (zero copy 4) */
     int32_t host_threads; /* threads incl. the caller's, 1 .. FV_TRANSFER_MAX_THREADS; 0 = 8 */
     int32_t mode;         /* FV_TRANSFER_* */
     int32_t reserved;     /* 0 */
@@ -501,6 +511,16 @@ typedef struct fv_transfer_stats {
     double seconds;           /* wall time of the call */
     double host_copy_seconds; /* gathering into / scattering from the staging, summed over threads */
 } fv_transfer_stats;
+
+/* Page-locked host memory for patches that the GPU reads and writes in place
+ * (FV_TRANSFER_ZERO_COPY): *ptr receives `bytes` (> 0) of host memory,
+ * 16-byte aligned, kept until fv_host_free.  Errors: FV_ERR_INVALID_ARG,
+ * FV_ERR_NO_DEVICE, FV_ERR_OOM. */
+fv_status fv_host_alloc(size_t bytes, void **ptr);
+
+/* Free memory from fv_host_alloc (NULL: no-op; FV_ERR_INVALID_ARG for any other
+ * pointer).  No call may be using it. */
+fv_status fv_host_free(void *ptr);
 
 fv_status fv_host_patches_update(const double *const *patches_in, double *const *patches_out, const int32_t *sizes,
                                  int32_t num_patches, int32_t dim, int32_t unknowns, double dt, double h,

@@ -31,6 +31,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -44,6 +45,8 @@ namespace {
 constexpr int64_t kDefaultChunk = 8ll << 20;
 constexpr int32_t kDefaultSlots = 2;
 constexpr int32_t kDefaultThreads = 8;
+constexpr int64_t kZeroCopyChunk = 32ll << 20;
+constexpr int32_t kZeroCopySlots = 4;
 
 // Fixed set of host threads running one job at a time: a job is `parts`
 // calls body(0) .. body(parts - 1), part 0 on the calling thread and part k
@@ -147,10 +150,27 @@ struct SlotSet {
     int32_t patches = 0;  // eigenvalues per slot
 };
 
+// Zero-copy chunk in flight: device copies of the chunk, its table of patch
+// pointers (host staging and device copy), its eigenvalues.
+struct ZSlot {
+    double *d_in = nullptr, *d_out = nullptr, *d_lam = nullptr, *h_lam = nullptr;
+    const double **h_ptr = nullptr, **d_ptr = nullptr;  // [2 * patches]: inputs, then outputs
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    int32_t first = 0, count = 0;
+};
+
+struct ZSlotSet {
+    std::vector<ZSlot> slots;
+    size_t doubles = 0;
+    int32_t patches = 0;
+};
+
 // Per-device state, grow-only, kept until the process ends.
 struct Transfer {
     std::mutex mu;
     SlotSet chunks;               // pipelined
+    ZSlotSet zchunks;             // zero copy
     SlotSet whole;                // staged: one slot for the whole batch
     double *d_all = nullptr;      // per patch: recycled device area
     size_t all_doubles = 0;
@@ -205,6 +225,50 @@ fv_status ensure_slots(SlotSet &set, int32_t slots, size_t doubles, int32_t patc
             set.doubles = 0;
             set.patches = 0;
             return fail(FV_ERR_OOM, "staging for %d chunks of %zu bytes", want_slots, b);
+        }
+    }
+    return FV_OK;
+}
+
+void free_zslot(ZSlot &s) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    if (s.d_in) (void)hipFree(s.d_in);
+    if (s.d_out) (void)hipFree(s.d_out);
+    if (s.d_lam) (void)hipFree(s.d_lam);
+    if (s.h_lam) (void)hipHostFree(s.h_lam);
+    if (s.h_ptr) (void)hipHostFree(s.h_ptr);
+    if (s.d_ptr) (void)hipFree(s.d_ptr);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    s = ZSlot{};
+}
+
+fv_status ensure_zslots(ZSlotSet &set, int32_t slots, size_t doubles, int32_t patches) {
+    if ((int32_t)set.slots.size() >= slots && set.doubles >= doubles && set.patches >= patches) return FV_OK;
+    const size_t want_doubles = std::max(set.doubles, doubles);
+    const int32_t want_patches = std::max(set.patches, patches);
+    const int32_t want_slots = std::max((int32_t)set.slots.size(), slots);
+    for (auto &z : set.slots) free_zslot(z);
+    set.slots.assign(want_slots, ZSlot{});
+    set.doubles = want_doubles;
+    set.patches = want_patches;
+    const size_t b = sizeof(double) * want_doubles, bl = sizeof(double) * want_patches;
+    const size_t bp = 2 * sizeof(double *) * want_patches;
+    for (auto &z : set.slots) {
+        const bool ok = hipMalloc(&z.d_in, b) == hipSuccess && hipMalloc(&z.d_out, b) == hipSuccess &&
+                        hipMalloc(&z.d_lam, bl) == hipSuccess &&
+                        hipHostMalloc(reinterpret_cast<void **>(&z.h_lam), bl, hipHostMallocDefault) == hipSuccess &&
+                        hipHostMalloc(reinterpret_cast<void **>(&z.h_ptr), bp, hipHostMallocDefault) == hipSuccess &&
+                        hipMalloc(reinterpret_cast<void **>(&z.d_ptr), bp) == hipSuccess &&
+                        hipStreamCreateWithFlags(&z.stream, hipStreamNonBlocking) == hipSuccess &&
+                        hipEventCreateWithFlags(&z.done, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            for (auto &y : set.slots) free_zslot(y);
+            set.slots.clear();
+            set.doubles = 0;
+            set.patches = 0;
+            return fail(FV_ERR_OOM, "zero-copy buffers for %d chunks of %zu bytes", want_slots, b);
         }
     }
     return FV_OK;
@@ -452,10 +516,190 @@ fv_status pipelined(Transfer &x, const Call &c, const fv_transfer_config &cfg, i
     return FV_OK;
 }
 
+// ------------------------------------------------------------------ pinned patch memory
+// Blocks handed out by fv_host_alloc, by host start address, with the address
+// the device uses for them.
+struct PinnedBlock {
+    size_t bytes;
+    double *dev;
+};
+std::mutex g_pin_mu;
+std::map<uintptr_t, PinnedBlock> g_pinned;
+
+// The device address of host range [p, p + bytes) if it lies inside one pinned
+// block, else null.
+const double *pinned_device(const void *p, size_t bytes) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    auto it = g_pinned.upper_bound(a);
+    if (it == g_pinned.begin()) return nullptr;
+    --it;
+    if (a + bytes > it->first + it->second.bytes) return nullptr;
+    return it->second.dev + (a - it->first) / sizeof(double);
+}
+
+// Patch t of a chunk from (device-visible) host memory into both device copies:
+// one block per patch, 16-byte moves where the patch and the copies allow them.
+__global__ void __launch_bounds__(256) gather_patches(const double *const *__restrict__ src, double *__restrict__ d_in,
+                                                      double *__restrict__ d_out, int64_t pd) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const int64_t t = blockIdx.x;
+    const double *s = src[t];
+    double *a = d_in + t * pd, *b = d_out + t * pd;
+    if (((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(a)) & 15u) == 0 && pd % 2 == 0) {
+        for (int64_t k = threadIdx.x; k < pd / 2; k += blockDim.x) {
+            const dv2 v = reinterpret_cast<const dv2 *>(s)[k];
+            reinterpret_cast<dv2 *>(a)[k] = v;
+            reinterpret_cast<dv2 *>(b)[k] = v;
+        }
+    } else {
+        for (int64_t k = threadIdx.x; k < pd; k += blockDim.x) {
+            const double v = s[k];
+            a[k] = v;
+            b[k] = v;
+        }
+    }
+}
+
+// Patch t of a chunk from the device copy to (device-visible) host memory.
+__global__ void __launch_bounds__(256) scatter_patches(const double *__restrict__ d_out, double *const *__restrict__ dst,
+                                                       int64_t pd) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const int64_t t = blockIdx.x;
+    const double *s = d_out + t * pd;
+    double *d = dst[t];
+    if (((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(d)) & 15u) == 0 && pd % 2 == 0) {
+        for (int64_t k = threadIdx.x; k < pd / 2; k += blockDim.x)
+            reinterpret_cast<dv2 *>(d)[k] = reinterpret_cast<const dv2 *>(s)[k];
+    } else {
+        for (int64_t k = threadIdx.x; k < pd; k += blockDim.x) d[k] = s[k];
+    }
+}
+
+// Patches in memory from fv_host_alloc: the GPU reads and writes them in place.  Chunks of
+// whole patches, `slots` of them in flight on their own streams: table of patch addresses up,
+// gather kernel (PCIe reads), update, scatter kernel (PCIe writes), eigenvalues down.
+fv_status zero_copy(Transfer &x, const Call &c, const fv_transfer_config &cfg, const std::vector<const double *> &din,
+                    const std::vector<const double *> &dout, fv_transfer_stats *stats) {
+    const int32_t per_chunk = (int32_t)std::min<int64_t>(cfg.chunk_bytes / (int64_t)c.pbytes, c.T);
+    const int32_t nchunks = (c.T + per_chunk - 1) / per_chunk;
+    const int32_t nslots = std::min<int32_t>(cfg.slots, nchunks);
+    fv_status st = ensure_zslots(x.zchunks, nslots, (size_t)per_chunk * c.pd, per_chunk);
+    if (st != FV_OK) return st;
+    const BatchShape uniform{true, c.p, 0, (int64_t)per_chunk * c.pd};
+    fv_status err = FV_OK;
+    auto retire = [&](ZSlot &z) {
+        if (z.count == 0) return;
+        const hipError_t e = hipEventSynchronize(z.done);
+        if (e != hipSuccess && err == FV_OK) err = fail(FV_ERR_LAUNCH, "chunk failed: %s", hipGetErrorString(e));
+        if (e == hipSuccess && c.lambda_out) std::memcpy(c.lambda_out + z.first, z.h_lam, sizeof(double) * z.count);
+        z.count = 0;
+    };
+    for (int32_t chunk = 0; chunk < nchunks && err == FV_OK; ++chunk) {
+        ZSlot &z = x.zchunks.slots[chunk % nslots];
+        retire(z);
+        if (err != FV_OK) break;
+        const int32_t first = chunk * per_chunk, count = std::min(per_chunk, c.T - first);
+        for (int32_t t = 0; t < count; ++t) {
+            z.h_ptr[t] = din[first + t];
+            z.h_ptr[count + t] = dout[first + t];
+        }
+        bool ok = hipMemcpyAsync(z.d_ptr, z.h_ptr, 2 * sizeof(double *) * count, hipMemcpyHostToDevice, z.stream) ==
+                  hipSuccess;
+        if (ok) {
+            hipLaunchKernelGGL(gather_patches, dim3((unsigned)count), dim3(256), 0, z.stream, z.d_ptr, z.d_in, z.d_out,
+                               c.pd);
+            ok = hipGetLastError() == hipSuccess;
+        }
+        if (ok) {
+            st = plain_update(z.d_in, z.d_out, c.sizes + first, nullptr, count, c.dim, c.nq, c.dt, c.h, c.gamma,
+                              c.flags, c.lambda_out ? z.d_lam : nullptr, z.stream, uniform, nullptr);
+            ok = st == FV_OK;
+        }
+        if (ok) {
+            hipLaunchKernelGGL(scatter_patches, dim3((unsigned)count), dim3(256), 0, z.stream, z.d_out,
+                               const_cast<double *const *>(z.d_ptr + count), c.pd);
+            ok = hipGetLastError() == hipSuccess;
+        }
+        if (ok && c.lambda_out)
+            ok = hipMemcpyAsync(z.h_lam, z.d_lam, sizeof(double) * count, hipMemcpyDeviceToHost, z.stream) ==
+                 hipSuccess;
+        if (ok) ok = hipEventRecord(z.done, z.stream) == hipSuccess;
+        if (!ok) {
+            err = st != FV_OK ? st : fail(FV_ERR_LAUNCH, "zero-copy chunk at patch %d failed", first);
+            (void)hipStreamSynchronize(z.stream);
+            (void)hipGetLastError();
+            break;
+        }
+        z.first = first;
+        z.count = count;
+    }
+    // every chunk in flight is waited for, also after an error
+    for (auto &z : x.zchunks.slots) {
+        if (err == FV_OK) {
+            retire(z);
+        } else if (z.count) {
+            (void)hipStreamSynchronize(z.stream);
+            z.count = 0;
+        }
+    }
+    if (err != FV_OK) return err;
+    if (stats) {
+        const int64_t n = (int64_t)c.T * (int64_t)c.pbytes;
+        stats->bytes_to_device = n;
+        stats->bytes_to_host = n + (c.lambda_out ? 8ll * c.T : 0);
+        stats->host_copy_seconds = 0.0;
+    }
+    return FV_OK;
+}
+
 }  // namespace
 }  // namespace fv
 
 using namespace fv;
+
+extern "C" fv_status fv_host_alloc(size_t bytes, void **ptr) {
+    clear_error();
+    if (!ptr) return fail(FV_ERR_INVALID_ARG, "ptr must be non-null");
+    *ptr = nullptr;
+    if (bytes == 0) return fail(FV_ERR_INVALID_ARG, "bytes must be > 0");
+    DeviceContext *ctx = nullptr;
+    fv_status st = current_context(&ctx);
+    if (st != FV_OK) return st;
+    void *h = nullptr;
+    if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FV_ERR_OOM, "pinned allocation of %zu bytes", bytes);
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return fail(FV_ERR_LAUNCH, "no device address for pinned memory");
+    }
+    {
+        std::lock_guard<std::mutex> g(g_pin_mu);
+        g_pinned[reinterpret_cast<uintptr_t>(h)] = PinnedBlock{bytes, static_cast<double *>(d)};
+    }
+    *ptr = h;
+    return FV_OK;
+}
+
+extern "C" fv_status fv_host_free(void *ptr) {
+    clear_error();
+    if (!ptr) return FV_OK;
+    {
+        std::lock_guard<std::mutex> g(g_pin_mu);
+        auto it = g_pinned.find(reinterpret_cast<uintptr_t>(ptr));
+        if (it == g_pinned.end()) return fail(FV_ERR_INVALID_ARG, "pointer was not returned by fv_host_alloc");
+        g_pinned.erase(it);
+    }
+    if (hipHostFree(ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FV_ERR_LAUNCH, "hipHostFree failed");
+    }
+    return FV_OK;
+}
 
 extern "C" fv_status fv_host_patches_update(const double *const *patches_in, double *const *patches_out,
                                             const int32_t *sizes, int32_t num_patches, int32_t dim, int32_t unknowns,
@@ -470,11 +714,14 @@ extern "C" fv_status fv_host_patches_update(const double *const *patches_in, dou
     fv_transfer_config cfg{kDefaultChunk, kDefaultSlots, kDefaultThreads, FV_TRANSFER_PIPELINED, 0};
     if (config) {
         cfg = *config;
-        if (cfg.chunk_bytes == 0) cfg.chunk_bytes = kDefaultChunk;
-        if (cfg.slots == 0) cfg.slots = kDefaultSlots;
+        // zero copy moves larger chunks on more streams (no host copies to overlap with)
+        const bool zc = cfg.mode == FV_TRANSFER_ZERO_COPY;
+        if (cfg.chunk_bytes == 0) cfg.chunk_bytes = zc ? kZeroCopyChunk : kDefaultChunk;
+        if (cfg.slots == 0) cfg.slots = zc ? kZeroCopySlots : kDefaultSlots;
         if (cfg.host_threads == 0) cfg.host_threads = kDefaultThreads;
     }
-    if (cfg.mode != FV_TRANSFER_PIPELINED && cfg.mode != FV_TRANSFER_PER_PATCH && cfg.mode != FV_TRANSFER_STAGED)
+    if (cfg.mode != FV_TRANSFER_PIPELINED && cfg.mode != FV_TRANSFER_PER_PATCH && cfg.mode != FV_TRANSFER_STAGED &&
+        cfg.mode != FV_TRANSFER_ZERO_COPY)
         return fail(FV_ERR_INVALID_ARG, "unknown transfer mode %d", cfg.mode);
     if (cfg.slots < 1 || cfg.slots > FV_TRANSFER_MAX_SLOTS)
         return fail(FV_ERR_INVALID_ARG, "slots must be in [1, %d]", FV_TRANSFER_MAX_SLOTS);
@@ -509,7 +756,19 @@ extern "C" fv_status fv_host_patches_update(const double *const *patches_in, dou
             if ((starts[k].second == 1 || starts[k - 1].second == 1) && starts[k].first - starts[k - 1].first < pbytes)
                 return fail(FV_ERR_OVERLAP, "an output patch overlaps another patch");
     }
-    if (cfg.mode == FV_TRANSFER_PIPELINED && cfg.chunk_bytes < (int64_t)pbytes)
+    // zero copy: every patch must lie in memory from fv_host_alloc (the kernels dereference it)
+    std::vector<const double *> zin, zout;
+    if (cfg.mode == FV_TRANSFER_ZERO_COPY) {
+        zin.resize(num_patches);
+        zout.resize(num_patches);
+        for (int32_t t = 0; t < num_patches; ++t) {
+            zin[t] = pinned_device(patches_in[t], pbytes);
+            zout[t] = pinned_device(patches_out[t], pbytes);
+            if (!zin[t] || !zout[t])
+                return fail(FV_ERR_INVALID_ARG, "patch %d does not lie in memory from fv_host_alloc", t);
+        }
+    }
+    if ((cfg.mode == FV_TRANSFER_PIPELINED || cfg.mode == FV_TRANSFER_ZERO_COPY) && cfg.chunk_bytes < (int64_t)pbytes)
         return fail(FV_ERR_INVALID_ARG, "chunk_bytes below one patch (%zu bytes)", pbytes);
     DeviceContext *ctx = nullptr;
     st = current_context(&ctx);
@@ -523,6 +782,7 @@ extern "C" fv_status fv_host_patches_update(const double *const *patches_in, dou
     switch (cfg.mode) {
         case FV_TRANSFER_PER_PATCH: st = per_patch(*x, c, stats); break;
         case FV_TRANSFER_STAGED: st = staged(*x, c, cfg.host_threads, stats); break;
+        case FV_TRANSFER_ZERO_COPY: st = zero_copy(*x, c, cfg, zin, zout, stats); break;
         default: st = pipelined(*x, c, cfg, dev, stats); break;
     }
     if (st == FV_OK && stats) stats->seconds = now_s() - t_start;

@@ -39,7 +39,7 @@ EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_c
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
            "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_mesh_create",
            "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_flavour_update",
-           "fv_host_patches_update", "fv_pde_unknowns", "fv_pde_batch_update", "fv_status_string",
+           "fv_host_patches_update", "fv_host_alloc", "fv_host_free", "fv_pde_unknowns", "fv_pde_batch_update", "fv_status_string",
            "fv_last_error", "fv_version"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
@@ -62,6 +62,7 @@ PDE_IDS = {"euler": FV_PDE_EULER, "shallow_water": FV_PDE_SHALLOW_WATER, "advect
 FV_TRANSFER_PIPELINED = 0
 FV_TRANSFER_PER_PATCH = 1
 FV_TRANSFER_STAGED = 2
+FV_TRANSFER_ZERO_COPY = 3
 FV_TRANSFER_MAX_SLOTS = 8
 FV_TRANSFER_MAX_THREADS = 64
 FIXED_SIZES_2D = (3, 5, 9, 16, 17)  # patch sizes with a fixed-size build (2D, unknowns = 5)
@@ -193,6 +194,10 @@ def load(path: str = LIBRARY):
     lib.fv_host_patches_update.argtypes = [vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp,
                                            ctypes.POINTER(fv_transfer_config), ctypes.POINTER(fv_transfer_stats)]
     lib.fv_host_patches_update.restype = ctypes.c_int
+    lib.fv_host_alloc.argtypes = [ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]
+    lib.fv_host_alloc.restype = ctypes.c_int
+    lib.fv_host_free.argtypes = [vp]
+    lib.fv_host_free.restype = ctypes.c_int
     lib.fv_pde_unknowns.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.fv_pde_unknowns.restype = ctypes.c_int
     lib.fv_pde_batch_update.argtypes = [i32, vp, i32, vp, vp, vp, vp, i32, i32, f64, f64, u32, vp, vp]
@@ -419,6 +424,27 @@ def host_pointer_table(patches) -> np.ndarray:
             raise ValueError(f"patch {t} must be a C-contiguous float64 numpy array")
         addrs[t] = a.ctypes.data
     return addrs
+
+
+def fv_host_alloc(nbytes: int, raise_on_error: bool = True):
+    """Pinned host memory for zero-copy patches: returns its address (int)."""
+    p = ctypes.c_void_p()
+    st = load().fv_host_alloc(int(nbytes), ctypes.byref(p))
+    if raise_on_error:
+        _check(st)
+        return p.value
+    return st, p.value
+
+
+def fv_host_free(addr, raise_on_error: bool = True) -> int:
+    st = load().fv_host_free(addr)
+    return _check(st) if raise_on_error else st
+
+
+def pinned_array(addr: int, n: int) -> np.ndarray:
+    """A float64 numpy view of n doubles at `addr` (memory from fv_host_alloc); the view
+    must not be used after fv_host_free."""
+    return np.ctypeslib.as_array((ctypes.c_double * n).from_address(addr))
 
 
 def fv_host_patches_update(patches_in, patches_out, sizes, num_patches: int, dim: int, unknowns: int, dt: float,

@@ -341,3 +341,23 @@ def test_pde_shapes_and_validation_before_device():
     except ImportError:
         pass
     assert call(F.FV_PDE_ADVECTION, [1.0, 0.0, 0.0]) == F.FV_ERR_NO_DEVICE
+
+
+def test_zero_copy_and_pinned_validation_before_device():
+    n = (4 + 2) ** 2 * 5
+    src = [np.zeros(n) for _ in range(2)]
+    dst = [np.zeros(n) for _ in range(2)]
+    # pageable patches are refused by the zero-copy mode before any device work
+    assert F.fv_host_patches_update(src, dst, [4, 4], 2, 2, 5, 1e-3, 0.1, 1.4,
+                                    config={"mode": F.FV_TRANSFER_ZERO_COPY},
+                                    raise_on_error=False) == F.FV_ERR_INVALID_ARG
+    assert F.fv_host_free(None) == F.FV_OK
+    assert F.fv_host_free(src[0].ctypes.data, raise_on_error=False) == F.FV_ERR_INVALID_ARG
+    assert F.fv_host_alloc(0, raise_on_error=False)[0] == F.FV_ERR_INVALID_ARG
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    assert F.fv_host_alloc(1024, raise_on_error=False)[0] == F.FV_ERR_NO_DEVICE

@@ -149,3 +149,91 @@ def test_empty_and_single():
         want, want_lam = oracle.batch_update(b.data, b.sizes, b.offsets, 2, 5, 1.1e-3, wl.H_DEFAULT, wl.GAMMA)
         assert inv.rel_err(dst[0], want) <= TOL
         assert abs(lam[0] - want_lam[0]) <= TOL * want_lam[0]
+
+
+def pinned_patches(batch, gaps=False, seed=0):
+    """The batch's patches as views into two pinned arenas from fv_host_alloc (inputs filled,
+    outputs NaN), in a shuffled order, optionally at uneven (odd double) gaps."""
+    from paper_2306_16731_amd import fvpatch
+    T = batch.num_patches
+    n = int((int(batch.sizes[0]) + 2) ** batch.dim * batch.nq)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    step = n + (3 if gaps else 0)
+    total = T * step + 8
+    a_in = fvpatch.fv_host_alloc(8 * total)
+    a_out = fvpatch.fv_host_alloc(8 * total)
+    big_in = fvpatch.pinned_array(a_in, total)
+    big_out = fvpatch.pinned_array(a_out, total)
+    big_in[:] = 0.0
+    big_out[:] = np.nan
+    place = rng.permutation(T)
+    shift = 1 if gaps else 0
+    src = [big_in[shift + place[t] * step: shift + place[t] * step + n] for t in range(T)]
+    dst = [big_out[shift + place[t] * step: shift + place[t] * step + n] for t in range(T)]
+    for t in range(T):
+        src[t][:] = batch.data[batch.offsets[t]:batch.offsets[t] + n]
+    return (a_in, a_out), src, dst
+
+
+ZERO_COPY_CASES = [  # (p, dim, T, chunk patches, slots, gaps, periodic)
+    (16, 2, 37, 5, 3, False, True),
+    (16, 2, 29, 0, 0, True, False),     # odd double offsets: 8-byte moves; defaults (one chunk)
+    (7, 2, 23, 4, 1, False, False),     # one slot: chunks in turn
+    (8, 3, 19, 3, 4, False, True),
+    (5, 3, 11, 2, 8, True, False),
+]
+
+
+@pytest.mark.parametrize("p,dim,T,chunk,slots,gaps,periodic", ZERO_COPY_CASES)
+def test_zero_copy_matches_device_path(p, dim, T, chunk, slots, gaps, periodic):
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"zero copy p={p} dim={dim} T={T} chunk={chunk} slots={slots} gaps={gaps} periodic={periodic}")
+    b = wl.make_uniform(T, p, dim=dim, seed=p + 2 * T, pulse=True)
+    arenas, src, dst = pinned_patches(b, gaps=gaps, seed=T)
+    try:
+        lam = np.full(T, -1.0)
+        pbytes = src[0].nbytes
+        cfg = {"mode": fvpatch.FV_TRANSFER_ZERO_COPY, "slots": slots,
+               "chunk_bytes": int(pbytes * chunk + pbytes // 2) if chunk else 0}
+        stats = {}
+        fvpatch.fv_host_patches_update(src, dst, b.sizes, T, dim, 5, 1.1e-3, wl.H_DEFAULT, wl.GAMMA,
+                                       fvpatch.FV_HALO_PERIODIC if periodic else 0, lam, config=cfg, stats=stats)
+        got = np.concatenate([d.copy() for d in dst])
+        dev, dev_lam = hp.gpu_step(b.data, b.sizes, b.offsets, dim, 5, 1.1e-3, wl.H_DEFAULT, wl.GAMMA, periodic)
+        assert np.array_equal(got, dev), "zero-copy path differs from the device path"
+        assert np.array_equal(lam, dev_lam)
+        assert np.array_equal(np.concatenate([s.copy() for s in src]), b.data), "inputs changed"
+        assert stats["bytes_to_device"] == b.data.nbytes and stats["host_copy_seconds"] == 0.0
+    finally:
+        del src, dst
+        for a in arenas:
+            fvpatch.fv_host_free(a)
+
+
+def test_zero_copy_refuses_pageable_patches():
+    from paper_2306_16731_amd import fvpatch
+    _announce("zero copy refuses pageable memory")
+    b = wl.make_uniform(4, 6, dim=2, seed=2)
+    arenas, src, dst = pinned_patches(b)
+    try:
+        pageable = [np.zeros_like(d) for d in dst]
+        mixed = list(src[:3]) + [b.data[b.offsets[3]:b.offsets[3] + src[3].size].copy()]
+        cfg = {"mode": fvpatch.FV_TRANSFER_ZERO_COPY}
+        assert fvpatch.fv_host_patches_update(src, pageable, b.sizes, 4, 2, 5, 1e-3, 0.1, 1.4, config=cfg,
+                                              raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG
+        assert fvpatch.fv_host_patches_update(mixed, dst, b.sizes, 4, 2, 5, 1e-3, 0.1, 1.4, config=cfg,
+                                              raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG
+        # a patch that runs past the end of its pinned block
+        a = fvpatch.fv_host_alloc(8 * 100)
+        try:
+            short = [fvpatch.pinned_array(a, 100)] * 1
+            assert fvpatch.fv_host_patches_update(short, dst[:1], b.sizes[:1], 1, 2, 5, 1e-3, 0.1, 1.4, config=cfg,
+                                                  raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG
+        finally:
+            del short
+            fvpatch.fv_host_free(a)
+        assert fvpatch.fv_host_free(a, raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG   # freed already
+    finally:
+        del src, dst
+        for x in arenas:
+            fvpatch.fv_host_free(x)
