@@ -88,7 +88,7 @@ def main() -> int:
                     help="untimed steps first (about 40 ms: the GPU's clocks and TLBs settle)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-patches", type=int, default=4096,
+    ap.add_argument("--cpu-sample-patches", type=int, default=8192,
                     help="patches the CPU oracle advances through all warmup + timed steps")
     ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer", "pde"], default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
@@ -257,6 +257,7 @@ def main() -> int:
                                "single_thread": {"value": round(S1 * p ** dim * steps_total / cpu1_s, 1),
                                                  "sample": f"first {S1} patches, {steps_total} steps "
                                                            f"({cpu1_s:.2f} s wall)"},
+                               "cpu_work_core_s": round(cpu_s * threads + cpu1_s, 1),
                                "host_cpus_visible": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
         # the timed GPU run advanced the same patches with the same dt: compare them
         got = sample_state.cpu().numpy()
