@@ -100,6 +100,9 @@ size_t pde_min_lds_bytes(int pde, int dim, int p);
 // The 2D wave form for the PDEs other than Euler (built for p = 16).
 bool pde_wave_fits(int pde, int dim, int p);
 hipError_t launch_update2d_pde(const UpdateLaunch &L, hipStream_t stream);
+// The interior-mapped 3D form for advection and acoustics (built for p = 4, 8).
+bool pde3d_fits(int pde, int dim, int p);
+hipError_t launch_update3d_pde(const UpdateLaunch &L, hipStream_t stream);
 
 // 2D kernel with each padded patch row inside one wavefront (p + 2 <= 64).
 bool wave2d_fits(int p);

@@ -308,10 +308,11 @@ hipError_t launch_euler(const UpdateLaunch &L, hipStream_t stream) {
     return launch_typed<D, EulerPDE<NQ>>(L, typename EulerPDE<NQ>::Params{L.gamma}, stream);
 }
 
-// The other built-in PDEs (FV_PDE_* of include/fvpatch.h): the 2D wave form where it is
-// built, the plane-marching kernel otherwise.
+// The other built-in PDEs (FV_PDE_* of include/fvpatch.h): the 2D wave form and the 3D
+// interior-mapped form where they are built, the plane-marching kernel otherwise.
 hipError_t launch_pde(const UpdateLaunch &L, hipStream_t stream) {
     if (pde_wave_fits(L.pde, L.dim, L.p) && !L.r_dev) return launch_update2d_pde(L, stream);
+    if (pde3d_fits(L.pde, L.dim, L.p) && !L.r_dev) return launch_update3d_pde(L, stream);
     const double *c = L.pde_prm;
     switch (L.pde) {
         case kPdeShallowWater:

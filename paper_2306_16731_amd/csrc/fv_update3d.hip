@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "fv_internal.h"
+#include "fv_pde.h"
 #include "fv_physics.h"
 
 namespace fv {
@@ -411,33 +412,34 @@ __device__ __forceinline__ void wave_update3d(const double *__restrict__ in, dou
 // face is the same Rusanov evaluation of the same two states as in the other
 // kernels, so results are equal bit for bit.  The output goes through the
 // same LDS ring and bursts as the pair-mapped form.
-template <int P>
+template <int P, int NQ = 5>
 struct Shape3i {
     static constexpr int W = P + 2;
-    static constexpr int LP = P * P;         // lanes per patch
-    static constexpr int ppw = 64 / LP;      // patches per wave
-    static constexpr int PLANE = W * W * 5;  // doubles per layer
+    static constexpr int LP = P * P;          // lanes per patch
+    static constexpr int ppw = 64 / LP;       // patches per wave
+    static constexpr int PLANE = W * W * NQ;  // doubles per layer
     static constexpr int PF = 1;             // layers in flight per lane (halos included: 15 doubles)
     static constexpr int R = 2;              // layers per burst
     static constexpr int ring_words = ppw * R * PLANE + ppw;
     // a burst of R interior layers without halos, in 8-byte chunks: per lane
-    static constexpr int CHUNKS = ppw * R * P * P * 5;
+    static constexpr int CHUNKS = ppw * R * P * P * NQ;
     static constexpr int ITERS = (CHUNKS + 63) / 64;
     static_assert(64 % LP == 0, "needs p^2 dividing 64");
     static_assert(P % R == 0, "bursts of whole rings");
 };
 
-template <int P, int VEC, bool PERIODIC, bool MESH = false>
+template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false>
 __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, double *__restrict__ out,
                                                 const int64_t *__restrict__ offsets,
                                                 const int64_t *__restrict__ out_offsets,
                                                 const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
-                                                int64_t stride, double r, double gamma,
+                                                int64_t stride, double r, double dt,
+                                                const typename PDE::Params &prm,
                                                 double *__restrict__ lambda_out, double *ring,
                                                 MeshArgs mesh = MeshArgs{}) {
     static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
-    using S = Shape3i<P>;
-    constexpr int NQ = 5;
+    constexpr int NQ = PDE::NQ, NV = PDE::NV;
+    using S = Shape3i<P, NQ>;
     constexpr int W = S::W, LP = S::LP, ppw = S::ppw, PLANE = S::PLANE, PF = S::PF, R = S::R;
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
@@ -510,11 +512,11 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
         }
     }
 
-    double qprev[NQ], fzprev[NQ], fhzprev[NQ], dprev[NQ], lzprev = 0.0;
-    rest_state<NQ>(qprev);
-    rest_state<NQ>(fzprev);
-    rest_state<NQ>(fhzprev);
-    rest_state<NQ>(dprev);
+    double qprev[NQ], fzprev[NV], gzprev[NV], dprev[NV], lzprev = 0.0;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) qprev[c] = 1.0;  // a finite state; the face it forms is never used
+#pragma unroll
+    for (int c = 0; c < NV; ++c) fzprev[c] = gzprev[c] = dprev[c] = 0.0;
     double lmax = 0.0;
 
     double qbuf[PF][3][NQ];
@@ -532,20 +534,20 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
         }
         if (k + PF < W) load_layer(k + PF, qbuf[k % PF]);
 
-        const Prim a = primitives<NQ>(q, gamma);
-        // z: the face between layers k - 1 and k
-        double fz[NQ], lz, fhz[NQ];
-        euler_flux<NQ>(q, a, 2, fz, lz);
-        rusanov<NQ>(qprev, fzprev, lzprev, q, fz, lz, fhz);
+        const typename PDE::Cache a = PDE::prepare(q, prm);
+        // z: the face between layers k - 1 and k (G+ for layer k, G- for layer k - 1)
+        double fz[NV], lz, gpz[NV], gmz[NV];
+        PDE::flux(q, a, 2, fz, lz, prm);
+        face_terms<PDE>(qprev, fzprev, lzprev, q, fz, lz, 2, prm, gpz, gmz);
         if (k >= 2) {
             const int kk = k - 1;         // layer completed now
             const int rr = (kk - 1) % R;  // its place in the ring
             double *lay = ring + (slot * R + rr) * PLANE;
             if (active) {
-                double dsum[NQ], qn[NQ];
+                double dsum[NV], qn[NQ];
 #pragma unroll
-                for (int c = 0; c < NQ; ++c) dsum[c] = dprev[c] + (fhzprev[c] - fhz[c]);
-                advance<NQ>(qprev, dsum, ratio, qn);
+                for (int c = 0; c < NV; ++c) dsum[c] = dprev[c] + (gzprev[c] - gmz[c]);
+                advance_pde<PDE>(qprev, dsum, ratio, dt, prm, qn);
 #pragma unroll
                 for (int c = 0; c < NQ; ++c) lay[(j * W + i) * NQ + c] = qn[c];
                 if (PERIODIC) {
@@ -563,7 +565,7 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
 #pragma unroll
                         for (int c = 0; c < NQ; ++c) lay[((P + 1) * W + i) * NQ + c] = qn[c];
                 }
-                if (lambda_out) lmax = nanmax(lmax, volume_lambda<3, NQ>(qn, gamma));
+                if (lambda_out) lmax = nanmax(lmax, PDE::template max_lambda<3>(qn, prm));
             }
             if (rr == R - 1 || kk == P) {
                 const int nl = rr + 1;
@@ -614,10 +616,11 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
             }
         }
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            qprev[c] = q[c];
+        for (int c = 0; c < NQ; ++c) qprev[c] = q[c];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
             fzprev[c] = fz[c];
-            fhzprev[c] = fhz[c];
+            gzprev[c] = gpz[c];
         }
         lzprev = lz;
         if (k == 0 || k == W - 1) continue;  // z halo layers: no in-plane faces
@@ -625,48 +628,56 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
 
         // x: the face to the left from the lane to the left, or (i = 1) from the halo; the face
         // to the right from the lane to the right, or (i = p) the boundary face with the halo
-        double din[NQ];
+        double din[NV];
         {
-            double fx[NQ], lx, fh[NQ], lh, qL[NQ], fL[NQ], fleft[NQ], fbound[NQ];
-            euler_flux<NQ>(q, a, 0, fx, lx);
-            const Prim ah = primitives<NQ>(qx, gamma);
-            euler_flux<NQ>(qx, ah, 0, fh, lh);
+            double fx[NV], lx, fh[NV], lh, qL[NQ], fL[NV], gpl[NV], gml[NV], gpb[NV], gmb[NV];
+            PDE::flux(q, a, 0, fx, lx, prm);
+            const typename PDE::Cache ah = PDE::prepare(qx, prm);
+            PDE::flux(qx, ah, 0, fh, lh, prm);
 #pragma unroll
             for (int c = 0; c < NQ; ++c) {
-                const double ql = lane_left(q[c]), fl = lane_left(fx[c]);
+                const double ql = lane_left(q[c]);
                 qL[c] = xlo ? qx[c] : ql;
+            }
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                const double fl = lane_left(fx[c]);
                 fL[c] = xlo ? fh[c] : fl;
             }
             const double ll = lane_left(lx);
-            rusanov<NQ>(qL, fL, xlo ? lh : ll, q, fx, lx, fleft);
-            rusanov<NQ>(q, fx, lx, qx, fh, lh, fbound);
+            face_terms<PDE>(qL, fL, xlo ? lh : ll, q, fx, lx, 0, prm, gpl, gml);
+            face_terms<PDE>(q, fx, lx, qx, fh, lh, 0, prm, gpb, gmb);
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                const double fr = lane_right(fleft[c]);
-                din[c] = fleft[c] - (xhi ? fbound[c] : fr);
+            for (int c = 0; c < NV; ++c) {
+                const double fr = lane_right(gml[c]);
+                din[c] = gpl[c] - (xhi ? gmb[c] : fr);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
         // y: the face below from row j - 1, or (j = 1) from the halo; the face above from
         // row j + 1, or (j = p) the boundary face with the halo
         {
-            double fy[NQ], ly, fh[NQ], lh, qS[NQ], fS[NQ], fbelow[NQ], fbound[NQ];
-            euler_flux<NQ>(q, a, 1, fy, ly);
-            const Prim ah = primitives<NQ>(qy, gamma);
-            euler_flux<NQ>(qy, ah, 1, fh, lh);
+            double fy[NV], ly, fh[NV], lh, qS[NQ], fS[NV], gpb_[NV], gmb_[NV], gpu[NV], gmu[NV];
+            PDE::flux(q, a, 1, fy, ly, prm);
+            const typename PDE::Cache ah = PDE::prepare(qy, prm);
+            PDE::flux(qy, ah, 1, fh, lh, prm);
 #pragma unroll
             for (int c = 0; c < NQ; ++c) {
-                const double qs = lane_from(q[c], below), fs = lane_from(fy[c], below);
+                const double qs = lane_from(q[c], below);
                 qS[c] = ylo ? qy[c] : qs;
+            }
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                const double fs = lane_from(fy[c], below);
                 fS[c] = ylo ? fh[c] : fs;
             }
             const double ls = lane_from(ly, below);
-            rusanov<NQ>(qS, fS, ylo ? lh : ls, q, fy, ly, fbelow);
-            rusanov<NQ>(q, fy, ly, qy, fh, lh, fbound);
+            face_terms<PDE>(qS, fS, ylo ? lh : ls, q, fy, ly, 1, prm, gpb_, gmb_);   // the face below
+            face_terms<PDE>(q, fy, ly, qy, fh, lh, 1, prm, gpu, gmu);                 // the boundary face above
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                const double fa = lane_from(fbelow[c], above);
-                dprev[c] = din[c] + (fbelow[c] - (yhi ? fbound[c] : fa));
+            for (int c = 0; c < NV; ++c) {
+                const double fa = lane_from(gmb_[c], above);
+                dprev[c] = din[c] + (gpb_[c] - (yhi ? gmu[c] : fa));
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -706,8 +717,9 @@ update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
     if constexpr (kInteriorMapped<P>) {
         const int64_t item0 = (int64_t)blockIdx.x * Shape3i<P>::ppw;
         if (item0 >= num_items) return;
-        wave_update3d_i<P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr,
-                                                gamma, lambda_out, lds, mesh);
+        wave_update3d_i<EulerPDE<5>, P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items,
+                                                             stride, rr, 0.0, typename EulerPDE<5>::Params{gamma},
+                                                             lambda_out, lds, mesh);
     } else {
         const int64_t item0 = (int64_t)blockIdx.x * Shape3<P>::ppw;
         if (item0 >= num_items) return;
@@ -740,7 +752,60 @@ hipError_t launch3d_p(const UpdateLaunch &L, hipStream_t stream) {
     return periodic ? launch3d<P, 1, true>(L, stream) : launch3d<P, 1, false>(L, stream);
 }
 
+// The interior-mapped form for the other PDEs (fv_pde.h).
+template <class PDE, int P, int VEC, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock3)
+update3d_pde_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
+                    const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
+                    int64_t stride, double r, double dt, typename PDE::Params prm, double *__restrict__ lambda_out) {
+    extern __shared__ double lds[];
+    const int64_t item0 = (int64_t)blockIdx.x * Shape3i<P, PDE::NQ>::ppw;
+    if (item0 >= num_items) return;
+    wave_update3d_i<PDE, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, item0, num_items, stride, r, dt, prm,
+                                           lambda_out, lds);
+}
+
+template <class PDE, int P, int VEC, bool PERIODIC>
+void launch3d_pde_form(const UpdateLaunch &L, const typename PDE::Params &prm, int64_t blocks, size_t lds,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL((update3d_pde_kernel<PDE, P, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(kBlock3), lds,
+                       stream, L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.dt, prm,
+                       L.lambda_out);
+}
+
+template <class PDE, int P>
+hipError_t launch3d_pde(const UpdateLaunch &L, const typename PDE::Params &prm, hipStream_t stream) {
+    using S = Shape3i<P, PDE::NQ>;
+    const int64_t blocks = ((int64_t)L.num_items + S::ppw - 1) / S::ppw;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(double) * (size_t)S::ring_words;
+    if ((L.flags & kPeriodic3) == 0) launch3d_pde_form<PDE, P, 1, false>(L, prm, blocks, lds, stream);
+    else if (L.vec2) launch3d_pde_form<PDE, P, 2, true>(L, prm, blocks, lds, stream);
+    else launch3d_pde_form<PDE, P, 1, true>(L, prm, blocks, lds, stream);
+    return hipGetLastError();
+}
+
+template <class PDE>
+hipError_t launch3d_pde_p(const UpdateLaunch &L, const typename PDE::Params &prm, hipStream_t stream) {
+    return L.p == 4 ? launch3d_pde<PDE, 4>(L, prm, stream) : launch3d_pde<PDE, 8>(L, prm, stream);
+}
+
 }  // namespace
+
+bool pde3d_fits(int pde, int dim, int p) {
+    return dim == 3 && (p == 4 || p == 8) && (pde == kPdeAdvection || pde == kPdeAcoustics || pde == kPdeAcousticsNcp);
+}
+
+hipError_t launch_update3d_pde(const UpdateLaunch &L, hipStream_t stream) {
+    if (!pde3d_fits(L.pde, L.dim, L.p) || L.r_dev) return hipErrorInvalidValue;
+    const double *c = L.pde_prm;
+    switch (L.pde) {
+        case kPdeAdvection: return launch3d_pde_p<AdvectionPDE>(L, AdvectionPDE::Params{{c[0], c[1], c[2]}}, stream);
+        case kPdeAcoustics: return launch3d_pde_p<AcousticsPDE<3, false>>(L, {c[0], c[1], c[2]}, stream);
+        case kPdeAcousticsNcp: return launch3d_pde_p<AcousticsPDE<3, true>>(L, {c[0], c[1], c[2]}, stream);
+    }
+    return hipErrorInvalidValue;
+}
 
 bool wave3d_fixed(int p, int nq) { return nq == 5 && (p == 4 || p == 6 || p == 8); }
 

@@ -81,6 +81,9 @@ CASES = [  # (name, dim, sizes)
     ("acoustics", 3, [6] * 7 + [13]),
     ("acoustics_ncp", 2, [16, 5, 63]),
     ("acoustics_ncp", 3, [8, 3, 23, 10]),   # 23: the largest 3D size whose block fits the LDS
+    ("advection", 3, [8] * 5 + [4] * 3),         # the 3D interior-mapped form (p = 4, 8)
+    ("acoustics", 3, [4] * 9 + [8] * 3 + [5]),   # interior-mapped form and plane-marching kernel in one batch
+    ("acoustics_ncp", 3, [4] * 6 + [8] * 2),
     ("euler", 2, [16, 7, 40]),
     ("euler", 3, [8, 5]),
 ]
@@ -155,6 +158,13 @@ def test_shallow_water_pins(p):
     pc.check_swe_conservation(gpu_update, p=p)
     pc.check_swe_swap_xy(gpu_update, p=p)
     pc.check_coriolis(gpu_update, p=p)
+
+
+@pytest.mark.parametrize("name", ["advection", "acoustics", "acoustics_ncp"])
+@pytest.mark.parametrize("p", [8, 4])
+def test_fourier_mode_3d_interior_form(name, p):
+    _announce(f"fourier {name} 3D p={p}")
+    pc.check_fourier_mode(gpu_update, name, 3, p=p, modes=((1, 2, 3), (3, 1, 2), (p // 2, p // 2, 0)))
 
 
 @pytest.mark.parametrize("name", ["advection", "acoustics", "acoustics_ncp"])
