@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # sources of the kernel the roofline reports (the 2D wave kernel and its physics)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_16731_amd", "csrc", f) for f in ("fv_update2d.hip", "fv_physics.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_16731_amd", "csrc", f) for f in ("fv_update2d.hip", "fv_physics.h", "fv_pde.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv_update_c2_2d_p16_T65536_traffic.md")
 
 
@@ -397,7 +397,7 @@ def bench_pde(args) -> int:
         line = {"metric": "cell-updates/s", "form": "pde", "pde": name, "value": round(T * p ** dim / (ms / 1e3), 1),
                 "unit": "cell-updates/s", "ms_per_step": round(ms, 5), "alg_GBs": round(gbs, 1),
                 "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": alg,
-                "kernel": ("2D wave form (update2d_pde_kernel)" if dim == 2 and p == 16 and name != "euler"
+                "kernel": ("2D wave form (update2d_pde_kernel)" if dim == 2 and p in (3, 5, 9, 16, 17) and name != "euler"
                            else "3D interior-mapped form (update3d_pde_kernel)"
                            if dim == 3 and p in (4, 8) and name != "euler"
                            else "plane-marching kernel (update_kernel)"), "dtype": "f64", "data": "synthetic",

@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(PKG, "libfvpatch.so")
 
-SOURCES = ["fv_update.hip", "fv_update2d.hip", "fv_update2d_tile.hip", "fv_update3d.hip", "fv_update2d_pde.hip", "fv_step.hip", "fv_abi.hip",
+SOURCES = ["fv_update.hip", "fv_update2d.hip", "fv_update2d_tile.hip", "fv_update3d.hip", "fv_step.hip", "fv_abi.hip",
            "fv_plan.hip", "fv_serve.hip", "fv_mesh.hip", "fv_flavours.hip",
            "fv_transfer.hip"]
 HEADERS = ["fv_internal.h", "fv_host.h", "fv_physics.h"]

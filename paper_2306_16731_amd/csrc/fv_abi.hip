@@ -282,7 +282,8 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         for (int k = 0; k < 4; ++k) L.pde_prm[k] = pde->prm[k];
     }
     L.dt = dt;
-    // Euler classes take their tuned kernel; the other PDEs run on the generic block kernel
+    // Euler classes take their tuned kernel; the other PDEs their built wave form, else the
+    // generic block kernel (launch_pde picks)
     auto tune = [](UpdateLaunch &X) {
         if (X.pde == kPdeEuler) {
             apply_tuning(X);

@@ -97,7 +97,7 @@ size_t update_lds_bytes(int dim, int nq, int block);
 hipError_t launch_update(const UpdateLaunch &L, hipStream_t stream);
 // LDS of the generic kernel's smallest block for one patch of size p of a PDE (kPde*).
 size_t pde_min_lds_bytes(int pde, int dim, int p);
-// The 2D wave form for the PDEs other than Euler (built for p = 16).
+// The 2D wave form for the PDEs other than Euler (at the fixed sizes p = 3, 5, 9, 16, 17).
 bool pde_wave_fits(int pde, int dim, int p);
 hipError_t launch_update2d_pde(const UpdateLaunch &L, hipStream_t stream);
 // The interior-mapped 3D form for advection and acoustics (built for p = 4, 8).

@@ -35,6 +35,7 @@
 #include <algorithm>
 
 #include "fv_internal.h"
+#include "fv_pde.h"
 #include "fv_physics.h"
 
 namespace fv {
@@ -282,23 +283,25 @@ constexpr int kTaskBlock = 64;                      // the same for the task-lis
 
 inline bool fixed_size(int p) { return p == 3 || p == 5 || p == 9 || p == 16 || p == 17; }
 
-template <int P>
+template <int P, int NQ = 5>
 constexpr int fixed_ring_words() {
-    return (64 / (P + 2)) * FixedShape<P>::R * (P + 2) * 5 + 64 / (P + 2);
+    return (64 / (P + 2)) * FixedShape<P>::R * (P + 2) * NQ + 64 / (P + 2);
 }
 
 // MESH: the face halos come from the neighbouring patches' interiors (the
 // halo volumes of a patch without a neighbour on that face are its own), and
 // patch t advances by dt[t] / h[t]; the output is the interior only.
-template <int NQ, int P, int VEC, bool PERIODIC, bool MESH = false>
+template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false>
 __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in, double *__restrict__ out,
                                                   const int64_t *__restrict__ offsets,
                                                   const int64_t *__restrict__ out_offsets,
                                                   const int32_t *__restrict__ ids, int64_t item0, int64_t num_items,
-                                                  int64_t stride, double r, double gamma,
+                                                  int64_t stride, double r, double dt,
+                                                  const typename PDE::Params &prm,
                                                   double *__restrict__ lambda_out, double *ring,
                                                   MeshArgs mesh = MeshArgs{}) {
     static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
+    constexpr int NQ = PDE::NQ, NV = PDE::NV;
     constexpr int W = P + 2;
     constexpr int ppw = 64 / W;
     constexpr int ROWD = W * NQ;
@@ -340,12 +343,12 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     if (i == 0 && slot < ppw) bases[slot] = off_out;
     wave_lds_fence();
 
-    double qprev[NQ], fyprev[NQ], fhprev[NQ], dxprev[NQ];
+    double qprev[NQ], fyprev[NV], fhprev[NV], dxprev[NV];
     double lyprev = 0.0, lmax = 0.0;
-    rest_state<NQ>(qprev);
-    rest_state<NQ>(fyprev);
-    rest_state<NQ>(fhprev);
-    rest_state<NQ>(dxprev);
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) qprev[c] = 1.0;  // a finite state; the face it forms is never used
+#pragma unroll
+    for (int c = 0; c < NV; ++c) fyprev[c] = fhprev[c] = dxprev[c] = 0.0;
 
     double qbuf[PF][NQ];
 #pragma unroll
@@ -358,31 +361,33 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
         for (int c = 0; c < NQ; ++c) q[c] = qbuf[k % PF][c];
         load_volume<NQ>(row_ptr(k + PF < W ? k + PF : W - 1), qbuf[k % PF]);
 
-        const Prim a = primitives<NQ>(q, gamma);
-        double fx[NQ], lx, fy[NQ], ly;
-        euler_flux<NQ>(q, a, 0, fx, lx);
-        euler_flux<NQ>(q, a, 1, fy, ly);
-        double qL[NQ], fL[NQ], fhx[NQ];
+        // the faces of the row: x to the lane's left (G+ for this lane, G- for the lane to the left)
+        // and y below (G+ for this row, G- for the row below); G+ = G- = Fhat without a
+        // non-conservative product
+        const typename PDE::Cache a = PDE::prepare(q, prm);
+        double fx[NV], lx, fy[NV], ly;
+        PDE::flux(q, a, 0, fx, lx, prm);
+        PDE::flux(q, a, 1, fy, ly, prm);
+        double qL[NQ], fL[NV], gpx[NV], gmx[NV];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            qL[c] = from_left(q[c]);
-            fL[c] = from_left(fx[c]);
-        }
+        for (int c = 0; c < NQ; ++c) qL[c] = from_left(q[c]);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) fL[c] = from_left(fx[c]);
         const double lL = from_left(lx);
-        rusanov<NQ>(qL, fL, lL, q, fx, lx, fhx);
-        double dx[NQ], fh[NQ];
+        face_terms<PDE>(qL, fL, lL, q, fx, lx, 0, prm, gpx, gmx);
+        double dx[NV], fh[NV], gmy[NV];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) dx[c] = fhx[c] - from_right(fhx[c]);
-        rusanov<NQ>(qprev, fyprev, lyprev, q, fy, ly, fh);
+        for (int c = 0; c < NV; ++c) dx[c] = gpx[c] - from_right(gmx[c]);
+        face_terms<PDE>(qprev, fyprev, lyprev, q, fy, ly, 1, prm, fh, gmy);
 
         if (k >= 2) {
             const int kk = k - 1;          // output row completed at this layer
             const int rr = (kk - 1) % R;   // its row in the ring
             if (writer) {
-                double d[NQ], qn[NQ];
+                double d[NV], qn[NQ];
 #pragma unroll
-                for (int c = 0; c < NQ; ++c) d[c] = dxprev[c] + (fhprev[c] - fh[c]);
-                advance<NQ>(qprev, d, ratio, qn);
+                for (int c = 0; c < NV; ++c) d[c] = dxprev[c] + (fhprev[c] - gmy[c]);
+                advance_pde<PDE>(qprev, d, ratio, dt, prm, qn);
                 double *srow = ring + (slot * R + rr) * ROWD;
 #pragma unroll
                 for (int c = 0; c < NQ; ++c) srow[i * NQ + c] = qn[c];
@@ -394,7 +399,7 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
 #pragma unroll
                         for (int c = 0; c < NQ; ++c) srow[(P + 1) * NQ + c] = qn[c];
                 }
-                if (lambda_out) lmax = nanmax(lmax, volume_lambda<2, NQ>(qn, gamma));
+                if (lambda_out) lmax = nanmax(lmax, PDE::template max_lambda<2>(qn, prm));
             }
             if (rr == R - 1 || kk == P) {
                 const int nrows = rr + 1;
@@ -464,8 +469,9 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
             }
         }
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            qprev[c] = q[c];
+        for (int c = 0; c < NQ; ++c) qprev[c] = q[c];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
             fyprev[c] = fy[c];
             fhprev[c] = fh[c];
             dxprev[c] = dx[c];
@@ -492,8 +498,8 @@ __device__ __forceinline__ void fixed_task_body(const double *__restrict__ in, d
                                              const int64_t *__restrict__ out_offsets,
                                              const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
                                              double *__restrict__ lambda_out, double *ring) {
-    wave_update_fixed<5, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, 0, count, 0, r, gamma, lambda_out,
-                                           ring);
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, 0, count, 0, r, 0.0,
+                                                     typename EulerPDE<5>::Params{gamma}, lambda_out, ring);
 }
 
 // Task-list body for a fixed size: false when p has no fixed-size build.
@@ -549,8 +555,25 @@ update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
     const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
     if (item0 >= num_items) return;
     const double rr = r_dev ? *r_dev : r;
-    wave_update_fixed<5, P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items, stride, rr,
-                                                 gamma, lambda_out, lds + (size_t)wave * fixed_ring_words<P>(), mesh);
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items,
+                                                           stride, rr, 0.0, typename EulerPDE<5>::Params{gamma},
+                                                           lambda_out, lds + (size_t)wave * fixed_ring_words<P>(),
+                                                           mesh);
+}
+
+// The wave form for the other PDEs of Eq. 1 (fv_pde.h) at the fixed sizes: the
+// same march as the Euler instance above on the PDE's user terms.
+template <class PDE, int P, int VEC, bool PERIODIC>
+__global__ void __launch_bounds__(kFixedBlock)
+update2d_pde_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
+                    const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
+                    int64_t stride, double r, double dt, typename PDE::Params prm, double *__restrict__ lambda_out) {
+    extern __shared__ double lds[];
+    constexpr int ppw = 64 / (P + 2);
+    const int64_t item0 = (int64_t)blockIdx.x * ppw;
+    if (item0 >= num_items) return;
+    wave_update_fixed<PDE, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, item0, num_items, stride, r, dt, prm,
+                                             lambda_out, lds);
 }
 
 // Task-list launch over mixed patch sizes: task t holds `count` patches of
@@ -755,6 +778,60 @@ hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream) {
         case 9: return fixed_periodic<9, 1>(L, stream);
         case 16: return L.vec2 ? fixed_periodic<16, 2>(L, stream) : fixed_periodic<16, 1>(L, stream);
         case 17: return fixed_periodic<17, 1>(L, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <class PDE, int P, int VEC, bool PERIODIC>
+void launch_pde_wave_form(const UpdateLaunch &L, const typename PDE::Params &prm, int64_t blocks, size_t lds,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL((update2d_pde_kernel<PDE, P, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(kFixedBlock), lds,
+                       stream, L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.dt, prm,
+                       L.lambda_out);
+}
+
+template <class PDE, int P>
+hipError_t launch_pde_wave(const UpdateLaunch &L, const typename PDE::Params &prm, hipStream_t stream) {
+    constexpr int ppw = 64 / (P + 2);
+    const int64_t blocks = ((int64_t)L.num_items + ppw - 1) / ppw;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(double) * (size_t)fixed_ring_words<P, PDE::NQ>();
+    // 16-byte row bursts where the rows are an even number of doubles (p = 16)
+    if ((L.flags & kPeriodic) == 0) launch_pde_wave_form<PDE, P, 1, false>(L, prm, blocks, lds, stream);
+    else if (P == 16 && L.vec2) launch_pde_wave_form<PDE, P, P == 16 ? 2 : 1, true>(L, prm, blocks, lds, stream);
+    else launch_pde_wave_form<PDE, P, 1, true>(L, prm, blocks, lds, stream);
+    return hipGetLastError();
+}
+
+template <class PDE>
+hipError_t launch_pde_wave_p(const UpdateLaunch &L, const typename PDE::Params &prm, hipStream_t stream) {
+    switch (L.p) {
+        case 3: return launch_pde_wave<PDE, 3>(L, prm, stream);
+        case 5: return launch_pde_wave<PDE, 5>(L, prm, stream);
+        case 9: return launch_pde_wave<PDE, 9>(L, prm, stream);
+        case 16: return launch_pde_wave<PDE, 16>(L, prm, stream);
+        case 17: return launch_pde_wave<PDE, 17>(L, prm, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool pde_wave_fits(int pde, int dim, int p) {
+    return dim == 2 && fixed_size(p) &&
+           (pde == kPdeShallowWater || pde == kPdeAdvection || pde == kPdeAcoustics || pde == kPdeAcousticsNcp);
+}
+
+hipError_t launch_update2d_pde(const UpdateLaunch &L, hipStream_t stream) {
+    if (!pde_wave_fits(L.pde, L.dim, L.p) || L.r_dev) return hipErrorInvalidValue;
+    const double *c = L.pde_prm;
+    switch (L.pde) {
+        case kPdeShallowWater: return launch_pde_wave_p<ShallowWaterPDE>(L, {c[0], c[1]}, stream);
+        case kPdeAdvection: return launch_pde_wave_p<AdvectionPDE>(L, AdvectionPDE::Params{{c[0], c[1], c[2]}}, stream);
+        case kPdeAcoustics: return launch_pde_wave_p<AcousticsPDE<2, false>>(L, {c[0], c[1], c[2]}, stream);
+        case kPdeAcousticsNcp: return launch_pde_wave_p<AcousticsPDE<2, true>>(L, {c[0], c[1], c[2]}, stream);
     }
     return hipErrorInvalidValue;
 }

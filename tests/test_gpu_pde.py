@@ -74,7 +74,7 @@ CASES = [  # (name, dim, sizes)
     ("shallow_water", 2, [16] * 9),
     ("shallow_water", 2, [3, 17, 5, 64, 9, 1, 31]),
     ("advection", 2, [8] * 11),
-    ("advection", 2, [16] * 7),                 # the 2D wave form (p = 16)
+    ("advection", 2, [16] * 7),                 # the 2D wave form (p = 16, 16-byte bursts when periodic)
     ("acoustics", 2, [16] * 4 + [7]),           # wave form and plane-marching kernel in one batch
     ("advection", 3, [4, 7, 12, 24, 1, 5]),
     ("acoustics", 2, [9, 33, 2, 62]),
@@ -84,6 +84,9 @@ CASES = [  # (name, dim, sizes)
     ("advection", 3, [8] * 5 + [4] * 3),         # the 3D interior-mapped form (p = 4, 8)
     ("acoustics", 3, [4] * 9 + [8] * 3 + [5]),   # interior-mapped form and plane-marching kernel in one batch
     ("acoustics_ncp", 3, [4] * 6 + [8] * 2),
+    ("shallow_water", 2, [3] * 23 + [5] * 9 + [9] * 8 + [17] * 5),   # the 2D wave form at every fixed size
+    ("acoustics_ncp", 2, [17] * 5 + [9] * 7 + [3] * 3),
+    ("advection", 2, [5] * 12 + [3] * 40 + [17] * 2),
     ("euler", 2, [16, 7, 40]),
     ("euler", 3, [8, 5]),
 ]
@@ -151,7 +154,7 @@ def test_ncp_form_equals_flux_form(dim):
     pc.check_ncp_form_equals_flux_form(gpu_update, dim)
 
 
-@pytest.mark.parametrize("p", [16, 10])   # the 2D wave form and the plane-marching kernel
+@pytest.mark.parametrize("p", [16, 5, 10])   # the 2D wave form (even and odd rows) and the plane-marching kernel
 def test_shallow_water_pins(p):
     _announce(f"lake at rest / conservation / swap / coriolis p={p}")
     pc.check_lake_at_rest(gpu_update, p=p)
@@ -168,9 +171,10 @@ def test_fourier_mode_3d_interior_form(name, p):
 
 
 @pytest.mark.parametrize("name", ["advection", "acoustics", "acoustics_ncp"])
-def test_fourier_mode_wave_form(name):
-    _announce(f"fourier {name} 2D p=16")
-    pc.check_fourier_mode(gpu_update, name, 2, p=16, modes=((1, 2, 0), (5, 3, 0), (8, 8, 0)))
+@pytest.mark.parametrize("p", [16, 9])
+def test_fourier_mode_wave_form(name, p):
+    _announce(f"fourier {name} 2D p={p}")
+    pc.check_fourier_mode(gpu_update, name, 2, p=p, modes=((1, 2, 0), (3, p // 3, 0), (p // 2, p // 2, 0)))
 
 
 def test_dam_break_converges_to_stoker():
