@@ -686,8 +686,8 @@ def bench_batching(args) -> int:
         for _ in range(args.warmup // 10 + 3):
             plain()
         results = {"plain": _timed(plain, steps) / steps}
-        plan_choice = autotune.tune_plan(b, periodic) if dim == 2 else {"persistent": True}
-        pflags = flags | (0 if plan_choice["persistent"] else fvpatch.FV_PLAN_NO_PERSIST)
+        plan_choice = autotune.tune_plan(b, periodic) if dim == 2 else {"mode": "persistent", "flags": 0}
+        pflags = flags | plan_choice["flags"]
         plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags)
         try:
             info = fvpatch.fv_plan_info(plan)

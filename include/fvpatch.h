@@ -178,6 +178,9 @@ fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *tun
 typedef struct fv_plan fv_plan;
 
 #define FV_PLAN_NO_PERSIST 0x100u /* plan flag: one wave per task instead of a persistent grid */
+#define FV_PLAN_PER_CLASS 0x200u  /* plan flag: no fused launch; each size class is launched on its own
+                                     kernel, at that kernel's occupancy (the fused launch holds every
+                                     wave to the LDS of its largest class) */
 
 typedef struct fv_plan_stats {
     int32_t num_patches;
@@ -191,8 +194,8 @@ typedef struct fv_plan_stats {
 
 /* Build a plan for the composition (sizes, offsets as for
  * fv_patch_batch_update; offsets NULL = contiguous, equal sizes).  flags:
- * FV_HALO_PERIODIC and/or FV_PLAN_NO_PERSIST.  Tuning installed later does
- * not change an existing plan. */
+ * FV_HALO_PERIODIC, and FV_PLAN_NO_PERSIST or FV_PLAN_PER_CLASS.  Tuning
+ * installed later does not change an existing plan. */
 fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *offsets, int32_t num_patches,
                          int32_t dim, int32_t unknowns, uint32_t flags);
 

@@ -7,14 +7,14 @@ output rows staged per burst -- on a synthetic
 batch of that class, ping-ponging steps through the C ABI after a warmup,
 and installs the fastest with fv_set_tuning.  Plans built afterwards pick the
 installed parameters up per size class.  For a whole batch it also picks the
-plan's work split: a persistent grid walking the task list, or one wave per
-task.
+plan's launch mode: the fused launch on a persistent grid walking the task
+list, the fused launch with one wave per task, or one launch per size class.
 
 The table persists as JSON:
 
     {"device": "...", "entries": {"2,5,16": {"kernel": 2, "block": 256, "prefetch": 4, "rows": 6,
                                              "ms": 0.37, "patches": 65536}, ...},
-     "plans": {"<composition key>": {"persistent": true, "ms": ...}}}
+     "plans": {"<composition key>": {"mode": "per_class", "flags": 512, "ms": ...}}}
 """
 from __future__ import annotations
 
@@ -144,12 +144,17 @@ def composition_key(sizes, dim: int, nq: int) -> str:
     return f"{dim},{nq}:" + ";".join(f"{int(v)}x{int(c)}" for v, c in zip(vals, counts))
 
 
+PLAN_MODES = {"persistent": 0, "per_task": fv.FV_PLAN_NO_PERSIST, "per_class": fv.FV_PLAN_PER_CLASS}
+
+
 def tune_plan(batch: wl.Batch, periodic: bool = False, steps: int = 10, warmup: int = 10) -> dict:
-    """Persistent grid vs one wave per task for a batch composition; returns {"persistent", "ms"}."""
+    """The plan's launch mode for a batch composition, by timing: the fused launch on a persistent
+    grid, the fused launch with one wave per task, or one launch per size class.  Returns
+    {"mode", "flags", "ms", "ms_<mode>" for each mode}."""
     import torch
     res = {}
-    for persistent in (True, False):
-        flags = (fv.FV_HALO_PERIODIC if periodic else 0) | (0 if persistent else fv.FV_PLAN_NO_PERSIST)
+    for mode, mflags in PLAN_MODES.items():
+        flags = (fv.FV_HALO_PERIODIC if periodic else 0) | mflags
         plan = fv.fv_plan_create(batch.sizes, batch.offsets, batch.num_patches, batch.dim, batch.nq, flags)
         try:
             a = torch.from_numpy(batch.data).to("cuda")
@@ -161,12 +166,12 @@ def tune_plan(batch: wl.Batch, periodic: bool = False, steps: int = 10, warmup: 
                 fv.fv_plan_execute(plan, bufs[0], bufs[1], 1e-3, wl.H_DEFAULT, wl.GAMMA, lam)
                 bufs.reverse()
 
-            res[persistent] = _time_steps(step, steps, warmup)
+            res[mode] = _time_steps(step, steps, warmup)
             del a, c, lam
         finally:
             fv.fv_plan_destroy(plan)
     best = min(res, key=res.get)
-    return {"persistent": bool(best), "ms": res[best], "ms_persistent": res[True], "ms_per_task": res[False]}
+    return {"mode": best, "flags": PLAN_MODES[best], "ms": res[best], **{f"ms_{m}": t for m, t in res.items()}}
 
 
 def device_name() -> str:

@@ -5,12 +5,17 @@
 // The paper bundles T patch updates into one kernel call (task fusion, Sec.
 // 2.1) and proposes, without being able to run it, to precompile the fixed
 // task graph so the GPU resolves the dependencies (Sec. 6, Sec. 8).  Here the
-// plan sorts the patches by size (largest first), cuts each size class into
-// wave tasks (floor(64 / (p+2)) patches per task) with the launch parameters
-// the tuning table holds for that class, and runs all classes in ONE launch of
-// the 2D wave kernel whose waves walk the task list (persistent: as many
-// waves as fit on the device).  Classes the wave kernel cannot take (3D, or
-// 2D p > 62) are launched per class inside the same step.
+// plan sorts the patches by size, cuts each size class into wave tasks
+// (floor(64 / (p+2)) patches per task; the fixed-size body for the sizes built
+// in that form, else the runtime-size body with the class's tuned rows), and
+// runs all classes in ONE launch of the 2D wave kernel whose waves walk the
+// task list: a persistent grid (as many waves as fit on the device, tasks
+// largest first) or one wave per task (tasks in memory order).  Classes the
+// wave kernel cannot take (3D, or 2D p > 62) are launched per class inside the
+// same step.  A plan may instead launch every class on its own kernel with its
+// tuned parameters (FV_PLAN_PER_CLASS): the descriptors are still built once,
+// and each class runs at its own kernel's occupancy, where the fused launch
+// reserves the largest class's LDS ring for every wave.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,8 +44,9 @@ struct fv_plan {
     bool even_offsets = true;  // every wave-task patch starts at an even double and has even rows
     struct Group {
         int32_t p, first, count;
+        bool even;  // every patch of the class starts at an even double and spans an even number
     };
-    std::vector<Group> groups;  // classes launched per class (3D, 2D p > 62)
+    std::vector<Group> groups;  // classes launched per class (3D, 2D p > 62; every class with FV_PLAN_PER_CLASS)
     // captured multi-step run
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -106,8 +112,9 @@ fv_status enqueue_step(const fv_plan *pl, const double *in, double *out, double 
         L.gamma = gamma;
         L.flags = pl->flags;
         L.lambda_out = lambda_out;
+        L.vec2 = g.even && aligned16(in) && aligned16(out);
         apply_tuning(L);
-        if (L.dim == 2 && L.kernel == FV_KERNEL_WAVE) L.kernel = FV_KERNEL_BLOCK;  // wave-eligible sizes are in the task list
+        if (L.dim == 2 && L.kernel == FV_KERNEL_WAVE && !wave2d_fits(L.p)) L.kernel = FV_KERNEL_BLOCK;
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "class launch (p=%d) failed: %s", g.p, hipGetErrorString(e));
     }
@@ -148,7 +155,10 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     *plan = nullptr;
     fv_status st = check_scalars(dim, unknowns, 1.0, 1.0, 2.0, flags & FV_HALO_PERIODIC);
     if (st != FV_OK) return st;
-    if (flags & ~(FV_HALO_PERIODIC | FV_PLAN_NO_PERSIST)) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if (flags & ~(FV_HALO_PERIODIC | FV_PLAN_NO_PERSIST | FV_PLAN_PER_CLASS))
+        return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & FV_PLAN_NO_PERSIST) && (flags & FV_PLAN_PER_CLASS))
+        return fail(FV_ERR_INVALID_ARG, "FV_PLAN_NO_PERSIST and FV_PLAN_PER_CLASS exclude each other");
     if (num_patches < 1) return fail(FV_ERR_INVALID_ARG, "a plan needs at least one patch");
     BatchShape shape;
     st = check_layout(sizes, offsets, num_patches, dim, unknowns, &shape);
@@ -162,7 +172,8 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     pl->dim = dim;
     pl->nq = unknowns;
     pl->flags = flags & FV_HALO_PERIODIC;
-    pl->persistent = !(flags & FV_PLAN_NO_PERSIST);
+    pl->persistent = !(flags & (FV_PLAN_NO_PERSIST | FV_PLAN_PER_CLASS));
+    const bool per_class = (flags & FV_PLAN_PER_CLASS) != 0;
     pl->num_patches = num_patches;
     pl->lo = shape.lo;
     pl->hi = shape.hi;
@@ -191,10 +202,13 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     }
     for (int p = pmax; p >= 1; --p) {
         if (!count[p]) continue;
-        if (dim == 2 && wave2d_fits(p)) {
+        if (dim == 2 && wave2d_fits(p) && !per_class) {
             const fv_tuning tu = tuning_for(dim, unknowns, p);
-            // rows == 0: the fixed-size form of the kernel
-            const bool fixed = tu.kernel == FV_KERNEL_FIXED;
+            // rows == 0: the fixed-size form of the kernel.  A class built in that form runs it
+            // in the fused launch whatever its tuning: a tuned runtime-size body keeps its rows
+            // there but not its block size or prefetch (one of each per fused launch), and
+            // measured slower than the fixed-size body
+            const bool fixed = tu.kernel == FV_KERNEL_FIXED || wave2d_fixed(p, unknowns);
             const int rows = fixed ? 0 : (tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6);
             const int ppw = 64 / (p + 2);
             for (int32_t f = 0; f < count[p]; f += ppw)
@@ -210,9 +224,17 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
             for (int32_t k = start[p]; k < start[p] + count[p]; ++k)
                 if (hoff[k] & 1) pl->even_offsets = false;
         } else {
-            pl->groups.push_back(fv_plan::Group{p, start[p], count[p]});
+            bool even = patch_doubles(p, dim, unknowns) % 2 == 0;
+            for (int32_t k = start[p]; k < start[p] + count[p] && even; ++k) even = (hoff[k] & 1) == 0;
+            pl->groups.push_back(fv_plan::Group{p, start[p], count[p], even});
         }
     }
+    // One wave per task: workgroups start in task order, so tasks in memory order keep the
+    // resident waves on neighbouring patches (DRAM page locality); a persistent grid keeps
+    // largest-first, which balances the waves' shares.
+    if (!pl->persistent)
+        std::stable_sort(tasks.begin(), tasks.end(),
+                         [&](const WaveTask &a, const WaveTask &b) { return hoff[a.first] < hoff[b.first]; });
     pl->num_tasks = (int32_t)tasks.size();
 
     // device copies of the work list

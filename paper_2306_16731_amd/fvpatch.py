@@ -44,6 +44,7 @@ EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_c
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
 FV_PLAN_NO_PERSIST = 0x100
+FV_PLAN_PER_CLASS = 0x200
 FV_KERNEL_AUTO = 0
 FV_KERNEL_BLOCK = 1
 FV_KERNEL_WAVE = 2

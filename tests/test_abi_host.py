@@ -46,7 +46,8 @@ def test_header_constants_match_binding():
     hdr = open(os.path.join(ROOT, "include", "fvpatch.h")).read()
     for name in ["FV_MAX_P_2D", "FV_MAX_P_3D"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name)
-    assert int(re.search(r"#define FV_HALO_PERIODIC (0x[0-9a-f]+)u", hdr).group(1), 16) == F.FV_HALO_PERIODIC
+    for name in ["FV_HALO_PERIODIC", "FV_PLAN_NO_PERSIST", "FV_PLAN_PER_CLASS"]:
+        assert int(re.search(rf"#define {name} (0x[0-9a-f]+)u", hdr).group(1), 16) == getattr(F, name), name
     for name in ["FV_KERNEL_AUTO", "FV_KERNEL_BLOCK", "FV_KERNEL_WAVE", "FV_KERNEL_TILE", "FV_KERNEL_FIXED"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name), name
     found = re.findall(r"p in \{([0-9, ]+)\}", hdr)
@@ -143,6 +144,8 @@ def test_plan_validation_before_device():
         (dict(sizes=[4, 5], offsets=None, num_patches=2, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
         (dict(sizes=[4, 4], offsets=[0, 10], num_patches=2, dim=2, unknowns=5), F.FV_ERR_OVERLAP),
         (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5, flags=0x4), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5,
+              flags=F.FV_PLAN_NO_PERSIST | F.FV_PLAN_PER_CLASS), F.FV_ERR_INVALID_ARG),
     ]
     for kw, status in bad:
         st, h = F.fv_plan_create(raise_on_error=False, **kw)

@@ -1,7 +1,8 @@
 """Batching form (plans) vs the CPU oracle through the C ABI (needs a gfx950 GPU).
 
 A plan runs every size class of a mixed batch in one fused launch (persistent
-or one wave per task), per-class launches for 3D and 2D p > 62, and captures k
+or one wave per task) or in one launch per class, per-class launches for 3D and
+2D p > 62 in every mode, and captures k
 steps with a device-side time step in a hipGraph.  Tolerance as for the plain
 launch: 1e-12 per-unknown relative max-norm, and the same for lambda and for the
 device-formed time steps.
@@ -73,32 +74,87 @@ def check_against_oracle(batch, dts, periodic, got, got_lams):
     assert max(hp.lambda_error(g, w) for g, w in zip(got_lams, want_lams)) <= TOL
 
 
-@pytest.mark.parametrize("persistent", [True, False])
-def test_plan_mixed_sizes(persistent):
+@pytest.mark.parametrize("mode", ["persistent", "per_task", "per_class"])
+def test_plan_mixed_sizes(mode):
     from paper_2306_16731_amd import fvpatch
-    _announce(f"plan: 3000 mixed {{3,5,9,17}}^2, 6 steps, persistent={persistent}")
+    _announce(f"plan: 3000 mixed {{3,5,9,17}}^2, 6 steps, mode={mode}")
     b, _ = wl.build_workload("c3_2d_mixed_T200000", seed=21, num_patches=3000)
     dts = oracle_dts(b, 5, False, 1.5e-3)
-    got, lams, info = run_plan(b, dts, False, 0 if persistent else fvpatch.FV_PLAN_NO_PERSIST)
-    assert info["num_class_launches"] == 0 and info["num_tasks"] > 0 and info["persistent"] == int(persistent)
+    flags = {"persistent": 0, "per_task": fvpatch.FV_PLAN_NO_PERSIST, "per_class": fvpatch.FV_PLAN_PER_CLASS}[mode]
+    got, lams, info = run_plan(b, dts, False, flags)
+    if mode == "per_class":
+        assert info["num_class_launches"] == 4 and info["num_tasks"] == 0
+    else:
+        assert info["num_class_launches"] == 0 and info["num_tasks"] > 0
+        assert info["persistent"] == int(mode == "persistent")
     check_against_oracle(b, dts, False, got, lams)
 
 
 @pytest.mark.parametrize("periodic", [False, True])
-def test_plan_mixed_sizes_runtime_size_bodies(periodic):
-    """The task list with every class on the runtime-size wave kernel (the fixed-size build switched
-    off), so both task bodies stay covered."""
+def test_plan_modes_agree_bitwise(periodic):
+    """The fused launch and the per-class launches run the same fixed-size bodies in the same
+    order of operations, whatever their load and store widths: outputs and eigenvalues agree bit
+    for bit with each other and with the plain per-batch launch, on gapped offsets."""
+    import torch
     from paper_2306_16731_amd import fvpatch
-    _announce(f"plan: mixed sizes, runtime-size bodies, periodic={periodic}")
-    b, _ = wl.build_workload("c3_2d_mixed_T200000", seed=24, num_patches=1500)
+    _announce(f"plan modes bitwise, periodic={periodic}")
+    rng = np.random.Generator(np.random.PCG64(41))
+    sizes = rng.choice(np.array([3, 5, 9, 16, 17, 30], np.int32), size=700)
+    compact = wl.make_batch(sizes, 2, 5, seed=42)
+    vols = (sizes.astype(np.int64) + 2) ** 2 * 5
+    # every patch starts at an even double (16-byte loads and stores for the even-sized classes
+    # p = 16, 30), or, periodic case, from the first p = 16 patch on at shifted parity
+    gaps = rng.integers(0, 3, size=len(sizes)) * 2 + vols % 2
+    if periodic:
+        gaps[int(np.argmax(sizes == 16))] += 1
+    starts = np.cumsum(np.concatenate([[0], (vols + gaps)[:-1]])).astype(np.int64)
+    data = np.zeros(int(starts[-1] + vols[-1] + 2))
+    for t in range(len(sizes)):
+        data[starts[t]:starts[t] + vols[t]] = compact.data[compact.offsets[t]:compact.offsets[t] + vols[t]]
+    batch = wl.Batch(data=data, sizes=sizes, offsets=starts, dim=2, nq=5)
+    dts = [1.1e-3, 0.9e-3]
+    results = {}
+    for mode, flags in [("persistent", 0), ("per_task", fvpatch.FV_PLAN_NO_PERSIST),
+                        ("per_class", fvpatch.FV_PLAN_PER_CLASS)]:
+        got, lams, info = run_plan(batch, dts, periodic, flags)
+        results[mode] = (got, np.stack(lams))
+    fl = fvpatch.FV_HALO_PERIODIC if periodic else 0
+    a = hp.to_dev(data)
+    b2 = a.clone()
+    lam = torch.empty((len(dts), len(sizes)), dtype=torch.float64, device="cuda")
+    for s, dt in enumerate(dts):
+        fvpatch.fv_patch_batch_update(a, b2, sizes, starts, len(sizes), 2, 5, dt, wl.H_DEFAULT, wl.GAMMA, fl, lam[s])
+        a, b2 = b2, a
+    torch.cuda.synchronize()
+    results["plain"] = (a.cpu().numpy(), lam.cpu().numpy())
+    ref = results["per_class"]
+    for mode, (got, lams) in results.items():
+        assert np.array_equal(got, ref[0]) and np.array_equal(lams, ref[1]), mode
+    mask = np.zeros(len(data), bool)
+    for t in range(len(sizes)):
+        mask[starts[t]:starts[t] + vols[t]] = True
+    assert np.array_equal(ref[0][~mask], data[~mask])
+    want, want_lams = oracle.run_steps(data, sizes, starts, 2, 5, dts, wl.H_DEFAULT, wl.GAMMA, periodic)
+    assert np.all(hp.component_errors(ref[0][mask], want[mask], 5) <= TOL)
+    assert max(hp.lambda_error(g, w) for g, w in zip(ref[1], want_lams)) <= TOL
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("persistent", [True, False])
+def test_plan_mixed_sizes_runtime_size_bodies(periodic, persistent):
+    """The task list with runtime-size bodies (sizes without a fixed-size build, tuned rows and
+    prefetch) beside fixed-size ones, so both task bodies stay covered in both task orders."""
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"plan: mixed sizes, runtime-size bodies, periodic={periodic}, persistent={persistent}")
+    b = wl.make_mixed(1500, choices=(4, 7, 12, 20, 9), seed=24)
     try:
-        for p in (3, 5, 9, 17):
+        for p in (4, 7, 12, 20):
             fvpatch.fv_set_tuning(2, 5, p, dict(kernel=fvpatch.FV_KERNEL_WAVE, block=256, prefetch=3, rows=4))
         dts = oracle_dts(b, 3, periodic, 1.5e-3)
-        got, lams, info = run_plan(b, dts, periodic)
+        got, lams, info = run_plan(b, dts, periodic, 0 if persistent else fvpatch.FV_PLAN_NO_PERSIST)
         assert info["prefetch"] == 3
     finally:
-        for p in (3, 5, 9, 17):
+        for p in (4, 7, 12, 20):
             fvpatch.fv_set_tuning(2, 5, p, None)
     check_against_oracle(b, dts, periodic, got, lams)
 
@@ -137,20 +193,23 @@ def test_plan_3d():
     check_against_oracle(b, dts, False, got, lams)
 
 
-@pytest.mark.parametrize("name,T,periodic", [("c3_2d_mixed_T200000", 2500, False), ("c4_3d_p8_T32768", 200, False),
-                                             ("c2_2d_p16_T65536", 600, True)])
-def test_graph_replay_with_device_dt(name, T, periodic):
+@pytest.mark.parametrize("name,T,periodic,per_class", [("c3_2d_mixed_T200000", 2500, False, False),
+                                                       ("c3_2d_mixed_T200000", 2500, True, True),
+                                                       ("c4_3d_p8_T32768", 200, False, False),
+                                                       ("c2_2d_p16_T65536", 600, True, False)])
+def test_graph_replay_with_device_dt(name, T, periodic, per_class):
     """k steps captured in one graph; step sizes formed on the device from each step's
     eigenvalues.  Replayed twice with eager work and synchronisations in between;
     every replay is checked against the oracle run with the device's step sizes,
     and those step sizes against the ones the oracle's own eigenvalues give."""
     import torch
     from paper_2306_16731_amd import fvpatch
-    _announce(f"graph: {name} T={T}, 5 steps x 2 replays")
+    _announce(f"graph: {name} T={T}, periodic={periodic}, per_class={per_class}, 5 steps x 2 replays")
     b, _ = wl.build_workload(name, seed=23, num_patches=T)
     steps = 5
     plan = fvpatch.fv_plan_create(b.sizes, b.offsets, b.num_patches, b.dim, b.nq,
-                                  fvpatch.FV_HALO_PERIODIC if periodic else 0)
+                                  (fvpatch.FV_HALO_PERIODIC if periodic else 0) |
+                                  (fvpatch.FV_PLAN_PER_CLASS if per_class else 0))
     try:
         bufa = hp.to_dev(b.data)
         bufb = bufa.clone()
