@@ -90,9 +90,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patches", type=int, default=8192,
                     help="patches the CPU oracle advances through all warmup + timed steps")
-    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer", "pde"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer", "pde", "latency"],
+                    default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
-                         "plans and captured graphs (one line each).  serving: the request loop (config 5)")
+                         "plans and captured graphs (one line each).  serving: the request loop (config 5).  "
+                         "latency: launch-to-done p50/p99 of config 1 (16 patches of 3^2, cache-resident)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
     ap.add_argument("--tuning-table", default=None, help="install this autotuner table instead of tuning now")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -125,6 +127,8 @@ def main() -> int:
         return bench_pde(args)
     if args.form == "batching":
         return bench_batching(args)
+    if args.form == "latency":
+        return bench_latency(args)
     if args.form == "serving":
         from paper_2306_16731_amd import serving
         return serving.bench_main(args)
@@ -279,6 +283,75 @@ def _timed(fn, steps: int) -> float:
         fn()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def bench_latency(args, samples: int = 4000) -> int:
+    """Config 1 (16 patches of 3 x 3, 2D Euler, one step): 19 KB of state, so the step is bound by
+    launch and completion latency, not by HBM.  For the plain call, a plan's fused launch and a
+    one-step captured graph: host time from the call to the stream's completion, per sample
+    (p50 / p99 / max), and the device time per launch when launches run back to back.  The plain call
+    runs twice: with an offsets array (uploaded with the call) and contiguous (offsets NULL, nothing
+    uploaded)."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    name = "c1_2d_p3_T16"
+    b, spec = wl.build_workload(name, seed=args.seed)
+    T, dim, nq = b.num_patches, b.dim, b.nq
+    flags = fvpatch.FV_HALO_PERIODIC if spec["periodic"] else 0
+    h, dt = wl.H_DEFAULT, 1.0e-3
+    stream = torch.cuda.Stream()
+    a = torch.from_numpy(b.data).to("cuda")
+    c = a.clone()
+    lam = torch.empty(T, dtype=torch.float64, device="cuda")
+    dt_dev = torch.full((2,), dt, dtype=torch.float64, device="cuda")
+    plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, flags)
+    try:
+        torch.cuda.synchronize()
+        fvpatch.fv_plan_capture_steps(plan, 1, a, c, h, wl.GAMMA, wl.CFL, lam, dt_dev, stream)
+        paths = {
+            "plain": lambda: fvpatch.fv_patch_batch_update(a, c, b.sizes, b.offsets, T, dim, nq, dt, h, wl.GAMMA,
+                                                           flags, lam, stream=stream),
+            "plain_contiguous": lambda: fvpatch.fv_patch_batch_update(a, c, b.sizes, None, T, dim, nq, dt, h,
+                                                                      wl.GAMMA, flags, lam, stream=stream),
+            "plan": lambda: fvpatch.fv_plan_execute(plan, a, c, dt, h, wl.GAMMA, lam, stream=stream),
+            "graph": lambda: fvpatch.fv_plan_replay(plan, stream),
+        }
+        for path, call in paths.items():
+            for _ in range(200):
+                call()
+            stream.synchronize()
+            lat = np.empty(samples)
+            for i in range(samples):
+                t0 = time.perf_counter()
+                call()
+                stream.synchronize()
+                lat[i] = time.perf_counter() - t0
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            n = 1000
+            e0.record(stream)
+            for _ in range(n):
+                call()
+            e1.record(stream)
+            e1.synchronize()
+            us = lat * 1e6
+            line = {"metric": "launch-to-done latency", "form": "latency", "path": path,
+                    "p50_us": round(float(np.percentile(us, 50)), 2), "p99_us": round(float(np.percentile(us, 99)), 2),
+                    "max_us": round(float(us.max()), 2), "samples": samples, "unit": "us",
+                    "device_us_per_launch_back_to_back": round(e0.elapsed_time(e1) * 1e3 / n, 2),
+                    "cell_updates_per_call": int(b.interior_volumes()), "dtype": "f64", "data": "synthetic",
+                    "higher_is_better": False,
+                    "config": {"workload": name, "patches": T, "p": int(b.sizes[0]), "dim": dim, "unknowns": nq,
+                               "state_bytes": int(b.data.nbytes)},
+                    "timing": "host perf_counter from the call to hipStreamSynchronize's return, per sample"}
+            print(json.dumps(line), flush=True)
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+    return 0
 
 
 def bench_flavours(args) -> int:
