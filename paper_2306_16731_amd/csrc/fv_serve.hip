@@ -13,9 +13,9 @@
 // and retired when their completion event has fired, which records the
 // arrival-to-completion latency.
 //
-// Two launch modes: FV_SERVE_FUSED builds the batch's task list (largest
-// patches first) in pinned staging memory and runs the whole batch in one
-// fused launch; FV_SERVE_PLAIN runs each batch through the plain per-batch
+// Two launch modes: FV_SERVE_FUSED builds the batch's task list (one wave per
+// task, tasks in memory order) in pinned staging memory and runs the whole
+// batch in one fused launch; FV_SERVE_PLAIN runs each batch through the plain per-batch
 // path (validation, grouping by size, one launch per size class).
 #include <hip/hip_runtime.h>
 
@@ -161,8 +161,9 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
         if (!count[p]) continue;
         if (dim == 2 && wave2d_fits(p)) {
             const fv_tuning tu = tuning_for(dim, nq, p);
-            // rows == 0: the fixed-size form of the kernel
-            const bool fixed = tu.kernel == FV_KERNEL_FIXED;
+            // rows == 0: the fixed-size form of the kernel, which a class built in that form
+            // always runs here (as in a plan's fused launch)
+            const bool fixed = tu.kernel == FV_KERNEL_FIXED || wave2d_fixed(p, nq);
             const int rows = fixed ? 0 : (tu.kernel == FV_KERNEL_WAVE && tu.rows > 0 ? tu.rows : 6);
             const int ppw = 64 / (p + 2);
             for (int32_t f = 0; f < count[p]; f += ppw)
@@ -177,6 +178,9 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
             classes.push_back(Cls{p, start[p], count[p]});
         }
     }
+    // one wave per task: tasks in memory order keep the resident waves on neighbouring patches
+    std::stable_sort(htask, htask + ntask,
+                     [&](const WaveTask &a, const WaveTask &b) { return hin[a.first] < hin[b.first]; });
     const size_t bytes = (size_t)(reinterpret_cast<char *>(htask + ntask) - static_cast<char *>(st.host));
     if (hipMemcpyAsync(st.dev, st.host, bytes, hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return fail(FV_ERR_LAUNCH, "descriptor upload failed");
