@@ -262,3 +262,47 @@ def test_plan_replay_without_capture_is_an_error():
                                              raise_on_error=False) == fvpatch.FV_ERR_INVALID_ARG  # null stream
     finally:
         fvpatch.fv_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("name,mode", [("c3_2d_mixed_T200000", "per_task"), ("c4_3d_p8_T32768", "persistent")])
+def test_full_size_graph_sampled(name, mode):
+    """Configs 3 and 4 at their full sizes in the launch the benchmark times (the plan mode it picks,
+    a captured 10-step graph with device dt): 96 sampled patches re-run by the oracle with the
+    device's dt sequence, their eigenvalues, and the last dt against the device's own eigenvalues."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"full size graph: {name}, mode={mode}, 10 steps, sampled check")
+    b, spec = wl.build_workload(name, seed=0)
+    T, dim, steps = b.num_patches, b.dim, 10
+    flags = {"persistent": 0, "per_task": fvpatch.FV_PLAN_NO_PERSIST}[mode]
+    plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, b.nq, flags)
+    try:
+        bufa = hp.to_dev(b.data)
+        bufb = bufa.clone()
+        lam = torch.empty(T, dtype=torch.float64, device="cuda")
+        dt_dev = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+        s = torch.cuda.Stream()
+        fvpatch.fv_plan_capture_steps(plan, steps, bufa, bufb, wl.H_DEFAULT, wl.GAMMA, wl.CFL, lam, dt_dev, s)
+        dt_dev[0] = 1.5e-3
+        torch.cuda.synchronize()
+        fvpatch.fv_plan_replay(plan, s)
+        s.synchronize()
+        dts = dt_dev.cpu().numpy()
+        lam_h = lam.cpu().numpy()
+        rng = np.random.Generator(np.random.PCG64(98))
+        sample = np.unique(np.concatenate([[0, T - 1], rng.choice(T, size=96, replace=False)]))
+        vols = (b.sizes[sample].astype(np.int64) + 2) ** dim * b.nq
+        sub_off = np.concatenate([[0], np.cumsum(vols)[:-1]]).astype(np.int64)
+        sub = np.concatenate([b.data[b.offsets[t]:b.offsets[t] + v] for t, v in zip(sample, vols)])
+        final = bufa if steps % 2 == 0 else bufb
+        got = np.concatenate([final[int(b.offsets[t]):int(b.offsets[t]) + int(v)].cpu().numpy()
+                              for t, v in zip(sample, vols)])
+        assert torch.isfinite(final).all().item() and np.all(np.isfinite(lam_h))
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+    want, want_lams = oracle.run_steps(sub, b.sizes[sample], sub_off, dim, b.nq, list(dts[:steps]), wl.H_DEFAULT,
+                                       wl.GAMMA, False)
+    assert np.all(hp.component_errors(got, want, b.nq) <= TOL)
+    assert hp.lambda_error(lam_h[sample], want_lams[-1]) <= TOL
+    np.testing.assert_allclose(dts[steps], wl.CFL * wl.H_DEFAULT / (dim * float(np.max(lam_h))), rtol=TOL, atol=0)
+    assert np.all(dts[1:] > 0) and np.all(np.isfinite(dts))
