@@ -300,11 +300,23 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
     L.gamma = gamma;
     L.flags = flags;
     L.lambda_out = lambda_out;
-    if (shape.contiguous && !out_offsets) {
+    // Equal sizes at evenly spaced offsets (offsets[t] = offsets[0] + t s, s at least one patch):
+    // the launch of a contiguous batch from offsets[0] with stride s, no descriptors to upload.
+    int64_t base = 0, stride = shape.uniform_p > 0 ? patch_doubles(shape.uniform_p, dim, nq) : 0;
+    bool regular = shape.contiguous;
+    if (!shape.contiguous && !out_offsets && shape.uniform_p > 0) {
+        base = offsets[0];
+        if (T > 1) stride = offsets[1] - offsets[0];
+        regular = stride >= patch_doubles(shape.uniform_p, dim, nq);
+        for (int32_t t = 2; t < T && regular; ++t) regular = offsets[t] - offsets[t - 1] == stride;
+    }
+    if (regular && !out_offsets) {
+        L.in = in + base;
+        L.out = out + base;
         L.num_items = T;
         L.p = shape.uniform_p;
-        L.stride = patch_doubles(L.p, dim, nq);
-        L.vec2 = (L.stride % 2 == 0) && aligned16(in) && aligned16(out);
+        L.stride = stride;
+        L.vec2 = (L.stride % 2 == 0) && aligned16(L.in) && aligned16(L.out);
         tune(L);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));

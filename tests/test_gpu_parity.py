@@ -138,6 +138,42 @@ def test_ragged_offsets_with_gaps_unsorted_and_odd():
     assert max(hp.lambda_error(g, w) for g, w in zip(got_lams, want_lams)) <= TOL
 
 
+@pytest.mark.parametrize("dim,p,base,gap", [(2, 16, 0, 0), (2, 16, 1, 6), (2, 17, 2, 3), (2, 9, 3, 1), (3, 8, 1, 10)])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_evenly_spaced_offsets(dim, p, base, gap, periodic):
+    """Equal sizes at evenly spaced offsets (patch t at base + t (patch + gap)) run as a contiguous
+    launch from the first patch, with no descriptors uploaded: the result must equal, bit for bit,
+    the same patches at offsets that are not evenly spaced (the descriptor path), leave the gaps
+    untouched, and match the oracle."""
+    _announce(f"evenly spaced offsets dim={dim} p={p} base={base} gap={gap} periodic={periodic}")
+    T = 97
+    vol = (p + 2) ** dim * 5
+    compact = wl.make_uniform(T, p, dim=dim, seed=61)
+    rng = np.random.Generator(np.random.PCG64(62))
+    layouts = {"even": base + np.arange(T, dtype=np.int64) * (vol + gap)}
+    jitter = np.concatenate([[0], rng.integers(0, 3, size=T - 1)])   # one uneven gap at least
+    jitter[T // 2] = 1
+    layouts["uneven"] = base + np.arange(T, dtype=np.int64) * (vol + gap) + np.cumsum(jitter)
+    results = {}
+    for name, offs in layouts.items():
+        total = int(offs[-1] + vol + 4)
+        data = rng.uniform(-1, 1, total)
+        for t in range(T):
+            data[offs[t]:offs[t] + vol] = compact.data[t * vol:(t + 1) * vol]
+        got, lam = hp.gpu_step(data, compact.sizes, offs, dim, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, periodic)
+        mask = np.ones(total, bool)
+        for t in range(T):
+            mask[offs[t]:offs[t] + vol] = False
+        assert np.array_equal(got[mask], data[mask]), (name, "bytes outside the patches were written")
+        results[name] = (np.concatenate([got[o:o + vol] for o in offs]), lam)
+    assert np.array_equal(results["even"][0], results["uneven"][0])
+    assert np.array_equal(results["even"][1], results["uneven"][1])
+    want, want_lam = oracle.batch_update(compact.data, compact.sizes, compact.offsets, dim, 5, 1.2e-3,
+                                         wl.H_DEFAULT, wl.GAMMA, periodic)
+    assert np.all(hp.component_errors(results["even"][0], want, 5) <= TOL)
+    assert hp.lambda_error(results["even"][1], want_lam) <= TOL
+
+
 def test_single_patch_and_zero_patches():
     import torch
     from paper_2306_16731_amd import fvpatch
