@@ -78,6 +78,14 @@ typedef enum fv_status {
 
 /* flags */
 #define FV_HALO_PERIODIC 0x2u /* also write the self-wrapped face halo of each output patch */
+/* Without FV_HALO_PERIODIC: the caller allows the update to overwrite halo
+ * volumes of the output with the input's values at the same positions.  The
+ * fixed-size 2D kernels (N = 5) then write each interior row whole, its two
+ * x-halo volumes included, which saves HBM time: partly written cache lines
+ * cost more than whole ones.  Every output halo volume is afterwards either
+ * untouched or equal to the input's; the interior and lambda are the same as
+ * without the flag.  Ignored with FV_HALO_PERIODIC. */
+#define FV_HALO_FROM_IN 0x4u
 
 /* Largest interior size per axis this build accepts, per dimension. */
 #define FV_MAX_P_2D 64
@@ -102,7 +110,7 @@ typedef enum fv_status {
  *   unknowns     N: 5 (2D, 3D) or 4 (2D).
  *   dt, h        time step size and mesh width: finite and > 0.
  *   gamma        ratio of specific heats: finite and > 1.
- *   flags        0 or FV_HALO_PERIODIC.
+ *   flags        0, FV_HALO_PERIODIC and/or FV_HALO_FROM_IN.
  *   lambda_out   device [num_patches] or NULL: per-patch max eigenvalue of
  *                the new solution; NULL skips the reduction.
  *   stream       hipStream_t or NULL.
@@ -194,7 +202,8 @@ typedef struct fv_plan_stats {
 
 /* Build a plan for the composition (sizes, offsets as for
  * fv_patch_batch_update; offsets NULL = contiguous, equal sizes).  flags:
- * FV_HALO_PERIODIC, and FV_PLAN_NO_PERSIST or FV_PLAN_PER_CLASS.  Tuning
+ * FV_HALO_PERIODIC or FV_HALO_FROM_IN, and FV_PLAN_NO_PERSIST or
+ * FV_PLAN_PER_CLASS.  Tuning
  * installed later does not change an existing plan. */
 fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *offsets, int32_t num_patches,
                          int32_t dim, int32_t unknowns, uint32_t flags);

@@ -48,7 +48,8 @@ fv_status check_scalars(int32_t dim, int32_t nq, double dt, double h, double gam
     if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV_ERR_INVALID_ARG, "dt must be finite and > 0");
     if (!std::isfinite(h) || !(h > 0.0)) return fail(FV_ERR_INVALID_ARG, "h must be finite and > 0");
     if (!std::isfinite(gamma) || !(gamma > 1.0)) return fail(FV_ERR_INVALID_ARG, "gamma must be finite and > 1");
-    if (flags & ~FV_HALO_PERIODIC) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~FV_HALO_PERIODIC);
+    const uint32_t known = FV_HALO_PERIODIC | FV_HALO_FROM_IN;
+    if (flags & ~known) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~known);
     return FV_OK;
 }
 
@@ -435,7 +436,8 @@ fv_status fv_pde_batch_update(int32_t pde, const double *params, int32_t num_par
                                      flags, lambda_out, stream);
     if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FV_ERR_INVALID_ARG, "dt must be finite and > 0");
     if (!std::isfinite(h) || !(h > 0.0)) return fail(FV_ERR_INVALID_ARG, "h must be finite and > 0");
-    if (flags & ~FV_HALO_PERIODIC) return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~FV_HALO_PERIODIC);
+    if (flags & ~(FV_HALO_PERIODIC | FV_HALO_FROM_IN))
+        return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~(FV_HALO_PERIODIC | FV_HALO_FROM_IN));
     PdeArgs args;
     args.pde = pde;
     for (int k = 0; k < nprm; ++k) args.prm[k] = params[k];

@@ -153,9 +153,9 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     clear_error();
     if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
     *plan = nullptr;
-    fv_status st = check_scalars(dim, unknowns, 1.0, 1.0, 2.0, flags & FV_HALO_PERIODIC);
+    fv_status st = check_scalars(dim, unknowns, 1.0, 1.0, 2.0, flags & (FV_HALO_PERIODIC | FV_HALO_FROM_IN));
     if (st != FV_OK) return st;
-    if (flags & ~(FV_HALO_PERIODIC | FV_PLAN_NO_PERSIST | FV_PLAN_PER_CLASS))
+    if (flags & ~(FV_HALO_PERIODIC | FV_HALO_FROM_IN | FV_PLAN_NO_PERSIST | FV_PLAN_PER_CLASS))
         return fail(FV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if ((flags & FV_PLAN_NO_PERSIST) && (flags & FV_PLAN_PER_CLASS))
         return fail(FV_ERR_INVALID_ARG, "FV_PLAN_NO_PERSIST and FV_PLAN_PER_CLASS exclude each other");
@@ -171,7 +171,7 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     hipGetDevice(&pl->device);
     pl->dim = dim;
     pl->nq = unknowns;
-    pl->flags = flags & FV_HALO_PERIODIC;
+    pl->flags = flags & (FV_HALO_PERIODIC | FV_HALO_FROM_IN);
     pl->persistent = !(flags & (FV_PLAN_NO_PERSIST | FV_PLAN_PER_CLASS));
     const bool per_class = (flags & FV_PLAN_PER_CLASS) != 0;
     pl->num_patches = num_patches;

@@ -42,6 +42,7 @@ namespace fv {
 namespace {
 
 constexpr uint32_t kPeriodic = 0x2u;
+constexpr uint32_t kHaloFromIn = 0x4u;  // the output's halo volumes may take the input's values
 constexpr int kDefaultPrefetch2d = 4;
 constexpr int kDefaultRows2d = 6;
 
@@ -291,7 +292,7 @@ constexpr int fixed_ring_words() {
 // MESH: the face halos come from the neighbouring patches' interiors (the
 // halo volumes of a patch without a neighbour on that face are its own), and
 // patch t advances by dt[t] / h[t]; the output is the interior only.
-template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false>
+template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false>
 __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in, double *__restrict__ out,
                                                   const int64_t *__restrict__ offsets,
                                                   const int64_t *__restrict__ out_offsets,
@@ -301,6 +302,10 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                                                   double *__restrict__ lambda_out, double *ring,
                                                   MeshArgs mesh = MeshArgs{}) {
     static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
+    // WHOLE (without PERIODIC): the x-halo volumes of rows 1 .. p are written with their input
+    // values, so every output row is one contiguous run (partly written cache lines cost HBM time)
+    static_assert(!(WHOLE && (PERIODIC || MESH)), "whole rows are the non-periodic, non-mesh form");
+    constexpr bool kWholeRows = PERIODIC || WHOLE;
     constexpr int NQ = PDE::NQ, NV = PDE::NV;
     constexpr int W = P + 2;
     constexpr int ppw = 64 / W;
@@ -401,6 +406,13 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                 }
                 if (lambda_out) lmax = nanmax(lmax, PDE::template max_lambda<2>(qn, prm));
             }
+            if constexpr (WHOLE) {
+                if (active && !xin) {
+                    double *hrow = ring + (slot * R + rr) * ROWD;
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c) hrow[i * NQ + c] = qprev[c];
+                }
+            }
             if (rr == R - 1 || kk == P) {
                 const int nrows = rr + 1;
                 const int k0 = kk - rr;    // first output row in the ring
@@ -412,8 +424,8 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
                 wave_lds_fence();
-                if (PERIODIC) {
-                    // whole rows (x-halo volumes hold their wrapped copies)
+                if (kWholeRows) {
+                    // whole rows (x-halo volumes hold their wrapped copies, or their input values)
                     const int per = nrows * ROWD / VEC;
                     const int total = ppw * per;
 #pragma unroll
@@ -430,7 +442,7 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                             __builtin_nontemporal_store(ring[sl * R * ROWD + rem], out + base + rem);
                     }
                     // y-halo rows: row P+1 takes row 1, row 0 takes row P (interior columns)
-                    if (k0 == 1 || kk == P) {
+                    if (PERIODIC && (k0 == 1 || kk == P)) {
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
                             if (h == 0 ? k0 != 1 : kk != P) continue;
@@ -492,18 +504,19 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
 }
 
 // One task of the fixed-size form.
-template <int P, int VEC, bool PERIODIC>
+template <int P, int VEC, bool PERIODIC, bool WHOLE>
 __device__ __forceinline__ void fixed_task_body(const double *__restrict__ in, double *__restrict__ out,
                                              const int64_t *__restrict__ offsets,
                                              const int64_t *__restrict__ out_offsets,
                                              const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
                                              double *__restrict__ lambda_out, double *ring) {
-    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, 0, count, 0, r, 0.0,
-                                                     typename EulerPDE<5>::Params{gamma}, lambda_out, ring);
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, false, WHOLE>(in, out, offsets, out_offsets, ids, 0, count, 0,
+                                                                   r, 0.0, typename EulerPDE<5>::Params{gamma},
+                                                                   lambda_out, ring);
 }
 
 // Task-list body for a fixed size: false when p has no fixed-size build.
-template <int NQ, int VEC, bool PERIODIC>
+template <int NQ, int VEC, bool PERIODIC, bool WHOLE>
 __device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in, double *__restrict__ out,
                                            const int64_t *__restrict__ offsets,
                                            const int64_t *__restrict__ out_offsets,
@@ -513,11 +526,11 @@ __device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in,
         return false;
     } else {
         switch (p) {
-            case 3: fixed_task_body<3, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 5: fixed_task_body<5, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 9: fixed_task_body<9, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 16: fixed_task_body<16, VEC, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 17: fixed_task_body<17, 1, PERIODIC>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 3: fixed_task_body<3, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 5: fixed_task_body<5, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 9: fixed_task_body<9, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 16: fixed_task_body<16, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 17: fixed_task_body<17, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
         }
         return false;
     }
@@ -543,7 +556,7 @@ update2d_kernel(const double *__restrict__ in, double *__restrict__ out, const i
 }
 
 // Uniform launch of the fixed-size form.
-template <int P, int VEC, bool PERIODIC, bool MESH>
+template <int P, int VEC, bool PERIODIC, bool MESH, bool WHOLE>
 __global__ void __launch_bounds__(kFixedBlock)
 update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
@@ -555,10 +568,10 @@ update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
     const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
     if (item0 >= num_items) return;
     const double rr = r_dev ? *r_dev : r;
-    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items,
-                                                           stride, rr, 0.0, typename EulerPDE<5>::Params{gamma},
-                                                           lambda_out, lds + (size_t)wave * fixed_ring_words<P>(),
-                                                           mesh);
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, MESH, WHOLE>(in, out, offsets, out_offsets, ids, item0,
+                                                                  num_items, stride, rr, 0.0,
+                                                                  typename EulerPDE<5>::Params{gamma}, lambda_out,
+                                                                  lds + (size_t)wave * fixed_ring_words<P>(), mesh);
 }
 
 // The wave form for the other PDEs of Eq. 1 (fv_pde.h) at the fixed sizes: the
@@ -581,7 +594,7 @@ update2d_pde_kernel(const double *__restrict__ in, double *__restrict__ out, con
 // fixed-size form.  Each wave takes tasks gw, gw + nw, ... (nw = waves in
 // the grid), so a grid smaller than the task list is persistent; tasks sorted
 // largest first balance the tail.
-template <int NQ, int PF, int VEC, bool PERIODIC>
+template <int NQ, int PF, int VEC, bool PERIODIC, bool WHOLE>
 __global__ void __launch_bounds__(kTaskBlock)
 update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids,
@@ -598,7 +611,7 @@ update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, c
     for (int64_t t = gw; t < num_tasks; t += nw) {
         const WaveTask tk = tasks[t];
         const int64_t *to = out_offsets ? out_offsets + tk.first : nullptr;
-        if (tk.rows == 0 && fixed_task<NQ, VEC, PERIODIC>(tk.p, in, out, offsets + tk.first, to, ids + tk.first,
+        if (tk.rows == 0 && fixed_task<NQ, VEC, PERIODIC, WHOLE>(tk.p, in, out, offsets + tk.first, to, ids + tk.first,
                                                           tk.count, rr, gamma, lambda_out, ring))
             continue;
         wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, to, ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma,
@@ -639,7 +652,7 @@ hipError_t launch2d(const UpdateLaunch &L, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <int NQ, int PF, int VEC, bool PERIODIC>
+template <int NQ, int PF, int VEC, bool PERIODIC, bool WHOLE>
 hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
     const int B = kTaskBlock;
     const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)T.ring_words;
@@ -649,7 +662,7 @@ hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return hipErrorInvalidDevice;
     if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
-    const void *fn = reinterpret_cast<const void *>(&update2d_tasks_kernel<NQ, PF, VEC, PERIODIC>);
+    const void *fn = reinterpret_cast<const void *>(&update2d_tasks_kernel<NQ, PF, VEC, PERIODIC, WHOLE>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -661,7 +674,7 @@ hipError_t launch2d_tasks(const TaskLaunch &T, hipStream_t stream) {
         blocks = std::min<int64_t>(blocks, (int64_t)per_cu * cus);
     }
     if (blocks < 1) return hipSuccess;
-    hipLaunchKernelGGL((update2d_tasks_kernel<NQ, PF, VEC, PERIODIC>), dim3((unsigned)blocks), dim3(B), lds, stream,
+    hipLaunchKernelGGL((update2d_tasks_kernel<NQ, PF, VEC, PERIODIC, WHOLE>), dim3((unsigned)blocks), dim3(B), lds, stream,
                        T.in, T.out, T.offsets, T.out_offsets, T.ids, T.tasks, T.num_tasks, T.r, T.r_dev, T.gamma,
                        T.lambda_out, T.ring_words);
     return hipGetLastError();
@@ -689,20 +702,24 @@ int wave2d_ring_words(int p, int nq, int rows) {
     return ppw * rows * W * nq + ppw;
 }
 
-template <int NQ, int VEC, bool PERIODIC>
+template <int NQ, int VEC, bool PERIODIC, bool WHOLE>
 static hipError_t tasks_pf(const TaskLaunch &T, hipStream_t stream) {
     switch (T.prefetch > 0 ? T.prefetch : kDefaultPrefetch2d) {
-        case 1: return launch2d_tasks<NQ, 1, VEC, PERIODIC>(T, stream);
-        case 2: return launch2d_tasks<NQ, 2, VEC, PERIODIC>(T, stream);
-        case 3: return launch2d_tasks<NQ, 3, VEC, PERIODIC>(T, stream);
-        case 4: return launch2d_tasks<NQ, 4, VEC, PERIODIC>(T, stream);
+        case 1: return launch2d_tasks<NQ, 1, VEC, PERIODIC, WHOLE>(T, stream);
+        case 2: return launch2d_tasks<NQ, 2, VEC, PERIODIC, WHOLE>(T, stream);
+        case 3: return launch2d_tasks<NQ, 3, VEC, PERIODIC, WHOLE>(T, stream);
+        case 4: return launch2d_tasks<NQ, 4, VEC, PERIODIC, WHOLE>(T, stream);
     }
     return hipErrorInvalidValue;
 }
 
 template <int NQ, int VEC>
 static hipError_t tasks_periodic(const TaskLaunch &T, hipStream_t stream) {
-    return (T.flags & kPeriodic) ? tasks_pf<NQ, VEC, true>(T, stream) : tasks_pf<NQ, VEC, false>(T, stream);
+    if (T.flags & kPeriodic) return tasks_pf<NQ, VEC, true, false>(T, stream);
+    // whole output rows for the fixed-size bodies (N = 5) where the caller allows it
+    if constexpr (NQ == 5)
+        if (T.flags & kHaloFromIn) return tasks_pf<NQ, VEC, false, true>(T, stream);
+    return tasks_pf<NQ, VEC, false, false>(T, stream);
 }
 
 hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream) {
@@ -713,7 +730,7 @@ hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream) {
 }
 
 // Uniform launch of the fixed-size form over patches of one size.
-template <int P, int VEC, bool PERIODIC, bool MESH = false>
+template <int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false>
 static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
     constexpr int ppw = 64 / (P + 2);
     const int B = kFixedBlock;
@@ -726,12 +743,12 @@ static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return hipErrorInvalidDevice;
     if (lds > (size_t)lds_max) return hipErrorInvalidConfiguration;
-    const void *fn = reinterpret_cast<const void *>(&update2d_fixed_kernel<P, VEC, PERIODIC, MESH>);
+    const void *fn = reinterpret_cast<const void *>(&update2d_fixed_kernel<P, VEC, PERIODIC, MESH, WHOLE>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((update2d_fixed_kernel<P, VEC, PERIODIC, MESH>), dim3((unsigned)blocks), dim3(B), lds, stream,
+    hipLaunchKernelGGL((update2d_fixed_kernel<P, VEC, PERIODIC, MESH, WHOLE>), dim3((unsigned)blocks), dim3(B), lds, stream,
                        L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev, L.gamma,
                        L.lambda_out, L.mesh);
     return hipGetLastError();
@@ -740,7 +757,9 @@ static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
 template <int P, int VEC>
 static hipError_t fixed_periodic(const UpdateLaunch &L, hipStream_t stream) {
     if (L.mesh.neighbors) return (L.flags & kPeriodic) ? hipErrorInvalidValue : launch_fixed<P, VEC, false, true>(L, stream);
-    return (L.flags & kPeriodic) ? launch_fixed<P, VEC, true>(L, stream) : launch_fixed<P, VEC, false>(L, stream);
+    if (L.flags & kPeriodic) return launch_fixed<P, VEC, true>(L, stream);
+    if (L.flags & kHaloFromIn) return launch_fixed<P, VEC, false, false, true>(L, stream);
+    return launch_fixed<P, VEC, false>(L, stream);
 }
 
 bool wave2d_fixed(int p, int nq) { return nq == 5 && fixed_size(p); }

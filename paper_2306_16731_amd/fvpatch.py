@@ -43,6 +43,7 @@ EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_c
            "fv_last_error", "fv_version"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
+FV_HALO_FROM_IN = 0x4
 FV_PLAN_NO_PERSIST = 0x100
 FV_PLAN_PER_CLASS = 0x200
 FV_KERNEL_AUTO = 0

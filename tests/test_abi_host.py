@@ -46,7 +46,7 @@ def test_header_constants_match_binding():
     hdr = open(os.path.join(ROOT, "include", "fvpatch.h")).read()
     for name in ["FV_MAX_P_2D", "FV_MAX_P_3D"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name)
-    for name in ["FV_HALO_PERIODIC", "FV_PLAN_NO_PERSIST", "FV_PLAN_PER_CLASS"]:
+    for name in ["FV_HALO_PERIODIC", "FV_HALO_FROM_IN", "FV_PLAN_NO_PERSIST", "FV_PLAN_PER_CLASS"]:
         assert int(re.search(rf"#define {name} (0x[0-9a-f]+)u", hdr).group(1), 16) == getattr(F, name), name
     for name in ["FV_KERNEL_AUTO", "FV_KERNEL_BLOCK", "FV_KERNEL_WAVE", "FV_KERNEL_TILE", "FV_KERNEL_FIXED"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name), name
@@ -81,7 +81,7 @@ def test_status_strings():
     (dict(h=float("nan")), F.FV_ERR_INVALID_ARG),
     (dict(gamma=1.0), F.FV_ERR_INVALID_ARG),
     (dict(gamma=float("nan")), F.FV_ERR_INVALID_ARG),
-    (dict(flags=0x4), F.FV_ERR_INVALID_ARG),
+    (dict(flags=0x8), F.FV_ERR_INVALID_ARG),
     (dict(num_patches=-1), F.FV_ERR_INVALID_ARG),
     (dict(patches_in=0), F.FV_ERR_INVALID_ARG),
     (dict(patches_out=0), F.FV_ERR_INVALID_ARG),
@@ -143,7 +143,7 @@ def test_plan_validation_before_device():
         (dict(sizes=[4, 4], offsets=None, num_patches=0, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
         (dict(sizes=[4, 5], offsets=None, num_patches=2, dim=2, unknowns=5), F.FV_ERR_INVALID_ARG),
         (dict(sizes=[4, 4], offsets=[0, 10], num_patches=2, dim=2, unknowns=5), F.FV_ERR_OVERLAP),
-        (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5, flags=0x4), F.FV_ERR_INVALID_ARG),
+        (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5, flags=0x8), F.FV_ERR_INVALID_ARG),
         (dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5,
               flags=F.FV_PLAN_NO_PERSIST | F.FV_PLAN_PER_CLASS), F.FV_ERR_INVALID_ARG),
     ]

@@ -381,3 +381,85 @@ def test_fixed_3d_kernel_matches_block_kernel_bitwise(p, periodic):
                                          periodic)
     assert np.all(hp.component_errors(fc[0], want, 5) <= TOL)
     assert hp.lambda_error(fc[1], want_lam) <= TOL
+
+
+def _patch_masks(total, sizes, offsets, dim, nq):
+    """Boolean masks over the buffer: interior volumes, x-halo volumes of interior rows (2D), and
+    every volume of the patches."""
+    interior = np.zeros(total, bool)
+    xhalo = np.zeros(total, bool)
+    inside = np.zeros(total, bool)
+    for p, o in zip(sizes, offsets):
+        W = int(p) + 2
+        blk = np.zeros((W,) * dim + (nq,), bool)
+        inner = blk.copy()
+        inner[(slice(1, -1),) * dim] = True
+        xh = blk.copy()
+        if dim == 2:
+            xh[1:-1, 0] = True
+            xh[1:-1, -1] = True
+        n = W ** dim * nq
+        interior[o:o + n] = inner.reshape(-1)
+        xhalo[o:o + n] = xh.reshape(-1)
+        inside[o:o + n] = True
+    return interior, xhalo, inside
+
+
+@pytest.mark.parametrize("case", ["plain-3", "plain-5", "plain-9", "plain-16", "plain-17", "plain-7", "plain-3d",
+                                  "plan-mixed"])
+def test_halo_from_in(case):
+    """FV_HALO_FROM_IN: the interior and lambda equal, bit for bit, a step without the flag; every
+    output halo volume is either untouched or equal to the input's (the fixed-size 2D kernels write
+    the x-halo volumes of the interior rows, the other kernels none); bytes between patches stay
+    untouched."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"halo from input: {case}")
+    rng = np.random.Generator(np.random.PCG64(71))
+    dim = 3 if case == "plain-3d" else 2
+    if case == "plan-mixed":
+        sizes = rng.choice(np.array([3, 5, 7, 9, 16, 17], np.int32), size=600)
+    else:
+        p = 8 if case == "plain-3d" else int(case.split("-")[1])
+        sizes = np.full(150, p, np.int32)
+    vols = (sizes.astype(np.int64) + 2) ** dim * 5
+    offs = np.cumsum(np.concatenate([[2], (vols + 4)[:-1]])).astype(np.int64)
+    total = int(offs[-1] + vols[-1] + 3)
+    compact = wl.make_batch(sizes, dim, 5, seed=72)
+    data = rng.uniform(-1, 1, total)
+    for t in range(len(sizes)):
+        data[offs[t]:offs[t] + vols[t]] = compact.data[compact.offsets[t]:compact.offsets[t] + vols[t]]
+    filler = rng.uniform(-1, 1, total)   # the output buffer's prior contents
+    res = {}
+    for flag in (0, fvpatch.FV_HALO_FROM_IN):
+        a = hp.to_dev(data)
+        b = hp.to_dev(filler)
+        lam = torch.empty(len(sizes), dtype=torch.float64, device="cuda")
+        if case == "plan-mixed":
+            plan = fvpatch.fv_plan_create(sizes, offs, len(sizes), dim, 5, flag | fvpatch.FV_PLAN_NO_PERSIST)
+            try:
+                fvpatch.fv_plan_execute(plan, a, b, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, lam)
+                torch.cuda.synchronize()
+            finally:
+                fvpatch.fv_plan_destroy(plan)
+        else:
+            fvpatch.fv_patch_batch_update(a, b, sizes, offs, len(sizes), dim, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA,
+                                          flag, lam)
+            torch.cuda.synchronize()
+        res[flag] = (b.cpu().numpy(), lam.cpu().numpy())
+    interior, xhalo, inside = _patch_masks(total, sizes, offs, dim, 5)
+    (o0, l0), (o1, l1) = res[0], res[fvpatch.FV_HALO_FROM_IN]
+    assert np.array_equal(o1[interior], o0[interior]) and np.array_equal(l1, l0)
+    halo = inside & ~interior
+    assert np.array_equal(o0[halo], filler[halo])                       # without the flag: untouched
+    assert np.all((o1[halo] == filler[halo]) | (o1[halo] == data[halo]))
+    assert np.array_equal(o1[~inside], filler[~inside])                 # between patches: untouched
+    whole = np.isin(sizes, [3, 5, 9, 16, 17]) if dim == 2 else np.zeros(len(sizes), bool)
+    if whole.any():   # the whole-row form ran: the x-halo volumes of those patches took the input's values
+        xm = np.zeros(total, bool)
+        for t in np.nonzero(whole)[0]:
+            xm[offs[t]:offs[t] + vols[t]] = xhalo[offs[t]:offs[t] + vols[t]]
+        assert np.array_equal(o1[xm], data[xm])
+    want, want_lam = oracle.batch_update(data, sizes, offs, dim, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, False)
+    assert np.all(hp.component_errors(o1[interior], want[interior], 5) <= TOL)
+    assert hp.lambda_error(l1, want_lam) <= TOL
