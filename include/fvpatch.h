@@ -38,8 +38,9 @@
  * each patch's face halo as the self-wrap of its new interior (halo 0 takes
  * interior p, halo p+1 takes interior 1, per axis; corners untouched), so the
  * output can be fed straight back as the next step's input.  Other output
- * volumes are not touched.  Input and output must not overlap (use two
- * buffers and swap them between steps).
+ * volumes are not touched (unless FV_HALO_FROM_IN gives the halo volumes
+ * over, see below).  Input and output must not overlap (use two buffers and
+ * swap them between steps).
  *
  * Memory and ownership: patch and lambda buffers are DEVICE memory owned by
  * the caller; `sizes` and `offsets` are HOST arrays owned by the caller and
