@@ -44,7 +44,7 @@ struct fv_plan {
     bool even_offsets = true;  // every wave-task patch starts at an even double and has even rows
     struct Group {
         int32_t p, first, count;
-        bool even;  // every patch of the class starts at an even double and spans an even number
+        bool even;  // every patch of the class starts at an even double and spans an even number of them
     };
     std::vector<Group> groups;  // classes launched per class (3D, 2D p > 62; every class with FV_PLAN_PER_CLASS)
     // captured multi-step run

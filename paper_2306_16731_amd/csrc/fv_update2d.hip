@@ -70,17 +70,17 @@ __device__ __forceinline__ int small_div(int a, int b, float inv_b, int &rem) {
     return q;
 }
 
-// Write rows [k0, k0 + nrows) of the wave's patches from the LDS ring.
-// Periodic output covers whole rows (the x-halo volumes hold their wrapped
-// copies), otherwise only the interior volumes of each row.
+// Write rows [k0, k0 + nrows) of the wave's patches from the LDS ring: whole
+// rows (the x-halo volumes hold their wrapped copies, or their input values),
+// otherwise only the interior volumes of each row.
 template <int NQ, int VEC>
 __device__ __forceinline__ void flush_rows(double *__restrict__ out, const double *ring, const int64_t *bases,
-                                           int ppw, int R, int W, int P, int k0, int nrows, bool periodic,
+                                           int ppw, int R, int W, int P, int k0, int nrows, bool whole_rows,
                                            int lane) {
     typedef double dv2 __attribute__((ext_vector_type(2)));
     const int ROWD = W * NQ;
     const int64_t row = ROWD;
-    if (periodic) {
+    if (whole_rows) {
         // rows are contiguous in HBM and in the ring: nrows * ROWD doubles per patch
         const int per = nrows * ROWD / VEC;
         const float inv = 1.0f / (float)per;
@@ -148,6 +148,9 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
     double *dst = out + off_out + (int64_t)i * NQ;
     const int64_t row = (int64_t)W * NQ;
     const bool periodic = (flags & kPeriodic) != 0;
+    // the caller gave over the output's halo volumes: x-halo volumes of rows 1 .. p go out with
+    // their input values, so each output row is written whole
+    const bool whole = !periodic && (flags & kHaloFromIn) != 0;
 
     // LDS: the ring of R output rows of each of the wave's ppw patches, then their bases
     const int ring_words = ppw * R * W * NQ;
@@ -232,9 +235,14 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
             }
             if (lambda_out) lmax = nanmax(lmax, volume_lambda<2, NQ>(qn, gamma));
         }
+        if (k >= 2 && whole && active && !xin) {
+            double *srow = ring + ((size_t)slot * R + (k - 1 - k0)) * row;
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) srow[i * NQ + c] = qprev[c];
+        }
         if (k >= 2 && (k - k0 == R || k - 1 == P)) {
             wave_lds_fence();
-            flush_rows<NQ, VEC>(out, ring, bases, ppw, R, W, P, k0, k - k0, periodic, lane);
+            flush_rows<NQ, VEC>(out, ring, bases, ppw, R, W, P, k0, k - k0, periodic || whole, lane);
             wave_lds_fence();
             k0 = k;
         }
@@ -615,7 +623,8 @@ update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, c
                                                           tk.count, rr, gamma, lambda_out, ring))
             continue;
         wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, to, ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma,
-                                 PERIODIC ? kPeriodic : 0u, lambda_out, tk.rows > 0 ? tk.rows : kDefaultRows2d,
+                                 (PERIODIC ? kPeriodic : 0u) | (WHOLE ? kHaloFromIn : 0u), lambda_out,
+                                 tk.rows > 0 ? tk.rows : kDefaultRows2d,
                                  ring);
     }
 }

@@ -405,13 +405,13 @@ def _patch_masks(total, sizes, offsets, dim, nq):
     return interior, xhalo, inside
 
 
-@pytest.mark.parametrize("case", ["plain-3", "plain-5", "plain-9", "plain-16", "plain-17", "plain-7", "plain-3d",
-                                  "plan-mixed"])
+@pytest.mark.parametrize("case", ["plain-3", "plain-5", "plain-9", "plain-16", "plain-17", "plain-7", "plain-30",
+                                  "plain-3d", "plan-mixed"])
 def test_halo_from_in(case):
     """FV_HALO_FROM_IN: the interior and lambda equal, bit for bit, a step without the flag; every
-    output halo volume is either untouched or equal to the input's (the fixed-size 2D kernels write
-    the x-halo volumes of the interior rows, the other kernels none); bytes between patches stay
-    untouched."""
+    output halo volume is either untouched or equal to the input's (the 2D row-marching kernels,
+    fixed-size and runtime-size, write the x-halo volumes of the interior rows; the 3D kernels none);
+    bytes between patches stay untouched."""
     import torch
     from paper_2306_16731_amd import fvpatch
     _announce(f"halo from input: {case}")
@@ -454,7 +454,7 @@ def test_halo_from_in(case):
     assert np.array_equal(o0[halo], filler[halo])                       # without the flag: untouched
     assert np.all((o1[halo] == filler[halo]) | (o1[halo] == data[halo]))
     assert np.array_equal(o1[~inside], filler[~inside])                 # between patches: untouched
-    whole = np.isin(sizes, [3, 5, 9, 16, 17]) if dim == 2 else np.zeros(len(sizes), bool)
+    whole = (sizes + 2 <= 64) if dim == 2 else np.zeros(len(sizes), bool)
     if whole.any():   # the whole-row form ran: the x-halo volumes of those patches took the input's values
         xm = np.zeros(total, bool)
         for t in np.nonzero(whole)[0]:
