@@ -174,11 +174,14 @@ fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *tun
  * ---- Batching form: plans --------------------------------------------------
  *
  * A plan fixes a batch composition (sizes, offsets) once: it sorts the
- * patches by size, largest first, cuts every size class into wave tasks with
- * the launch parameters the tuning table holds for it, and uploads that work
- * list.  Each step is then ONE fused launch over all 2D classes with
- * p + 2 <= 64 (persistent: as many waves as fit the device walk the task
- * list), plus one launch per remaining class (3D, or 2D p > 62).  The plan
+ * patches by size, cuts every size class into wave tasks (the fixed-size body
+ * for p in {3, 5, 9, 16, 17} with N = 5, else the runtime-size body with the
+ * class's tuned rows), and uploads that work list.  Each step is then ONE
+ * fused launch over all 2D classes with p + 2 <= 64 -- a persistent grid
+ * walking the tasks largest first (default), or one wave per task with the
+ * tasks in memory order (FV_PLAN_NO_PERSIST) -- plus one launch per remaining
+ * class (3D, or 2D p > 62); FV_PLAN_PER_CLASS launches every class on its own
+ * kernel instead.  The plan
  * also captures k steps, with the time step formed on the device from each
  * step's eigenvalues, into one hipGraph that replays without host round
  * trips.  This is the paper's task fusion of T patch updates into one kernel
