@@ -787,7 +787,7 @@ def bench_batching(args) -> int:
             dts = dt_dev.cpu().numpy()
         finally:
             fvpatch.fv_plan_destroy(plan)
-        if dim == 2 and not periodic:
+        if not periodic:
             # the same plan with the output's halo volumes given over (FV_HALO_FROM_IN): whole output rows
             plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags | fvpatch.FV_HALO_FROM_IN)
             try:
@@ -816,7 +816,7 @@ def bench_batching(args) -> int:
                 line["device_dt"] = [float(x) for x in dts[:3]]
             if form == "plan_halo_from_in":
                 line["note"] = ("FV_HALO_FROM_IN: the output's halo volumes may take the input's values, so the "
-                                "fixed-size bodies write whole rows; algorithmic bytes counted without them")
+                                "row-marching kernels write whole rows; algorithmic bytes counted without them")
             print(json.dumps(line), flush=True)
         del a, c, lam
         torch.cuda.empty_cache()

@@ -81,9 +81,10 @@ typedef enum fv_status {
 #define FV_HALO_PERIODIC 0x2u /* also write the self-wrapped face halo of each output patch */
 /* Without FV_HALO_PERIODIC: the caller allows the update to overwrite halo
  * volumes of the output with the input's values at the same positions.  The
- * 2D row-marching kernels (p + 2 <= 64: the default for those sizes) then
- * write each interior row whole, its two x-halo volumes included, which saves
- * HBM time: partly written cache lines cost more than whole ones.  Every
+ * 2D row-marching kernels (p + 2 <= 64: the default for those sizes) and the
+ * 3D kernels built for p = 4 and 8 then write each interior row whole, its
+ * two x-halo volumes included, which saves HBM time: partly written cache
+ * lines cost more than whole ones.  Every
  * output halo volume is afterwards either untouched or equal to the input's;
  * the interior and lambda are the same as without the flag.  Ignored with
  * FV_HALO_PERIODIC. */

@@ -45,6 +45,7 @@ namespace fv {
 namespace {
 
 constexpr uint32_t kPeriodic3 = 0x2u;
+constexpr uint32_t kHaloFromIn3 = 0x4u;  // the output's halo volumes may take the input's values
 constexpr int kBlock3 = 64;
 
 template <int CTRL>
@@ -428,7 +429,7 @@ struct Shape3i {
     static_assert(P % R == 0, "bursts of whole rings");
 };
 
-template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false>
+template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false>
 __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, double *__restrict__ out,
                                                 const int64_t *__restrict__ offsets,
                                                 const int64_t *__restrict__ out_offsets,
@@ -438,6 +439,9 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
                                                 double *__restrict__ lambda_out, double *ring,
                                                 MeshArgs mesh = MeshArgs{}) {
     static_assert(!(MESH && PERIODIC), "a mesh takes its halos from neighbours, not by self-wrap");
+    // WHOLE (without PERIODIC): the x-halo volumes of the interior rows of each interior layer go
+    // out with their input values, so the rows 1 .. p of a layer are one contiguous run
+    static_assert(!(WHOLE && (PERIODIC || MESH)), "whole rows are the non-periodic, non-mesh form");
     constexpr int NQ = PDE::NQ, NV = PDE::NV;
     using S = Shape3i<P, NQ>;
     constexpr int W = S::W, LP = S::LP, ppw = S::ppw, PLANE = S::PLANE, PF = S::PF, R = S::R;
@@ -497,7 +501,7 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
     int tab[(S::ITERS + 1) / 2];
 #pragma unroll
     for (int t = 0; t < (S::ITERS + 1) / 2; ++t) tab[t] = 0;
-    if constexpr (!PERIODIC) {
+    if constexpr (!PERIODIC && !WHOLE) {
         constexpr int per_row = P * NQ, per_layer = P * per_row, per_slot = R * per_layer;
 #pragma unroll
         for (int jj = 0; jj < S::ITERS; ++jj) {
@@ -513,8 +517,9 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
     }
 
     double qprev[NQ], fzprev[NV], gzprev[NV], dprev[NV], lzprev = 0.0;
+    double qxprev[NQ];  // WHOLE: the lane's x-halo volume of the previous layer
 #pragma unroll
-    for (int c = 0; c < NQ; ++c) qprev[c] = 1.0;  // a finite state; the face it forms is never used
+    for (int c = 0; c < NQ; ++c) qprev[c] = qxprev[c] = 1.0;  // a finite state; the face it forms is never used
 #pragma unroll
     for (int c = 0; c < NV; ++c) fzprev[c] = gzprev[c] = dprev[c] = 0.0;
     double lmax = 0.0;
@@ -565,6 +570,15 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
 #pragma unroll
                         for (int c = 0; c < NQ; ++c) lay[((P + 1) * W + i) * NQ + c] = qn[c];
                 }
+                if constexpr (WHOLE) {
+                    // the x-halo volumes of this row, as read (left for xlo lanes, right for xhi)
+                    if (xlo)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lay[(j * W) * NQ + c] = qxprev[c];
+                    if (xhi)
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) lay[(j * W + P + 1) * NQ + c] = qxprev[c];
+                }
                 if (lambda_out) lmax = nanmax(lmax, PDE::template max_lambda<3>(qn, prm));
             }
             if (rr == R - 1 || kk == P) {
@@ -574,7 +588,18 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
                 asm volatile("" : "+v"(ln));
                 wave_fence();
                 auto ring_layer = [&](int sl, int ly) { return (sl * R + ly) * PLANE; };
-                if (PERIODIC) {
+                if constexpr (WHOLE) {
+                    // rows 1 .. p of each layer, whole
+                    auto body = [&](auto NLc) {
+                        constexpr int NL = decltype(NLc)::value;
+                        burst<VEC, ppw, NL, 1, P * W * NQ>(
+                            out, ring, bases, item0, num_items, ln,
+                            [&](int sl, int ly, int) { return ring_layer(sl, ly) + W * NQ; },
+                            [&](int ly, int) { return (int64_t)(k0 + ly) * PLANE + W * NQ; });
+                    };
+                    if (nl == R) body(std::integral_constant<int, R>{});
+                    else body(std::integral_constant<int, 1>{});
+                } else if (PERIODIC) {
                     auto body = [&](auto NLc) {
                         constexpr int NL = decltype(NLc)::value;
                         burst<VEC, ppw, NL, 1, P * W * NQ>(
@@ -617,6 +642,9 @@ __device__ __forceinline__ void wave_update3d_i(const double *__restrict__ in, d
         }
 #pragma unroll
         for (int c = 0; c < NQ; ++c) qprev[c] = q[c];
+        if constexpr (WHOLE)
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) qxprev[c] = qx[c];
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
             fzprev[c] = fz[c];
@@ -706,7 +734,7 @@ constexpr int wave3d_ring_words() {
     else return Shape3<P>::ring_words;
 }
 
-template <int P, int VEC, bool PERIODIC, bool MESH>
+template <int P, int VEC, bool PERIODIC, bool MESH, bool WHOLE>
 __global__ void __launch_bounds__(kBlock3)
 update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, const int64_t *__restrict__ offsets,
                       const int64_t *__restrict__ out_offsets, const int32_t *__restrict__ ids, int32_t num_items,
@@ -717,9 +745,10 @@ update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
     if constexpr (kInteriorMapped<P>) {
         const int64_t item0 = (int64_t)blockIdx.x * Shape3i<P>::ppw;
         if (item0 >= num_items) return;
-        wave_update3d_i<EulerPDE<5>, P, VEC, PERIODIC, MESH>(in, out, offsets, out_offsets, ids, item0, num_items,
-                                                             stride, rr, 0.0, typename EulerPDE<5>::Params{gamma},
-                                                             lambda_out, lds, mesh);
+        wave_update3d_i<EulerPDE<5>, P, VEC, PERIODIC, MESH, WHOLE>(in, out, offsets, out_offsets, ids, item0,
+                                                                    num_items, stride, rr, 0.0,
+                                                                    typename EulerPDE<5>::Params{gamma}, lambda_out,
+                                                                    lds, mesh);
     } else {
         const int64_t item0 = (int64_t)blockIdx.x * Shape3<P>::ppw;
         if (item0 >= num_items) return;
@@ -728,14 +757,14 @@ update3d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
     }
 }
 
-template <int P, int VEC, bool PERIODIC, bool MESH = false>
+template <int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false>
 hipError_t launch3d(const UpdateLaunch &L, hipStream_t stream) {
     constexpr int ppw = wave3d_ppw<P>();
     constexpr int words = wave3d_ring_words<P>();
     const int64_t blocks = ((int64_t)L.num_items + ppw - 1) / ppw;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(double) * (size_t)words;
-    hipLaunchKernelGGL((update3d_fixed_kernel<P, VEC, PERIODIC, MESH>), dim3((unsigned)blocks), dim3(kBlock3), lds,
+    hipLaunchKernelGGL((update3d_fixed_kernel<P, VEC, PERIODIC, MESH, WHOLE>), dim3((unsigned)blocks), dim3(kBlock3), lds,
                        stream, L.in, L.out, L.offsets, L.out_offsets, L.ids, L.num_items, L.stride, L.r, L.r_dev,
                        L.gamma, L.lambda_out, L.mesh);
     return hipGetLastError();
@@ -747,6 +776,11 @@ hipError_t launch3d_p(const UpdateLaunch &L, hipStream_t stream) {
     if (L.mesh.neighbors) {
         if (periodic) return hipErrorInvalidValue;
         return L.vec2 ? launch3d<P, 2, false, true>(L, stream) : launch3d<P, 1, false, true>(L, stream);
+    }
+    if constexpr (kInteriorMapped<P>) {
+        // whole rows where the caller gave the output's halo volumes over
+        if (!periodic && (L.flags & kHaloFromIn3))
+            return L.vec2 ? launch3d<P, 2, false, false, true>(L, stream) : launch3d<P, 1, false, false, true>(L, stream);
     }
     if (L.vec2) return periodic ? launch3d<P, 2, true>(L, stream) : launch3d<P, 2, false>(L, stream);
     return periodic ? launch3d<P, 1, true>(L, stream) : launch3d<P, 1, false>(L, stream);

@@ -398,6 +398,9 @@ def _patch_masks(total, sizes, offsets, dim, nq):
         if dim == 2:
             xh[1:-1, 0] = True
             xh[1:-1, -1] = True
+        else:   # axes (k, j, i): the x-halo volumes of the interior rows of the interior layers
+            xh[1:-1, 1:-1, 0] = True
+            xh[1:-1, 1:-1, -1] = True
         n = W ** dim * nq
         interior[o:o + n] = inner.reshape(-1)
         xhalo[o:o + n] = xh.reshape(-1)
@@ -406,22 +409,21 @@ def _patch_masks(total, sizes, offsets, dim, nq):
 
 
 @pytest.mark.parametrize("case", ["plain-3", "plain-5", "plain-9", "plain-16", "plain-17", "plain-7", "plain-30",
-                                  "plain-3d", "plan-mixed"])
+                                  "plain-3d-8", "plain-3d-4", "plain-3d-6", "plan-mixed"])
 def test_halo_from_in(case):
     """FV_HALO_FROM_IN: the interior and lambda equal, bit for bit, a step without the flag; every
     output halo volume is either untouched or equal to the input's (the 2D row-marching kernels,
-    fixed-size and runtime-size, write the x-halo volumes of the interior rows; the 3D kernels none);
-    bytes between patches stay untouched."""
+    fixed-size and runtime-size, and the 3D interior-mapped kernel (p = 4, 8) write the x-halo volumes
+    of the interior rows; the other kernels none); bytes between patches stay untouched."""
     import torch
     from paper_2306_16731_amd import fvpatch
     _announce(f"halo from input: {case}")
     rng = np.random.Generator(np.random.PCG64(71))
-    dim = 3 if case == "plain-3d" else 2
+    dim = 3 if case.startswith("plain-3d") else 2
     if case == "plan-mixed":
         sizes = rng.choice(np.array([3, 5, 7, 9, 16, 17], np.int32), size=600)
     else:
-        p = 8 if case == "plain-3d" else int(case.split("-")[1])
-        sizes = np.full(150, p, np.int32)
+        sizes = np.full(150, int(case.split("-")[-1]), np.int32)
     vols = (sizes.astype(np.int64) + 2) ** dim * 5
     offs = np.cumsum(np.concatenate([[2], (vols + 4)[:-1]])).astype(np.int64)
     total = int(offs[-1] + vols[-1] + 3)
@@ -454,7 +456,7 @@ def test_halo_from_in(case):
     assert np.array_equal(o0[halo], filler[halo])                       # without the flag: untouched
     assert np.all((o1[halo] == filler[halo]) | (o1[halo] == data[halo]))
     assert np.array_equal(o1[~inside], filler[~inside])                 # between patches: untouched
-    whole = (sizes + 2 <= 64) if dim == 2 else np.zeros(len(sizes), bool)
+    whole = (sizes + 2 <= 64) if dim == 2 else np.isin(sizes, [4, 8])
     if whole.any():   # the whole-row form ran: the x-halo volumes of those patches took the input's values
         xm = np.zeros(total, bool)
         for t in np.nonzero(whole)[0]:
