@@ -265,7 +265,7 @@ typedef struct fv_server_config {
     int32_t unknowns;     /* as for fv_patch_batch_update */
     double h;             /* mesh width */
     double gamma;         /* ratio of specific heats */
-    uint32_t flags;       /* 0 or FV_HALO_PERIODIC */
+    uint32_t flags;       /* 0, FV_HALO_PERIODIC or FV_HALO_FROM_IN */
     int32_t mode;         /* FV_SERVE_FUSED or FV_SERVE_PLAIN */
     int32_t max_inflight; /* batches running at once (0 = 8), at most 1024 */
     int32_t reserved;
@@ -403,7 +403,8 @@ fv_status fv_mesh_destroy(fv_mesh *mesh);
  *                          params {rho0 > 0, K0 > 0}.
  *   FV_PDE_ACOUSTICS_NCP   the same system written as B_n dQ/dx_n with F = 0.
  *
- * Layout, offsets, flags (FV_HALO_PERIODIC), lambda_out (per-patch max of l_n
+ * Layout, offsets, flags (FV_HALO_PERIODIC; FV_HALO_FROM_IN is accepted and
+ * lets the Euler kernels write whole rows), lambda_out (per-patch max of l_n
  * over the new interior), streams and errors as fv_patch_batch_update, with N
  * the PDE's unknowns; params: host [num_params], all finite.  The Euler
  * equations take every tuned kernel; the other PDEs run on the plane-marching

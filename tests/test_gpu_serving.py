@@ -60,13 +60,17 @@ def batch_sequence(M, n, seed, max_count=None):
     return seq
 
 
+@pytest.mark.parametrize("halo", ["periodic", "from_in"])
 @pytest.mark.parametrize("mode", [0, 1], ids=["fused", "plain"])
-def test_server_batches_match_oracle_2d(mode):
+def test_server_batches_match_oracle_2d(mode, halo):
+    """from_in: non-periodic with the output's halo volumes given over (whole-row writes); both
+    slots of a patch start with the same halos, so the state read back is the oracle's."""
     from paper_2306_16731_amd import fvpatch as fv
-    _announce(f"server 2D mixed, mode={mode}")
+    _announce(f"server 2D mixed, mode={mode}, halo={halo}")
     mesh = wl.make_mixed(300, (1, 3, 5, 9, 16, 17, 40, 63), dim=2, nq=5, seed=51)
     seq = batch_sequence(300, 40, 52)
-    srv = fv.fv_server_create(1 << 30, 2, 5, wl.H_DEFAULT, wl.GAMMA, fv.FV_HALO_PERIODIC, mode, 4)
+    flags = fv.FV_HALO_PERIODIC if halo == "periodic" else fv.FV_HALO_FROM_IN
+    srv = fv.fv_server_create(1 << 30, 2, 5, wl.H_DEFAULT, wl.GAMMA, flags, mode, 4)
     try:
         mid = fv.fv_server_add_mesh(srv, mesh.sizes, mesh.data)
         for first, count, dt in seq:
@@ -77,7 +81,7 @@ def test_server_batches_match_oracle_2d(mode):
         got = fv.fv_server_read_mesh(srv, mid, np.empty_like(mesh.data))
     finally:
         fv.fv_server_destroy(srv)
-    want = oracle_replay(mesh, seq)
+    want = oracle_replay(mesh, seq, periodic=halo == "periodic")
     assert np.all(hp.component_errors(got, want, 5) <= TOL)
 
 
