@@ -121,6 +121,10 @@ def test_valid_arguments_without_a_gpu_report_no_device():
     assert call(offsets=[0, 180, 360]) == F.FV_ERR_NO_DEVICE
     assert call(offsets=[360, 0, 180]) == F.FV_ERR_NO_DEVICE      # unsorted, disjoint
     assert call(lambda_out=None) == F.FV_ERR_NO_DEVICE
+    assert call(flags=F.FV_HALO_FROM_IN) == F.FV_ERR_NO_DEVICE       # a valid flag: fails only for want of a GPU
+    assert call(flags=F.FV_HALO_FROM_IN | F.FV_HALO_PERIODIC) == F.FV_ERR_NO_DEVICE
+    st, h = F.fv_plan_create([4, 4], None, 2, 2, 5, F.FV_HALO_FROM_IN | F.FV_PLAN_PER_CLASS, raise_on_error=False)
+    assert st == F.FV_ERR_NO_DEVICE and not h
 
 
 def test_error_raises_with_detail():
