@@ -8,12 +8,17 @@ face-halo write and the per-patch eigenvalue reduction, as one
 fv_patch_batch_update call per time step.  A "step" is one such call over the
 whole batch (one explicit Euler time step of every patch).
 
-Prints ONE JSON line with the metric (cell-updates/s over the timed steps,
-inputs resident in HBM), the roofline of the update kernel (algorithmic bytes
-per launch / average launch time, against 8 TB/s), and the CPU oracle timed on
-a bounded sample of the same workload on the host's cores.
+Prints ONE JSON line with the metric (cell-updates/s, inputs resident in HBM),
+the roofline of the update kernel (algorithmic bytes per launch / launch time,
+against 8 TB/s), and the CPU oracle timed on a bounded sample of the same
+workload on the host's cores.  Timing: W warmup steps, one K-step window
+reported on its own (the first launches of a process run slower), untimed steps
+up to 100 in all, then 16 windows of exactly K steps, each bracketed by device
+synchronisations and timed by HIP events on the launch stream; the headline is
+their median.  The same line carries config 1's launch-to-done latency and
+configs 3 and 4 (plain launches, plan, captured graph) under "extra".
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
@@ -84,13 +89,17 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=100,
-                    help="untimed steps first (about 40 ms: the GPU's clocks and TLBs settle)")
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed steps first; the headline samples start after at least 100 steps in all")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-patches", type=int, default=8192,
-                    help="patches the CPU oracle advances through all warmup + timed steps")
-    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer", "pde", "latency"],
+    ap.add_argument("--cpu-sample-patches", type=int, default=65536,
+                    help="at most this many patches for the CPU oracle (which advances them through the warmup "
+                         "and the first timed window); the sample is sized to about 16 core-seconds")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: skip the config-1 latency and config-3 / 4 batching keys")
+    ap.add_argument("--form", choices=["plain", "batching", "serving", "mesh", "flavours", "transfer", "pde", "latency",
+                                       "coldstart"],
                     default="plain",
                     help="plain: the headline line (config 2).  batching: configs 3 and 4 through plain launches, "
                          "plans and captured graphs (one line each).  serving: the request loop (config 5).  "
@@ -129,6 +138,8 @@ def main() -> int:
         return bench_batching(args)
     if args.form == "latency":
         return bench_latency(args)
+    if args.form == "coldstart":
+        return bench_coldstart(args)
     if args.form == "serving":
         from paper_2306_16731_amd import serving
         return serving.bench_main(args)
@@ -158,60 +169,41 @@ def main() -> int:
     torch.cuda.synchronize()
     dt = wl.CFL * h / (dim * float(lam.max().item()))
     d_b.copy_(d_a)
+    bufs = [d_a, d_b]
 
-    def step(src, dst):
-        fvpatch.fv_patch_batch_update(src, dst, b.sizes, None, T, dim, nq, dt, h, gamma, flags, lam, stream)
+    def step():
+        fvpatch.fv_patch_batch_update(bufs[0], bufs[1], b.sizes, None, T, dim, nq, dt, h, gamma, flags, lam, stream)
+        bufs.reverse()
 
     for _ in range(args.warmup):
-        step(d_a, d_b)
-        d_a, d_b = d_b, d_a
+        step()
     torch.cuda.synchronize()
 
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    # the first K-step window straight after the warmup, reported on its own: the first ~100
+    # launches of a process run slower (bench.py --form coldstart measures why)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step(d_a, d_b)
-        d_a, d_b = d_b, d_a
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    first_ms = _window_ms(step, args.steps, stream)
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
+    steps_done = args.warmup + args.steps
+    # the oracle's sample is compared against the state after these warmup + K steps
+    S = cpu_sample_patches(args, T, steps_done)
+    sample_state = bufs[0][: S * int(b.offsets[1])].clone()
+    settle = max(0, SETTLE_STEPS - steps_done)
+    for _ in range(settle):
+        step()
+    # the headline: median of SAMPLES windows of exactly K steps, each bracketed by device
+    # synchronisations and timed by HIP events on the launch stream
+    samples = sorted(_window_ms(step, args.steps, stream) for _ in range(SAMPLES))
+    ms_per_step = samples[len(samples) // 2]
     cells = T * p ** dim
-    value = cells * args.steps / (gpu_ms / 1e3)
+    value = cells / (ms_per_step / 1e3)
 
-    # the oracle's sample is compared against the state right after the timed steps
-    S = min(args.cpu_sample_patches, T)
-    sample_state = d_a[: S * int(b.offsets[1])].clone()
-
-    # the same K-step measurement repeated (median of 16 samples), then a plain device copy of the
-    # state as the streaming ceiling of this GPU (sanity check of the roofline)
-    samples = []
-    for _ in range(16):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            step(d_a, d_b)
-            d_a, d_b = d_b, d_a
-        e1.record(stream)
-        torch.cuda.synchronize()
-        samples.append(e0.elapsed_time(e1) / args.steps)
-    samples.sort()
+    # a plain device copy of the state: the streaming ceiling of this GPU (sanity check of the roofline)
     scratch = torch.empty_like(d_a)
     for _ in range(3):
         scratch.copy_(d_a)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        scratch.copy_(d_a)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2 * d_a.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    copy_ms = _window_ms(lambda: scratch.copy_(d_a), 10, stream)
+    copy_gbs = 2 * d_a.numel() * 8 / (copy_ms / 1e3) / 1e9
     del scratch
 
     per_launch = alg_bytes_per_patch(p, dim, nq, periodic, True) * T
@@ -233,45 +225,87 @@ def main() -> int:
                    "eigenvalue_reduction": True, "path": "fv_patch_batch_update", "dt": dt, "h": h},
         "dof_updates_per_s": round(value * nq, 1),
         "roofline": roofline,
-        "host_wall_s": round(wall, 4),
-        "repeat": {"samples": len(samples), "median_ms_per_step": round(samples[len(samples) // 2], 5),
-                   "min_ms_per_step": round(samples[0], 5), "max_ms_per_step": round(samples[-1], 5)},
+        "timing": {"headline": f"median of {SAMPLES} windows of {args.steps} steps, HIP events on the launch "
+                               "stream, device synchronised around each window",
+                   "settle_steps": settle, "samples_ms_per_step": [round(s, 5) for s in samples],
+                   "first_window_ms_per_step": round(first_ms, 5),
+                   "first_window_frac": round(per_launch / (first_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "first_window_host_wall_s": round(wall, 4)},
         "tuning": fvpatch.fv_get_tuning(dim, nq, p),
     }
+    del bufs, d_a, d_b, lam
+    torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         import oracle
-        steps_total = args.warmup + args.steps
         sub = b.data[: S * int(b.offsets[1])]
         threads = oracle.max_threads()
         t0 = time.perf_counter()
-        ora_state, _ = oracle.run_steps(sub, b.sizes[:S], b.offsets[:S], dim, nq, [dt] * steps_total, h, gamma,
+        ora_state, _ = oracle.run_steps(sub, b.sizes[:S], b.offsets[:S], dim, nq, [dt] * steps_done, h, gamma,
                                         periodic, nthreads=threads)
         cpu_s = time.perf_counter() - t0
         # one thread on a smaller sample of the same patches and steps
         S1 = max(1, S // 16)
         t1 = time.perf_counter()
-        oracle.run_steps(b.data[: S1 * int(b.offsets[1])], b.sizes[:S1], b.offsets[:S1], dim, nq, [dt] * steps_total,
+        oracle.run_steps(b.data[: S1 * int(b.offsets[1])], b.sizes[:S1], b.offsets[:S1], dim, nq, [dt] * steps_done,
                          h, gamma, periodic, nthreads=1)
         cpu1_s = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": round(S * p ** dim * steps_total / cpu_s, 1), "unit": "cell-updates/s",
+        out["cpu_baseline"] = {"value": round(S * p ** dim * steps_done / cpu_s, 1), "unit": "cell-updates/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": f"first {S} of the {T} patches, {steps_total} steps, same dt, "
+                               "sample": f"first {S} of the {T} patches, {steps_done} steps, same dt, "
                                          f"OpenMP over patches ({cpu_s:.2f} s wall)",
-                               "single_thread": {"value": round(S1 * p ** dim * steps_total / cpu1_s, 1),
-                                                 "sample": f"first {S1} patches, {steps_total} steps "
+                               "single_thread": {"value": round(S1 * p ** dim * steps_done / cpu1_s, 1),
+                                                 "sample": f"first {S1} patches, {steps_done} steps "
                                                            f"({cpu1_s:.2f} s wall)"},
                                "cpu_work_core_s": round(cpu_s * threads + cpu1_s, 1),
                                "host_cpus_visible": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
-        # the timed GPU run advanced the same patches with the same dt: compare them
+        # the GPU run advanced the same patches with the same dt: compare them
         got = sample_state.cpu().numpy()
         g = got.reshape(-1, nq)
         w = ora_state.reshape(-1, nq)
         errs = np.max(np.abs(g - w), axis=0) / np.max(np.abs(w), axis=0)
-        out["parity_sample"] = {"patches": S, "steps": steps_total, "max_rel_err": float(np.max(errs)),
+        out["parity_sample"] = {"patches": S, "steps": steps_done, "max_rel_err": float(np.max(errs)),
                                 "tolerance": 1e-12}
+    del sample_state
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["extra"] = extra_configs(args)
     print(json.dumps(out), flush=True)
     return 0
+
+
+SETTLE_STEPS = 100  # untimed steps (warmup included) before the headline samples
+SAMPLES = 16        # K-step windows whose median is the headline
+CPU_TARGET_CORE_S = 16.0  # CPU work of the oracle's sample, in core-seconds
+ORACLE_US_PER_PATCH_STEP = 40.0  # one core, one 16 x 16 patch, one step (measured on the host CPUs)
+
+
+def cpu_sample_patches(args, T: int, steps: int) -> int:
+    """Patches the oracle advances through all warmup + first-window steps: about
+    CPU_TARGET_CORE_S core-seconds of work, a multiple of 256, at most --cpu-sample-patches."""
+    s = int(CPU_TARGET_CORE_S / (ORACLE_US_PER_PATCH_STEP * 1e-6 * max(1, steps)))
+    s = max(256, min(args.cpu_sample_patches, T, s))
+    return s // 256 * 256
+
+
+def _window_ms(fn, steps: int, stream) -> float:
+    """Milliseconds per call over `steps` calls of fn: HIP events recorded on `stream` around
+    them, the device synchronised before and after."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _median_window_ms(fn, steps: int, samples: int, stream) -> float:
+    ts = sorted(_window_ms(fn, steps, stream) for _ in range(samples))
+    return ts[len(ts) // 2]
 
 
 def _timed(fn, steps: int) -> float:
@@ -287,11 +321,17 @@ def _timed(fn, steps: int) -> float:
 
 def bench_latency(args, samples: int = 4000) -> int:
     """Config 1 (16 patches of 3 x 3, 2D Euler, one step): 19 KB of state, so the step is bound by
-    launch and completion latency, not by HBM.  For the plain call, a plan's fused launch and a
-    one-step captured graph: host time from the call to the stream's completion, per sample
-    (p50 / p99 / max), and the device time per launch when launches run back to back.  The plain call
-    runs twice: with an offsets array (uploaded with the call) and contiguous (offsets NULL, nothing
-    uploaded)."""
+    launch and completion latency, not by HBM.  One JSON line per path (latency_lines)."""
+    for line in latency_lines(args, samples):
+        print(json.dumps(line), flush=True)
+    return 0
+
+
+def latency_lines(args, samples: int) -> list:
+    """For the plain call, a plan's fused launch and a one-step captured graph: host time from the
+    call to the stream's completion, per sample (p50 / p99 / max), and the device time per launch when
+    launches run back to back.  The plain call runs twice: with an offsets array (evenly spaced, so
+    nothing is uploaded) and contiguous (offsets NULL)."""
     import numpy as np
     import torch
 
@@ -308,9 +348,10 @@ def bench_latency(args, samples: int = 4000) -> int:
     c = a.clone()
     lam = torch.empty(T, dtype=torch.float64, device="cuda")
     dt_dev = torch.full((2,), dt, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, flags)
+    lines = []
     try:
-        torch.cuda.synchronize()
         fvpatch.fv_plan_capture_steps(plan, 1, a, c, h, wl.GAMMA, wl.CFL, lam, dt_dev, stream)
         paths = {
             "plain": lambda: fvpatch.fv_patch_batch_update(a, c, b.sizes, b.offsets, T, dim, nq, dt, h, wl.GAMMA,
@@ -339,18 +380,99 @@ def bench_latency(args, samples: int = 4000) -> int:
             e1.record(stream)
             e1.synchronize()
             us = lat * 1e6
-            line = {"metric": "launch-to-done latency", "form": "latency", "path": path,
-                    "p50_us": round(float(np.percentile(us, 50)), 2), "p99_us": round(float(np.percentile(us, 99)), 2),
-                    "max_us": round(float(us.max()), 2), "samples": samples, "unit": "us",
-                    "device_us_per_launch_back_to_back": round(e0.elapsed_time(e1) * 1e3 / n, 2),
-                    "cell_updates_per_call": int(b.interior_volumes()), "dtype": "f64", "data": "synthetic",
-                    "higher_is_better": False,
-                    "config": {"workload": name, "patches": T, "p": int(b.sizes[0]), "dim": dim, "unknowns": nq,
-                               "state_bytes": int(b.data.nbytes)},
-                    "timing": "host perf_counter from the call to hipStreamSynchronize's return, per sample"}
-            print(json.dumps(line), flush=True)
+            lines.append({"metric": "launch-to-done latency", "form": "latency", "path": path,
+                          "p50_us": round(float(np.percentile(us, 50)), 2),
+                          "p99_us": round(float(np.percentile(us, 99)), 2),
+                          "max_us": round(float(us.max()), 2), "samples": samples, "unit": "us",
+                          "device_us_per_launch_back_to_back": round(e0.elapsed_time(e1) * 1e3 / n, 2),
+                          "cell_updates_per_call": int(b.interior_volumes()), "dtype": "f64", "data": "synthetic",
+                          "higher_is_better": False,
+                          "config": {"workload": name, "patches": T, "p": int(b.sizes[0]), "dim": dim,
+                                     "unknowns": nq, "state_bytes": int(b.data.nbytes)},
+                          "timing": "host perf_counter from the call to hipStreamSynchronize's return, per sample"})
     finally:
         fvpatch.fv_plan_destroy(plan)
+    return lines
+
+
+def extra_configs(args) -> dict:
+    """The other configurations on the headline line: config 1's launch-to-done latency (p50 / p99)
+    and configs 3 and 4 through plain launches, a plan and the captured 10-step graph (ms per step and
+    fraction of the HBM roofline).  Class tunings are the library's defaults (every class of configs 3
+    and 4 has a fixed-size build, which the fused launch runs whatever the tuning); config 3's plan
+    launch mode is picked by timing the three modes (autotune.tune_plan)."""
+    t0 = time.perf_counter()
+    extra = {"c1_latency_us": {}}
+    for line in latency_lines(args, 2000):
+        extra["c1_latency_us"][line["path"]] = {k: line[k] for k in ("p50_us", "p99_us", "max_us")}
+    for name in ("c3_2d_mixed_T200000", "c4_3d_p8_T32768"):
+        r = batching_case(name, args, tune_plan_mode=True)
+        e = {"cells_per_step": r["cells"], "alg_bytes_per_step": r["alg_bytes"], "plan_mode": r["plan_choice"]["mode"]}
+        for form, ms in r["ms"].items():
+            e[form + "_ms"] = round(ms, 4)
+            e[form + "_frac"] = round(r["alg_bytes"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        e["speedup_plan_vs_plain"] = round(r["ms"]["plain"] / r["ms"]["plan"], 3)
+        e["speedup_graph_vs_plain"] = round(r["ms"]["plain"] / r["ms"]["graph"], 3)
+        extra[name] = e
+    extra["timing"] = ("configs 3 / 4: median of 5 windows of 10 steps per form, HIP events on one stream, "
+                       "host launch work inside the window; graph: one 10-step replay per window")
+    extra["seconds"] = round(time.perf_counter() - t0, 1)
+    return extra
+
+
+def bench_coldstart(args) -> int:
+    """Where the slow first launches of a process come from.  Config 2's plain launch, one HIP event
+    between consecutive launches, in three phases: (a) the first 150 launches of the process; (b) 50 more
+    on the same buffers after the GPU sat idle for 2 s (if the clocks drop when idle, the slow start comes
+    back here); (c) 50 on freshly allocated buffers while the GPU is busy and warm (new pages: if address
+    translation is the cause, the slow start comes back here).  Prints one JSON line per phase with the
+    per-launch times and their mean over launch windows."""
+    import numpy as np
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    name = "c2_2d_p16_T65536"
+    b, spec = wl.build_workload(name, seed=args.seed)
+    T, dim, nq = b.num_patches, b.dim, b.nq
+    flags = fvpatch.FV_HALO_PERIODIC
+    h, gamma, dt = wl.H_DEFAULT, wl.GAMMA, 1.0e-3
+    stream = torch.cuda.current_stream()
+    per_launch = alg_bytes_per_patch(16, dim, nq, True, True) * T
+
+    def run(a, c, n):
+        lam = torch.empty(T, dtype=torch.float64, device="cuda")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        bufs = [a, c]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(n):
+            fvpatch.fv_patch_batch_update(bufs[0], bufs[1], b.sizes, None, T, dim, nq, dt, h, gamma, flags, lam,
+                                          stream)
+            bufs.reverse()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(n)])
+
+    a = torch.from_numpy(b.data).to("cuda")
+    c = a.clone()
+    phases = {"a_fresh_process": run(a, c, 150)}
+    time.sleep(2.0)
+    phases["b_after_2s_idle_same_buffers"] = run(a, c, 50)
+    a2 = torch.empty_like(a)
+    c2 = torch.empty_like(c)
+    a2.copy_(a)  # warm GPU; a2's pages are new to the update kernel (the copy touched them once)
+    phases["c_fresh_buffers_warm_gpu"] = run(a2, c2, 50)
+    for phase, ms in phases.items():
+        win = [round(float(ms[i:i + 10].mean()), 4) for i in range(0, len(ms), 10)]
+        print(json.dumps({"form": "coldstart", "phase": phase, "launches": len(ms),
+                          "mean_ms_per_10_launches": win, "first_ms": round(float(ms[0]), 4),
+                          "last10_mean_ms": round(float(ms[-10:].mean()), 4),
+                          "first10_frac": round(per_launch / (float(ms[:10].mean()) / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "last10_frac": round(per_launch / (float(ms[-10:].mean()) / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "per_launch_ms": [round(float(x), 4) for x in ms],
+                          "config": {"workload": name}}), flush=True)
     return 0
 
 
@@ -722,104 +844,125 @@ def bench_mesh(args) -> int:
     return 0
 
 
-def bench_batching(args) -> int:
-    """Configs 3 (200000 mixed 2D patches) and 4 (32768 x 8^3): plain per-batch launches vs a plan's fused
-    launch vs the captured 10-step graph.  Wall time between device synchronisations (the plain path's host
-    work counts: it is what the plan removes)."""
+def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, samples: int = 5, tune=None) -> dict:
+    """One batching workload (config 3 or 4) through plain per-batch launches, a plan's fused launch,
+    the plan's captured `steps`-step graph with device dt and, when the workload is not periodic, the
+    plan with FV_HALO_FROM_IN.  ms per step: median of `samples` windows of `steps` steps, HIP events
+    on one stream (the plain path's host work, which the plan removes, is inside the window)."""
     import numpy as np
     import torch
 
     from paper_2306_16731_amd import autotune, fvpatch
     from paper_2306_16731_amd import workloads as wl
 
-    h, gamma, steps = wl.H_DEFAULT, wl.GAMMA, 10
-    t_tune = time.perf_counter()
-    if args.tuning_table:
-        autotune.load(args.tuning_table)
-        tuned = {"table": os.path.basename(args.tuning_table)}
+    h, gamma = wl.H_DEFAULT, wl.GAMMA
+    b, spec = wl.build_workload(name, seed=args.seed)
+    T, dim, nq = b.num_patches, b.dim, b.nq
+    periodic = spec["periodic"]
+    flags = fvpatch.FV_HALO_PERIODIC if periodic else 0
+    if dim == 2 and tune_plan_mode:
+        plan_choice = autotune.tune_plan(b, periodic, tune=tune)
+    elif dim == 2:
+        plan_choice = {"mode": "per_task", "flags": fvpatch.FV_PLAN_NO_PERSIST}
     else:
-        tuned = autotune.tune_classes([(2, 5, p) for p in (3, 5, 9, 17)] + [(3, 5, 8)], periodic=False)
-    t_tune = time.perf_counter() - t_tune
-    for name in ("c3_2d_mixed_T200000", "c4_3d_p8_T32768"):
-        b, spec = wl.build_workload(name, seed=args.seed)
-        T, dim, nq = b.num_patches, b.dim, b.nq
-        periodic = spec["periodic"]
-        flags = fvpatch.FV_HALO_PERIODIC if periodic else 0
-        cells = b.interior_volumes()
+        plan_choice = {"mode": "persistent", "flags": 0}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
         a = torch.from_numpy(b.data).to("cuda")
         c = a.clone()
         lam = torch.empty(T, dtype=torch.float64, device="cuda")
-        dt = 1.0e-3
-        bufs = [a, c]
+        dt_dev = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    dt = 1.0e-3
+    bufs = [a, c]
+    ms = {}
 
-        def plain():
-            fvpatch.fv_patch_batch_update(bufs[0], bufs[1], b.sizes, b.offsets, T, dim, nq, dt, h, gamma, flags, lam)
+    def plain():
+        fvpatch.fv_patch_batch_update(bufs[0], bufs[1], b.sizes, b.offsets, T, dim, nq, dt, h, gamma, flags, lam,
+                                      stream=s)
+        bufs.reverse()
+
+    for _ in range(3):
+        plain()
+    ms["plain"] = _median_window_ms(plain, steps, samples, s)
+    pflags = flags | plan_choice["flags"]
+    plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags, tune=tune)
+    try:
+        info = fvpatch.fv_plan_info(plan)
+
+        def fused():
+            fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam, stream=s)
             bufs.reverse()
 
-        for _ in range(args.warmup // 10 + 3):
-            plain()
-        results = {"plain": _timed(plain, steps) / steps}
-        plan_choice = autotune.tune_plan(b, periodic) if dim == 2 else {"mode": "persistent", "flags": 0}
-        pflags = flags | plan_choice["flags"]
-        plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags)
-        try:
-            info = fvpatch.fv_plan_info(plan)
+        for _ in range(3):
+            fused()
+        ms["plan"] = _median_window_ms(fused, steps, samples, s)
+        fvpatch.fv_plan_capture_steps(plan, steps, a, c, h, gamma, wl.CFL, lam, dt_dev, s)
 
-            def fused():
-                fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam)
+        def replay():
+            with torch.cuda.stream(s):
+                dt_dev[0] = dt
+            fvpatch.fv_plan_replay(plan, s)
+
+        for _ in range(2):
+            replay()
+        ms["graph"] = _median_window_ms(replay, 1, samples, s) / steps
+        dts = dt_dev.cpu().numpy()
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+    if not periodic:
+        plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags | fvpatch.FV_HALO_FROM_IN, tune=tune)
+        try:
+            def fused_whole():
+                fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam, stream=s)
                 bufs.reverse()
 
-            for _ in range(args.warmup // 10 + 3):
-                fused()
-            results["plan"] = _timed(fused, steps) / steps
-            dt_dev = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
-            stream = torch.cuda.Stream()
-            fvpatch.fv_plan_capture_steps(plan, steps, a, c, h, gamma, wl.CFL, lam, dt_dev, stream)
-
-            def replay():
-                dt_dev[0] = dt
-                fvpatch.fv_plan_replay(plan, stream)
-                stream.synchronize()
-
             for _ in range(3):
-                replay()
-            results["graph"] = _timed(replay, 5) / (5 * steps)
-            dts = dt_dev.cpu().numpy()
+                fused_whole()
+            ms["plan_halo_from_in"] = _median_window_ms(fused_whole, steps, samples, s)
         finally:
             fvpatch.fv_plan_destroy(plan)
-        if not periodic:
-            # the same plan with the output's halo volumes given over (FV_HALO_FROM_IN): whole output rows
-            plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, pflags | fvpatch.FV_HALO_FROM_IN)
-            try:
-                def fused_whole():
-                    fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam)
-                    bufs.reverse()
+    alg = float(np.sum([alg_bytes_per_patch(int(p), dim, nq, periodic, True) for p in b.sizes]))
+    del a, c, lam, bufs, dt_dev
+    torch.cuda.empty_cache()
+    return {"name": name, "ms": ms, "alg_bytes": alg, "cells": b.interior_volumes(), "T": T, "dim": dim,
+            "periodic": periodic, "plan_info": info, "plan_choice": plan_choice, "device_dt": [float(x) for x in dts[:3]],
+            "steps": steps}
 
-                for _ in range(args.warmup // 10 + 3):
-                    fused_whole()
-                results["plan_halo_from_in"] = _timed(fused_whole, steps) / steps
-            finally:
-                fvpatch.fv_plan_destroy(plan)
-        per_patch = [alg_bytes_per_patch(int(p), dim, nq, periodic, True) for p in b.sizes]
-        alg = float(np.sum(per_patch))
-        for form, sec in results.items():
-            line = {"metric": "cell-updates/s", "value": round(cells / sec, 1), "unit": "cell-updates/s",
-                    "form": form, "ms_per_step": round(sec * 1e3, 4), "alg_GBs": round(alg / sec / 1e9, 1),
-                    "hbm_frac": round(alg / sec / 1e9 / HBM_PEAK_GBS, 4),
-                    "speedup_vs_plain": round(results["plain"] / sec, 3), "dtype": "f64", "data": "synthetic",
-                    "config": {"workload": name, "patches": T, "dim": dim, "steps": steps, "cells_per_step": cells,
-                               "periodic_halo": periodic},
-                    "plan": info if form != "plain" else None,
-                    "plan_work_split": plan_choice if form != "plain" else None,
-                    "timing": "wall time between device synchronisations, host work included"}
+
+def bench_batching(args) -> int:
+    """Configs 3 (200000 mixed 2D patches) and 4 (32768 x 8^3): plain per-batch launches vs a plan's fused
+    launch vs the captured 10-step graph, after the autotuner has set every class (or a table is loaded)."""
+    from paper_2306_16731_amd import autotune
+
+    t_tune = time.perf_counter()
+    if args.tuning_table:
+        entries = autotune.load(args.tuning_table)["entries"]
+        tuned = {"table": os.path.basename(args.tuning_table)}
+    else:
+        # installed process-wide for the plain launches; the plans get the same table as their own
+        entries = tuned = autotune.tune_classes([(2, 5, p) for p in (3, 5, 9, 17)] + [(3, 5, 8)], periodic=False)
+    table = autotune.plan_table(entries)
+    t_tune = time.perf_counter() - t_tune
+    for name in ("c3_2d_mixed_T200000", "c4_3d_p8_T32768"):
+        r = batching_case(name, args, tune_plan_mode=True, tune=table)
+        for form, ms in r["ms"].items():
+            sec = ms / 1e3
+            line = {"metric": "cell-updates/s", "value": round(r["cells"] / sec, 1), "unit": "cell-updates/s",
+                    "form": form, "ms_per_step": round(ms, 4), "alg_GBs": round(r["alg_bytes"] / sec / 1e9, 1),
+                    "hbm_frac": round(r["alg_bytes"] / sec / 1e9 / HBM_PEAK_GBS, 4),
+                    "speedup_vs_plain": round(r["ms"]["plain"] / ms, 3), "dtype": "f64", "data": "synthetic",
+                    "config": {"workload": name, "patches": r["T"], "dim": r["dim"], "steps": r["steps"],
+                               "cells_per_step": r["cells"], "periodic_halo": r["periodic"]},
+                    "plan": r["plan_info"] if form != "plain" else None,
+                    "plan_work_split": r["plan_choice"] if form != "plain" else None,
+                    "timing": "median of 5 windows of 10 steps, HIP events on one stream, host work included"}
             if form == "graph":
-                line["device_dt"] = [float(x) for x in dts[:3]]
+                line["device_dt"] = r["device_dt"]
             if form == "plan_halo_from_in":
                 line["note"] = ("FV_HALO_FROM_IN: the output's halo volumes may take the input's values, so the "
                                 "row-marching kernels write whole rows; algorithmic bytes counted without them")
             print(json.dumps(line), flush=True)
-        del a, c, lam
-        torch.cuda.empty_cache()
     print(json.dumps({"autotune_seconds": round(t_tune, 2), "tuning": tuned}), flush=True)
     return 0
 

@@ -129,8 +129,9 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
 /*
  * Launch parameters of the update kernel for one patch class (dim, unknowns,
  * p).  The library picks defaults; the autotuner measures candidates and
- * installs the fastest.  Settings are process-wide and apply to every later
- * call (plain launches and plans built afterwards) on every device.
+ * installs the fastest.  Installed settings are process-wide defaults: they
+ * apply to every later plain launch on every device and to plans built
+ * afterwards for classes their own tuning table does not cover.
  *
  *   kernel    FV_KERNEL_AUTO, FV_KERNEL_BLOCK (plane-marching kernel, any
  *             size), FV_KERNEL_WAVE (2D only: one padded patch row per
@@ -182,11 +183,11 @@ fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *tun
  * walking the tasks largest first (default), or one wave per task with the
  * tasks in memory order (FV_PLAN_NO_PERSIST) -- plus one launch per remaining
  * class (3D, or 2D p > 62); FV_PLAN_PER_CLASS launches every class on its own
- * kernel instead.  The plan
+ * kernel instead.  Each plan may carry its own tuning table.  The plan
  * also captures k steps, with the time step formed on the device from each
  * step's eigenvalues, into one hipGraph that replays without host round
  * trips.  This is the paper's task fusion of T patch updates into one kernel
- * (Sec. 2.1) with the precompiled task graph it proposes (Sec. 6, Sec. 8).
+ * (Sec. 2.1) with the precompiled task graph it proposes (Sec. 5; outlook, Sec. 6).
  * Plans are single-owner objects; they keep their own device memory.
  */
 typedef struct fv_plan fv_plan;
@@ -206,18 +207,48 @@ typedef struct fv_plan_stats {
     int32_t captured_steps;     /* steps in the captured graph, 0 if none */
 } fv_plan_stats;
 
+/* Launch parameters for one patch class in a plan's own tuning table. */
+typedef struct fv_tune_entry {
+    int32_t dim;
+    int32_t unknowns;
+    int32_t p;
+    fv_tuning tuning; /* as for fv_set_tuning */
+} fv_tune_entry;
+
 /* Build a plan for the composition (sizes, offsets as for
  * fv_patch_batch_update; offsets NULL = contiguous, equal sizes).  flags:
  * FV_HALO_PERIODIC or FV_HALO_FROM_IN, and FV_PLAN_NO_PERSIST or
- * FV_PLAN_PER_CLASS.  Tuning
- * installed later does not change an existing plan. */
+ * FV_PLAN_PER_CLASS.
+ * tune_table (host [tune_entries], NULL when tune_entries = 0; read during
+ * the call only): the plan's own launch parameters per size class, e.g. an
+ * autotuner's table.  Entries for another (dim, unknowns) are ignored; each
+ * other entry is checked as fv_set_tuning checks its argument (its error is
+ * returned), two entries for one p are FV_ERR_INVALID_ARG.  A class without
+ * an entry takes the parameters installed by fv_set_tuning at creation time,
+ * else the defaults.  The plan keeps what it resolved: fv_set_tuning later,
+ * or another plan's table, does not change it (fv_plan_get_tuning reports
+ * it).  In the fused launch a class built in the fixed-size form runs that
+ * body whatever its tuning; tuning chooses the kernels of per-class launches
+ * (FV_PLAN_PER_CLASS, 3D, 2D p > 62) and the rows of runtime-size bodies. */
 fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *offsets, int32_t num_patches,
-                         int32_t dim, int32_t unknowns, uint32_t flags);
+                         int32_t dim, int32_t unknowns, uint32_t flags, const fv_tune_entry *tune_table,
+                         int32_t tune_entries);
+
+/* Launch parameters the plan resolved for its patches of size p
+ * (FV_ERR_INVALID_ARG if it has none of that size). */
+fv_status fv_plan_get_tuning(const fv_plan *plan, int32_t p, fv_tuning *tuning);
 
 /* One step of every patch of the plan: like fv_patch_batch_update on the
- * plan's composition.  Asynchronous on `stream`. */
-fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patches_out, double dt, double h,
-                          double gamma, double *lambda_out, void *stream);
+ * plan's composition.  Asynchronous on `stream`.
+ * dt_dev: NULL, or a device double holding the step size, read when the step
+ * runs (dt is then ignored): a device-side time step, e.g. one a previous
+ * kernel derived from the eigenvalues; dt / h is formed on the device,
+ * correctly rounded, so the result equals a host dt of the same value bit for
+ * bit.  It must not overlap patches_out or lambda_out (FV_ERR_OVERLAP).  The
+ * plan holds one device word for dt / h: executes with dt_dev on different
+ * streams must not overlap in time. */
+fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patches_out, double dt,
+                          const double *dt_dev, double h, double gamma, double *lambda_out, void *stream);
 
 /* Capture `steps` steps into a graph: step k reads buf_a (k even) or buf_b
  * (k odd) and writes the other (the result of an even number of steps is in
@@ -247,12 +278,25 @@ fv_status fv_plan_destroy(fv_plan *plan);
  * mesh's patch state resident in HBM -- two state slots per patch, each patch
  * ping-ponging on its own -- so no patch data crosses PCIe after registration
  * (the recycled device memory of Sec. 4 "Data transfer", without the copies).
- * A batch names a contiguous range of a mesh's patches and a time step.
+ * Meshes may differ in dimension, unknowns and mesh width (a 2D mesh of mixed
+ * patch sizes next to a 3D one): they share the server's stream and budget.
+ * A batch names a contiguous range of one mesh's patches and a time step.
  * Batches are admitted in arrival order while the resident bytes plus the
  * bytes of the batches in flight fit `budget_bytes` and fewer than
  * `max_inflight` are running; otherwise they wait (none is dropped).  Each
  * batch's latency runs from its arrival to the moment the loop sees its
  * completion event.  Servers are single-owner objects with their own stream.
+ *
+ * Failures.  A batch whose completion event reports an error (any status but
+ * "not ready") is re-run: its patches' state from before it is still in their
+ * input slots (no update writes in place), so the batch is queued first again
+ * and writes its output slots anew, up to max_retries times.  When its
+ * retries are spent (its patches then keep their state from before it), or
+ * when a later batch in flight has already read its output (the state of
+ * those patches is lost), fv_server_poll / _drain / _run_trace return
+ * FV_ERR_LAUNCH with the detail in fv_last_error(); the server can go on.
+ * With deadline_ms > 0 a batch still running that long after its launch makes
+ * them return FV_ERR_LAUNCH instead of waiting (the batch stays in flight).
  */
 typedef struct fv_server fv_server;
 
@@ -261,14 +305,12 @@ typedef struct fv_server fv_server;
 
 typedef struct fv_server_config {
     int64_t budget_bytes; /* HBM budget for resident state plus in-flight batches */
-    int32_t dim;          /* 2 or 3 */
-    int32_t unknowns;     /* as for fv_patch_batch_update */
-    double h;             /* mesh width */
     double gamma;         /* ratio of specific heats */
     uint32_t flags;       /* 0, FV_HALO_PERIODIC or FV_HALO_FROM_IN */
     int32_t mode;         /* FV_SERVE_FUSED or FV_SERVE_PLAIN */
     int32_t max_inflight; /* batches running at once (0 = 8), at most 1024 */
-    int32_t reserved;
+    int32_t max_retries;  /* re-runs of a batch whose completion reports an error, 0..16 */
+    double deadline_ms;   /* > 0: longest a batch may run before poll / drain fail; 0 = none */
 } fv_server_config;
 
 typedef struct fv_serve_request {
@@ -283,21 +325,38 @@ typedef struct fv_serve_request {
 typedef struct fv_server_stats {
     int64_t submitted, completed, queued, inflight, peak_queued, peak_inflight;
     int64_t cells_updated;  /* interior volumes updated by completed batches */
+    int64_t failed;         /* batches given up after errors */
+    int64_t retried;        /* re-runs after errors */
     int64_t resident_bytes, budget_bytes;
     double p50_ms, p99_ms, max_ms, mean_ms; /* arrival-to-completion latency of completed batches */
     double cell_updates_per_s;               /* completed cells / (last completion - first arrival) */
 } fv_server_stats;
 
+/* One completed batch (fv_server_batch_log); times in ns since the server's creation. */
+typedef struct fv_batch_record {
+    int64_t ticket;
+    int64_t arrival_ns;  /* arrival */
+    int64_t launch_ns;   /* its launches were enqueued */
+    int64_t done_ns;     /* the loop saw its completion */
+    int64_t cells;       /* interior volumes updated */
+    int32_t mesh;
+    int32_t count;       /* patches */
+    int32_t retries;     /* re-runs it took */
+    int32_t reserved;
+} fv_batch_record;
+
 fv_status fv_server_create(fv_server **server, const fv_server_config *cfg);
 
-/* Register a mesh: num_patches patches of the given sizes, stored contiguously
- * in host_state (layout as for fv_patch_batch_update with offsets NULL but
- * sizes free to differ); uploads it into both slots.  FV_ERR_BUDGET if its two
- * slots do not fit the budget. */
-fv_status fv_server_add_mesh(fv_server *server, const int32_t *sizes, int32_t num_patches, const double *host_state,
-                             int32_t *mesh_id);
+/* Register a mesh: num_patches patches of the given sizes in `dim`
+ * dimensions with `unknowns` unknowns (as for fv_patch_batch_update) and mesh
+ * width h, stored contiguously in host_state (layout as for
+ * fv_patch_batch_update with offsets NULL but sizes free to differ); uploads
+ * it into both slots.  FV_ERR_BUDGET if its two slots do not fit the budget. */
+fv_status fv_server_add_mesh(fv_server *server, int32_t dim, int32_t unknowns, double h, const int32_t *sizes,
+                             int32_t num_patches, const double *host_state, int32_t *mesh_id);
 
-/* Queue a batch (arrival_ns <= 0: now, on the server's steady clock in ns). */
+/* Queue a batch (arrival_ns <= 0: now, on the server's steady clock in ns).
+ * *ticket (optional) receives its ticket: 1, 2, ... in submission order. */
 fv_status fv_server_submit(fv_server *server, int32_t mesh_id, int32_t first, int32_t count, double dt,
                            int64_t arrival_ns, int64_t *ticket);
 
@@ -317,6 +376,20 @@ fv_status fv_server_run_trace(fv_server *server, const fv_serve_request *reqs, i
 fv_status fv_server_read_mesh(fv_server *server, int32_t mesh_id, double *host_state);
 
 fv_status fv_server_stats_get(fv_server *server, fv_server_stats *stats);
+
+/* Records of the completed batches in completion order: the first
+ * min(capacity, completed) into `records`; *count = all of them. */
+fv_status fv_server_batch_log(fv_server *server, fv_batch_record *records, int64_t capacity, int64_t *count);
+
+/* Test hook for the failure handling (the GPU is never made to fault): the
+ * batch with this ticket runs normally, but its completion check reports
+ *   FV_INJECT_FAIL  a launch failure, on its next `times` completions (each
+ *                   re-run completes once);
+ *   FV_INJECT_HANG  "not ready", until the injection is cleared;
+ * kind 0 clears the ticket's injection. */
+#define FV_INJECT_FAIL 1
+#define FV_INJECT_HANG 2
+fv_status fv_server_inject(fv_server *server, int64_t ticket, int32_t kind, int32_t times);
 
 /* Wait for the server's stream, then free everything it holds (NULL: no-op). */
 fv_status fv_server_destroy(fv_server *server);
@@ -458,7 +531,7 @@ fv_status fv_flavour_update(int32_t flavour, const double *patches_in, double *p
                             double h, double gamma, uint32_t flags, double *lambda_out, void *stream);
 
 /* ------------------------------------------------------------------------
- * Patches in host memory (Sec. 5, data transfer; Sec. 6, Fig. 4).  In the
+ * Patches in host memory (Sec. 4, data transfer; Sec. 5, Fig. 4).  In the
  * paper every patch is a separate allocation on the CPU heap, brought to the
  * accelerator one by one; those scattered copies dominate its runtime.  This
  * call takes such patches, moves them through the fused update and writes
@@ -554,6 +627,11 @@ const char *fv_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t fv_version(void);
+
+/* Identity of the sources the library was built from: a 16-digit hex digest of
+ * every source and header (static storage; "unknown" for a build that did not
+ * set it).  Lets a loader refuse a library older than its sources. */
+const char *fv_build_id(void);
 
 #ifdef __cplusplus
 }

@@ -139,6 +139,18 @@ def tune_classes(classes, verbose: bool = False, periodic: bool = False) -> dict
     return {class_key(*c): tune_class(*c, verbose=verbose, periodic=periodic) for c in classes}
 
 
+def plan_table(entries: dict) -> dict:
+    """A plan's own tuning table ({(dim, nq, p): tuning}, for fv_plan_create's `tune`) from the
+    entries of tune_classes or of a saved table."""
+    out = {}
+    for key, e in entries.items():
+        if not e:
+            continue
+        dim, nq, p = (int(x) for x in key.split(","))
+        out[(dim, nq, p)] = {k: int(e[k]) for k in ("kernel", "block", "prefetch", "rows")}
+    return out
+
+
 def composition_key(sizes, dim: int, nq: int) -> str:
     vals, counts = np.unique(np.asarray(sizes), return_counts=True)
     return f"{dim},{nq}:" + ";".join(f"{int(v)}x{int(c)}" for v, c in zip(vals, counts))
@@ -147,15 +159,15 @@ def composition_key(sizes, dim: int, nq: int) -> str:
 PLAN_MODES = {"persistent": 0, "per_task": fv.FV_PLAN_NO_PERSIST, "per_class": fv.FV_PLAN_PER_CLASS}
 
 
-def tune_plan(batch: wl.Batch, periodic: bool = False, steps: int = 10, warmup: int = 10) -> dict:
+def tune_plan(batch: wl.Batch, periodic: bool = False, steps: int = 10, warmup: int = 10, tune=None) -> dict:
     """The plan's launch mode for a batch composition, by timing: the fused launch on a persistent
-    grid, the fused launch with one wave per task, or one launch per size class.  Returns
-    {"mode", "flags", "ms", "ms_<mode>" for each mode}."""
+    grid, the fused launch with one wave per task, or one launch per size class (each plan with the
+    tuning table `tune`, if given).  Returns {"mode", "flags", "ms", "ms_<mode>" for each mode}."""
     import torch
     res = {}
     for mode, mflags in PLAN_MODES.items():
         flags = (fv.FV_HALO_PERIODIC if periodic else 0) | mflags
-        plan = fv.fv_plan_create(batch.sizes, batch.offsets, batch.num_patches, batch.dim, batch.nq, flags)
+        plan = fv.fv_plan_create(batch.sizes, batch.offsets, batch.num_patches, batch.dim, batch.nq, flags, tune=tune)
         try:
             a = torch.from_numpy(batch.data).to("cuda")
             c = a.clone()

@@ -8,6 +8,8 @@ gfx950 only, with packed-FP32 instruction selection disabled.
 from __future__ import annotations
 
 import concurrent.futures
+import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -23,7 +25,26 @@ LIBRARY = os.path.join(PKG, "libfvpatch.so")
 SOURCES = ["fv_update.hip", "fv_update2d.hip", "fv_update2d_tile.hip", "fv_update3d.hip", "fv_step.hip", "fv_abi.hip",
            "fv_plan.hip", "fv_serve.hip", "fv_mesh.hip", "fv_flavours.hip",
            "fv_transfer.hip"]
-HEADERS = ["fv_internal.h", "fv_host.h", "fv_physics.h"]
+
+
+def headers() -> list[str]:
+    """Every header of csrc/ (all of them are included by some source)."""
+    return sorted(os.path.basename(h) for h in glob.glob(os.path.join(CSRC, "*.h")))
+
+
+def source_files() -> list[str]:
+    return [os.path.join(CSRC, s) for s in SOURCES + headers()] + [os.path.join(INCLUDE, "fvpatch.h")]
+
+
+def source_hash() -> str:
+    """Hash of the library's sources and headers (names and contents): the build id the library
+    reports through fv_build_id()."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.basename(f).encode() + b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -59,7 +80,7 @@ def _run(cmd: list[str], verbose: bool) -> None:
 def build(verbose: bool = False, extra_flags: list[str] | None = None, output: str = LIBRARY) -> str:
     """Compile every source (in parallel, one object each) and link the shared
     library (always recompiles)."""
-    flags = [*HIPCC_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-I", CSRC]
+    flags = [*HIPCC_FLAGS, *(extra_flags or []), f'-DFV_BUILD_ID="{source_hash()}"', "-I", INCLUDE, "-I", CSRC]
     with tempfile.TemporaryDirectory(prefix="fvpatch_build_") as tmp:
         objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
         jobs = [[hipcc(), *flags, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
@@ -77,8 +98,7 @@ def stale() -> bool:
     if not os.path.exists(LIBRARY):
         return True
     t = os.path.getmtime(LIBRARY)
-    deps = [os.path.join(CSRC, s) for s in SOURCES + HEADERS] + [os.path.join(INCLUDE, "fvpatch.h")]
-    return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
+    return any(os.path.getmtime(d) > t for d in source_files() if os.path.exists(d))
 
 
 if __name__ == "__main__":

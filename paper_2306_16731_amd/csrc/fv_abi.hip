@@ -18,19 +18,18 @@
 
 namespace fv {
 
-static thread_local std::string g_last_error;
+// Thread-local, fixed-size: recording an error allocates nothing.
+static thread_local char g_last_error[512];
 
 fv_status fail(fv_status s, const char *fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return s;
 }
 
-void clear_error() { g_last_error.clear(); }
+void clear_error() { g_last_error[0] = '\0'; }
 
 int max_p(int dim) { return dim == 2 ? FV_MAX_P_2D : FV_MAX_P_3D; }
 
@@ -61,7 +60,7 @@ static bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b
 }
 
 fv_status check_layout(const int32_t *sizes, const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t nq,
-                       BatchShape *shape) {
+                       BatchShape *shape, std::pair<int64_t, int64_t> *sort_buf, int64_t sort_cap) {
     if (!sizes) return fail(FV_ERR_INVALID_ARG, "sizes must be non-null");
     if (num_patches <= 0) return fail(FV_ERR_INVALID_ARG, "num_patches must be > 0");
     const int pmax = max_p(dim);
@@ -98,9 +97,17 @@ fv_status check_layout(const int32_t *sizes, const int64_t *offsets, int32_t num
             prev_end = std::max(prev_end, e);
         }
         if (!sorted) {
-            std::vector<std::pair<int64_t, int64_t>> r(num_patches);
+            std::vector<std::pair<int64_t, int64_t>> own;
+            std::pair<int64_t, int64_t> *r = sort_buf;
+            if (!r) {
+                own.resize(num_patches);
+                r = own.data();
+            } else if (num_patches > sort_cap) {
+                return fail(FV_ERR_INVALID_ARG, "%d patches at unsorted offsets exceed the %lld this call can check",
+                            num_patches, (long long)sort_cap);
+            }
             for (int32_t t = 0; t < num_patches; ++t) r[t] = {offsets[t], offsets[t] + patch_doubles(sizes[t], dim, nq)};
-            std::sort(r.begin(), r.end());
+            std::sort(r, r + num_patches);
             for (int32_t t = 1; t < num_patches; ++t)
                 if (r[t].first < r[t - 1].second) return fail(FV_ERR_OVERLAP, "patch ranges overlap");
         }
@@ -128,11 +135,11 @@ fv_status check_buffers(const double *in, const double *out, const double *lambd
 
 fv_status check_batch(const double *in, const double *out, const int32_t *sizes, const int64_t *offsets,
                       int32_t num_patches, int32_t dim, int32_t nq, const double *lambda_out,
-                      BatchShape *shape) {
+                      BatchShape *shape, std::pair<int64_t, int64_t> *sort_buf, int64_t sort_cap) {
     if (!in || !out || !sizes) return fail(FV_ERR_INVALID_ARG, "patches_in, patches_out and sizes must be non-null");
     if (!aligned8(in) || !aligned8(out) || (lambda_out && !aligned8(lambda_out)))
         return fail(FV_ERR_INVALID_ARG, "device pointers must be 8-byte aligned");
-    fv_status st = check_layout(sizes, offsets, num_patches, dim, nq, shape);
+    fv_status st = check_layout(sizes, offsets, num_patches, dim, nq, shape, sort_buf, sort_cap);
     if (st != FV_OK) return st;
     return check_buffers(in, out, lambda_out, num_patches, shape->lo, shape->hi);
 }
@@ -258,12 +265,143 @@ fv_tuning tuning_for(int dim, int nq, int p) {
     return t->kernel < 0 ? default_tuning(dim, nq, p) : *t;
 }
 
-void apply_tuning(UpdateLaunch &L) {
-    const fv_tuning t = tuning_for(L.dim, L.nq, L.p);
+void apply_tuning(UpdateLaunch &L) { apply_tuning(L, tuning_for(L.dim, L.nq, L.p)); }
+
+void apply_tuning(UpdateLaunch &L, const fv_tuning &t) {
     L.kernel = t.kernel;
     L.block = t.block;
     L.prefetch = t.prefetch;
     L.rows = t.rows;
+}
+
+// Launch parameters shared by every launch of one plain call (everything but the patch
+// selection): the PDE, the step, the flags, lambda.
+UpdateLaunch launch_template(const double *in, double *out, int32_t dim, int32_t nq, double dt, double h,
+                             double gamma, uint32_t flags, double *lambda_out, const PdeArgs *pde) {
+    UpdateLaunch L;
+    if (pde) {
+        L.pde = pde->pde;
+        for (int k = 0; k < 4; ++k) L.pde_prm[k] = pde->prm[k];
+    }
+    L.dt = dt;
+    L.in = in;
+    L.out = out;
+    L.dim = dim;
+    L.nq = nq;
+    L.r = dt / h;
+    L.gamma = gamma;
+    L.flags = flags;
+    L.lambda_out = lambda_out;
+    return L;
+}
+
+// Euler classes take their tuned kernel; the other PDEs their built wave form, else the
+// generic block kernel (launch_pde picks).
+static void tune_launch(UpdateLaunch &X) {
+    if (X.pde == kPdeEuler) {
+        apply_tuning(X);
+    } else {
+        X.kernel = FV_KERNEL_BLOCK;
+        X.block = 0;
+    }
+}
+
+bool regular_batch(const int64_t *offsets, int32_t T, int32_t dim, int32_t nq, const BatchShape &shape,
+                   int64_t *base, int64_t *stride) {
+    // Equal sizes at evenly spaced offsets (offsets[t] = offsets[0] + t s, s at least one patch):
+    // the launch of a contiguous batch from offsets[0] with stride s, no descriptors to upload.
+    *base = 0;
+    *stride = shape.uniform_p > 0 ? patch_doubles(shape.uniform_p, dim, nq) : 0;
+    bool regular = shape.contiguous;
+    if (!shape.contiguous && shape.uniform_p > 0) {
+        *base = offsets[0];
+        if (T > 1) *stride = offsets[1] - offsets[0];
+        regular = *stride >= patch_doubles(shape.uniform_p, dim, nq);
+        for (int32_t t = 2; t < T && regular; ++t) regular = offsets[t] - offsets[t - 1] == *stride;
+    }
+    return regular;
+}
+
+fv_status regular_launch(const UpdateLaunch &tmpl, const int64_t *offsets, int32_t T, const BatchShape &shape,
+                         hipStream_t stream, bool *taken) {
+    *taken = false;
+    const int32_t dim = tmpl.dim, nq = tmpl.nq;
+    int64_t base = 0, stride = 0;
+    if (!regular_batch(offsets, T, dim, nq, shape, &base, &stride)) return FV_OK;
+    *taken = true;
+    UpdateLaunch L = tmpl;
+    L.in = tmpl.in + base;
+    L.out = tmpl.out + base;
+    L.num_items = T;
+    L.p = shape.uniform_p;
+    L.stride = stride;
+    // 16-byte accesses need every patch to start on a 16-byte boundary and span an even number
+    // of doubles (the row loaders of the runtime-size kernels assume it), as on the descriptor path
+    L.vec2 = (L.stride % 2 == 0) && patch_doubles(shape.uniform_p, dim, nq) % 2 == 0 && aligned16(L.in) &&
+             aligned16(L.out);
+    tune_launch(L);
+    hipError_t e = launch_update(L, stream);
+    if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
+    return FV_OK;
+}
+
+size_t descriptor_bytes(int32_t T, bool with_out_offsets) {
+    return (size_t)T * (sizeof(int64_t) + sizeof(int32_t)) + (with_out_offsets ? (size_t)T * sizeof(int64_t) : 0);
+}
+
+void build_descriptors(const int32_t *sizes, const int64_t *offsets, const int64_t *out_offsets, int32_t T,
+                       int32_t dim, int32_t nq, void *host, DescriptorGroups *g) {
+    const int pmax = max_p(dim);
+    for (int p = 0; p <= pmax + 1; ++p) {
+        g->count[p] = 0;
+        g->odd[p] = 0;
+    }
+    for (int32_t t = 0; t < T; ++t) g->count[sizes[t]]++;
+    g->start[0] = 0;
+    for (int p = 1; p <= pmax + 1; ++p) g->start[p] = g->start[p - 1] + g->count[p - 1];
+    g->num = T;
+    g->with_out = out_offsets != nullptr;
+    int32_t fill[FV_MAX_P_2D + 2];
+    for (int p = 0; p <= pmax + 1; ++p) fill[p] = g->start[p];
+    const int64_t nout = out_offsets ? T : 0;
+    int64_t *hoff = static_cast<int64_t *>(host);
+    int64_t *hout = hoff + T;
+    int32_t *hid = reinterpret_cast<int32_t *>(hout + nout);
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t k = fill[sizes[t]]++;
+        const int64_t o = offsets ? offsets[t] : (int64_t)t * patch_doubles(sizes[t], dim, nq);
+        hoff[k] = o;
+        hid[k] = t;
+        g->odd[sizes[t]] |= (char)(o & 1);
+        if (out_offsets) {
+            hout[k] = out_offsets[t];
+            g->odd[sizes[t]] |= (char)(out_offsets[t] & 1);
+        }
+    }
+}
+
+fv_status launch_descriptor_groups(const UpdateLaunch &tmpl, const void *dev, const DescriptorGroups &g,
+                                   hipStream_t stream) {
+    const int32_t T = g.num;
+    const int64_t nout = g.with_out ? T : 0;
+    const int64_t *doff = static_cast<const int64_t *>(dev);
+    const int64_t *dout = g.with_out ? doff + T : nullptr;
+    const int32_t *did = reinterpret_cast<const int32_t *>(doff + T + nout);
+    const bool bufs16 = aligned16(tmpl.in) && aligned16(tmpl.out);
+    for (int p = max_p(tmpl.dim); p >= 1; --p) {  // largest patches first
+        if (!g.count[p]) continue;
+        UpdateLaunch L = tmpl;
+        L.num_items = g.count[p];
+        L.p = p;
+        L.offsets = doff + g.start[p];
+        L.out_offsets = dout ? dout + g.start[p] : nullptr;
+        L.ids = did + g.start[p];
+        L.vec2 = bufs16 && !g.odd[p] && patch_doubles(p, tmpl.dim, tmpl.nq) % 2 == 0;
+        tune_launch(L);
+        hipError_t e = launch_update(L, stream);
+        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed (p=%d): %s", p, hipGetErrorString(e));
+    }
+    return FV_OK;
 }
 
 // Plain per-batch launch; arguments already validated.  out_offsets (host,
@@ -277,103 +415,26 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
     DeviceContext *ctx = nullptr;
     fv_status st = current_context(&ctx);
     if (st != FV_OK) return st;
-    UpdateLaunch L;
-    if (pde) {
-        L.pde = pde->pde;
-        for (int k = 0; k < 4; ++k) L.pde_prm[k] = pde->prm[k];
-    }
-    L.dt = dt;
-    // Euler classes take their tuned kernel; the other PDEs their built wave form, else the
-    // generic block kernel (launch_pde picks)
-    auto tune = [](UpdateLaunch &X) {
-        if (X.pde == kPdeEuler) {
-            apply_tuning(X);
-        } else {
-            X.kernel = FV_KERNEL_BLOCK;
-            X.block = 0;
-        }
-    };
-    L.in = in;
-    L.out = out;
-    L.dim = dim;
-    L.nq = nq;
-    L.r = dt / h;
-    L.gamma = gamma;
-    L.flags = flags;
-    L.lambda_out = lambda_out;
-    // Equal sizes at evenly spaced offsets (offsets[t] = offsets[0] + t s, s at least one patch):
-    // the launch of a contiguous batch from offsets[0] with stride s, no descriptors to upload.
-    int64_t base = 0, stride = shape.uniform_p > 0 ? patch_doubles(shape.uniform_p, dim, nq) : 0;
-    bool regular = shape.contiguous;
-    if (!shape.contiguous && !out_offsets && shape.uniform_p > 0) {
-        base = offsets[0];
-        if (T > 1) stride = offsets[1] - offsets[0];
-        regular = stride >= patch_doubles(shape.uniform_p, dim, nq);
-        for (int32_t t = 2; t < T && regular; ++t) regular = offsets[t] - offsets[t - 1] == stride;
-    }
-    if (regular && !out_offsets) {
-        L.in = in + base;
-        L.out = out + base;
-        L.num_items = T;
-        L.p = shape.uniform_p;
-        L.stride = stride;
-        L.vec2 = (L.stride % 2 == 0) && aligned16(L.in) && aligned16(L.out);
-        tune(L);
-        hipError_t e = launch_update(L, stream);
-        if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
-        return FV_OK;
+    const UpdateLaunch L = launch_template(in, out, dim, nq, dt, h, gamma, flags, lambda_out, pde);
+    if (!out_offsets) {
+        bool taken = false;
+        st = regular_launch(L, offsets, T, shape, stream, &taken);
+        if (st != FV_OK || taken) return st;
     }
     // Group the patches by size (counting sort), upload (offset, id) lists.
-    const int pmax = max_p(dim);
-    std::vector<int32_t> count(pmax + 2, 0);
-    for (int32_t t = 0; t < T; ++t) count[sizes[t]]++;
-    std::vector<int32_t> start(pmax + 2, 0);
-    for (int p = 1; p <= pmax + 1; ++p) start[p] = start[p - 1] + count[p - 1];
-    const int64_t nout = out_offsets ? T : 0;
-    const size_t bytes = (size_t)T * (sizeof(int64_t) + sizeof(int32_t)) + (size_t)nout * sizeof(int64_t);
+    const size_t bytes = descriptor_bytes(T, out_offsets != nullptr);
     DescSlot *slot = nullptr;
     st = acquire_slot(ctx, bytes, &slot);
     if (st != FV_OK) return st;
-    int64_t *hoff = static_cast<int64_t *>(slot->host);
-    int64_t *hout = hoff + T;
-    int32_t *hid = reinterpret_cast<int32_t *>(hout + nout);
-    std::vector<int32_t> fill(start);
-    std::vector<char> odd(pmax + 2, 0);  // some patch of this size starts at an odd double
-    for (int32_t t = 0; t < T; ++t) {
-        const int32_t k = fill[sizes[t]]++;
-        const int64_t o = offsets ? offsets[t] : (int64_t)t * patch_doubles(sizes[t], dim, nq);
-        hoff[k] = o;
-        hid[k] = t;
-        odd[sizes[t]] |= (char)(o & 1);
-        if (out_offsets) {
-            hout[k] = out_offsets[t];
-            odd[sizes[t]] |= (char)(out_offsets[t] & 1);
-        }
-    }
-    const bool bufs16 = aligned16(in) && aligned16(out);
+    DescriptorGroups g;
+    build_descriptors(sizes, offsets, out_offsets, T, dim, nq, slot->host, &g);
     if (hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
         (void)release_slot(slot, stream);
         return fail(FV_ERR_LAUNCH, "descriptor upload failed");
     }
-    const int64_t *doff = static_cast<const int64_t *>(slot->dev);
-    const int64_t *dout = out_offsets ? doff + T : nullptr;
-    const int32_t *did = reinterpret_cast<const int32_t *>(doff + T + nout);
-    for (int p = pmax; p >= 1; --p) {  // largest patches first
-        if (!count[p]) continue;
-        L.num_items = count[p];
-        L.p = p;
-        L.offsets = doff + start[p];
-        L.out_offsets = dout ? dout + start[p] : nullptr;
-        L.ids = did + start[p];
-        L.vec2 = bufs16 && !odd[p] && patch_doubles(p, dim, nq) % 2 == 0;
-        tune(L);
-        hipError_t e = launch_update(L, stream);
-        if (e != hipSuccess) {
-            (void)release_slot(slot, stream);
-            return fail(FV_ERR_LAUNCH, "kernel launch failed (p=%d): %s", p, hipGetErrorString(e));
-        }
-    }
-    return release_slot(slot, stream);
+    st = launch_descriptor_groups(L, slot->dev, g, stream);
+    const fv_status rs = release_slot(slot, stream);
+    return st != FV_OK ? st : rs;
 }
 
 // Unknowns and parameters of a built-in PDE in dim dimensions.
@@ -390,6 +451,84 @@ fv_status pde_shape(int32_t pde, int32_t dim, int32_t *nq, int32_t *nprm) {
         default: return fail(FV_ERR_INVALID_ARG, "unknown PDE %d", pde);
     }
 }
+
+fv_status check_class(int32_t dim, int32_t nq, int32_t p) {
+    if (dim != 2 && dim != 3) return fail(FV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", dim);
+    if (!(nq == 5 || (dim == 2 && nq == 4))) return fail(FV_ERR_INVALID_ARG, "unsupported unknowns=%d for %dD", nq, dim);
+    if (p < 1 || p > max_p(dim)) return fail(FV_ERR_INVALID_ARG, "p=%d outside [1, %d]", p, max_p(dim));
+    return FV_OK;
+}
+
+// Validate launch parameters for a class and fill in their defaults (the rules of
+// fv_set_tuning; also used for a plan's own table).
+fv_status resolve_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tuning &in, fv_tuning *out) {
+    fv_status st = check_class(dim, unknowns, p);
+    if (st != FV_OK) return st;
+    const fv_tuning *t = &in;
+    if (t->kernel < FV_KERNEL_AUTO || t->kernel > FV_KERNEL_FIXED) return fail(FV_ERR_INVALID_ARG, "unknown kernel %d", t->kernel);
+    if (t->block < 0 || t->block > 1024 || t->block % 64 != 0) return fail(FV_ERR_INVALID_ARG, "block must be a multiple of 64 in [0, 1024]");
+    if (t->prefetch < 0 || t->prefetch > 4) return fail(FV_ERR_INVALID_ARG, "prefetch must be in [0, 4]");
+    if (t->rows < 0 || t->rows > 16) return fail(FV_ERR_INVALID_ARG, "rows must be in [0, 16]");
+    fv_tuning v = *t;
+    const fv_tuning d = default_tuning(dim, unknowns, p);
+    if (v.kernel == FV_KERNEL_AUTO) {
+        v.kernel = d.kernel;
+        // explicit prefetch / rows other than the fixed-size build's: the runtime-size wave kernel
+        if (v.kernel == FV_KERNEL_FIXED && ((v.prefetch != 0 && v.prefetch != d.prefetch) ||
+                                            (v.rows != 0 && v.rows != d.rows)))
+            v.kernel = FV_KERNEL_WAVE;
+    }
+    if (v.kernel == FV_KERNEL_WAVE && !(dim == 2 && wave2d_fits(p)))
+        return fail(FV_ERR_UNSUPPORTED, "the wave kernel needs 2D and p + 2 <= 64");
+    if (v.kernel == FV_KERNEL_TILE && !(dim == 2 && tile2d_fits(p)))
+        return fail(FV_ERR_UNSUPPORTED, "the tile kernel needs 2D and p*p <= 1024");
+    if (v.kernel == FV_KERNEL_FIXED) {
+        if (!((dim == 2 && wave2d_fixed(p, unknowns)) || (dim == 3 && wave3d_fixed(p, unknowns))))
+            return fail(FV_ERR_UNSUPPORTED, "no fixed-size kernel for dim=%d unknowns=%d p=%d", dim, unknowns, p);
+        int pf = 0, rows = 0;
+        fixed_shape(dim, p, &pf, &rows);
+        const int fb = wave2d_fixed_block();
+        if (v.block != 0 && v.block != fb) return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel takes %d threads", fb);
+        if ((v.prefetch != 0 && v.prefetch != pf) || (v.rows != 0 && v.rows != rows))
+            return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel for p=%d is built with prefetch %d and rows %d", p,
+                        pf, rows);
+        *out = fv_tuning{FV_KERNEL_FIXED, fb, pf, rows};
+        return FV_OK;
+    }
+    if (v.block == 0) v.block = v.kernel == d.kernel ? d.block : default_block_for(v.kernel, p, dim);
+    if (v.kernel == FV_KERNEL_WAVE && v.block > 256) return fail(FV_ERR_INVALID_ARG, "the wave kernel takes at most 256 threads");
+    if (v.kernel == FV_KERNEL_TILE) {
+        if (v.block < p * p) return fail(FV_ERR_INVALID_ARG, "the tile kernel needs at least p*p = %d threads", p * p);
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            tile2d_patches_per_block(p, unknowns, v.block, (size_t)lds_max) < 1)
+            return fail(FV_ERR_INVALID_ARG, "a tile of p=%d needs more LDS than the device offers", p);
+        (void)hipGetLastError();
+    }
+    if (v.kernel == FV_KERNEL_BLOCK) {
+        if (v.block < plane_lanes(p, dim)) return fail(FV_ERR_INVALID_ARG, "block %d smaller than the %d lanes of a patch", v.block, plane_lanes(p, dim));
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            update_lds_bytes(dim, unknowns, v.block) > (size_t)lds_max)
+            return fail(FV_ERR_INVALID_ARG, "block %d needs more LDS than the device offers", v.block);
+        (void)hipGetLastError();
+    }
+    if (v.prefetch == 0) v.prefetch = v.kernel == FV_KERNEL_WAVE ? 4 : 1;
+    if (v.rows == 0) v.rows = v.kernel == FV_KERNEL_WAVE ? 6 : 1;
+    if (v.kernel == FV_KERNEL_WAVE) {
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            wave2d_lds_bytes(p, unknowns, v.block, v.rows) > (size_t)lds_max)
+            return fail(FV_ERR_INVALID_ARG, "block %d with %d staged rows needs more LDS than the device offers", v.block, v.rows);
+        (void)hipGetLastError();
+    }
+    *out = v;
+    return FV_OK;
+}
+
 
 }  // namespace fv
 
@@ -466,84 +605,21 @@ fv_status fv_pde_batch_update(int32_t pde, const double *params, int32_t num_par
                         static_cast<hipStream_t>(stream), shape, nullptr, &args);
 }
 
-static fv_status check_class(int32_t dim, int32_t nq, int32_t p) {
-    if (dim != 2 && dim != 3) return fail(FV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", dim);
-    if (!(nq == 5 || (dim == 2 && nq == 4))) return fail(FV_ERR_INVALID_ARG, "unsupported unknowns=%d for %dD", nq, dim);
-    if (p < 1 || p > max_p(dim)) return fail(FV_ERR_INVALID_ARG, "p=%d outside [1, %d]", p, max_p(dim));
-    return FV_OK;
-}
 
 fv_status fv_set_tuning(int32_t dim, int32_t unknowns, int32_t p, const fv_tuning *t) {
     clear_error();
-    fv_status st = check_class(dim, unknowns, p);
+    if (!t) {
+        fv_status st = check_class(dim, unknowns, p);
+        if (st != FV_OK) return st;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        *tune_slot(dim, unknowns, p) = fv_tuning{-1, 0, 0, 0};
+        return FV_OK;
+    }
+    fv_tuning v;
+    fv_status st = resolve_tuning(dim, unknowns, p, *t, &v);
     if (st != FV_OK) return st;
     std::lock_guard<std::mutex> g(g_tune_mu);
-    fv_tuning *slot = tune_slot(dim, unknowns, p);
-    if (!t) {
-        *slot = fv_tuning{-1, 0, 0, 0};
-        return FV_OK;
-    }
-    if (t->kernel < FV_KERNEL_AUTO || t->kernel > FV_KERNEL_FIXED) return fail(FV_ERR_INVALID_ARG, "unknown kernel %d", t->kernel);
-    if (t->block < 0 || t->block > 1024 || t->block % 64 != 0) return fail(FV_ERR_INVALID_ARG, "block must be a multiple of 64 in [0, 1024]");
-    if (t->prefetch < 0 || t->prefetch > 4) return fail(FV_ERR_INVALID_ARG, "prefetch must be in [0, 4]");
-    if (t->rows < 0 || t->rows > 16) return fail(FV_ERR_INVALID_ARG, "rows must be in [0, 16]");
-    fv_tuning v = *t;
-    const fv_tuning d = default_tuning(dim, unknowns, p);
-    if (v.kernel == FV_KERNEL_AUTO) {
-        v.kernel = d.kernel;
-        // explicit prefetch / rows other than the fixed-size build's: the runtime-size wave kernel
-        if (v.kernel == FV_KERNEL_FIXED && ((v.prefetch != 0 && v.prefetch != d.prefetch) ||
-                                            (v.rows != 0 && v.rows != d.rows)))
-            v.kernel = FV_KERNEL_WAVE;
-    }
-    if (v.kernel == FV_KERNEL_WAVE && !(dim == 2 && wave2d_fits(p)))
-        return fail(FV_ERR_UNSUPPORTED, "the wave kernel needs 2D and p + 2 <= 64");
-    if (v.kernel == FV_KERNEL_TILE && !(dim == 2 && tile2d_fits(p)))
-        return fail(FV_ERR_UNSUPPORTED, "the tile kernel needs 2D and p*p <= 1024");
-    if (v.kernel == FV_KERNEL_FIXED) {
-        if (!((dim == 2 && wave2d_fixed(p, unknowns)) || (dim == 3 && wave3d_fixed(p, unknowns))))
-            return fail(FV_ERR_UNSUPPORTED, "no fixed-size kernel for dim=%d unknowns=%d p=%d", dim, unknowns, p);
-        int pf = 0, rows = 0;
-        fixed_shape(dim, p, &pf, &rows);
-        const int fb = wave2d_fixed_block();
-        if (v.block != 0 && v.block != fb) return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel takes %d threads", fb);
-        if ((v.prefetch != 0 && v.prefetch != pf) || (v.rows != 0 && v.rows != rows))
-            return fail(FV_ERR_INVALID_ARG, "the fixed-size kernel for p=%d is built with prefetch %d and rows %d", p,
-                        pf, rows);
-        *slot = fv_tuning{FV_KERNEL_FIXED, fb, pf, rows};
-        return FV_OK;
-    }
-    if (v.block == 0) v.block = v.kernel == d.kernel ? d.block : default_block_for(v.kernel, p, dim);
-    if (v.kernel == FV_KERNEL_WAVE && v.block > 256) return fail(FV_ERR_INVALID_ARG, "the wave kernel takes at most 256 threads");
-    if (v.kernel == FV_KERNEL_TILE) {
-        if (v.block < p * p) return fail(FV_ERR_INVALID_ARG, "the tile kernel needs at least p*p = %d threads", p * p);
-        int dev = 0, lds_max = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            tile2d_patches_per_block(p, unknowns, v.block, (size_t)lds_max) < 1)
-            return fail(FV_ERR_INVALID_ARG, "a tile of p=%d needs more LDS than the device offers", p);
-        (void)hipGetLastError();
-    }
-    if (v.kernel == FV_KERNEL_BLOCK) {
-        if (v.block < plane_lanes(p, dim)) return fail(FV_ERR_INVALID_ARG, "block %d smaller than the %d lanes of a patch", v.block, plane_lanes(p, dim));
-        int dev = 0, lds_max = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            update_lds_bytes(dim, unknowns, v.block) > (size_t)lds_max)
-            return fail(FV_ERR_INVALID_ARG, "block %d needs more LDS than the device offers", v.block);
-        (void)hipGetLastError();
-    }
-    if (v.prefetch == 0) v.prefetch = v.kernel == FV_KERNEL_WAVE ? 4 : 1;
-    if (v.rows == 0) v.rows = v.kernel == FV_KERNEL_WAVE ? 6 : 1;
-    if (v.kernel == FV_KERNEL_WAVE) {
-        int dev = 0, lds_max = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            wave2d_lds_bytes(p, unknowns, v.block, v.rows) > (size_t)lds_max)
-            return fail(FV_ERR_INVALID_ARG, "block %d with %d staged rows needs more LDS than the device offers", v.block, v.rows);
-        (void)hipGetLastError();
-    }
-    *slot = v;
+    *tune_slot(dim, unknowns, p) = v;
     return FV_OK;
 }
 
@@ -570,8 +646,13 @@ const char *fv_status_string(fv_status s) {
     return "unknown status";
 }
 
-const char *fv_last_error(void) { return g_last_error.c_str(); }
+const char *fv_last_error(void) { return g_last_error; }
 
 int32_t fv_version(void) { return 100; }
+
+#ifndef FV_BUILD_ID
+#define FV_BUILD_ID "unknown"
+#endif
+const char *fv_build_id(void) { return FV_BUILD_ID; }
 
 }  // extern "C"

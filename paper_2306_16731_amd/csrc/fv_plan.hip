@@ -4,7 +4,7 @@
 //
 // The paper bundles T patch updates into one kernel call (task fusion, Sec.
 // 2.1) and proposes, without being able to run it, to precompile the fixed
-// task graph so the GPU resolves the dependencies (Sec. 6, Sec. 8).  Here the
+// task graph so the GPU resolves the dependencies (Sec. 5, and the outlook of Sec. 6).  Here the
 // plan sorts the patches by size, cuts each size class into wave tasks
 // (floor(64 / (p+2)) patches per task; the fixed-size body for the sizes built
 // in that form, else the runtime-size body with the class's tuned rows), and
@@ -47,6 +47,9 @@ struct fv_plan {
         bool even;  // every patch of the class starts at an even double and spans an even number of them
     };
     std::vector<Group> groups;  // classes launched per class (3D, 2D p > 62; every class with FV_PLAN_PER_CLASS)
+    // launch parameters of each size class, fixed at creation (index p; kernel -1: no such class)
+    std::vector<fv_tuning> tune;
+    double *d_rexec = nullptr;  // dt / h of an execute that takes its dt from device memory
     // captured multi-step run
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -113,7 +116,7 @@ fv_status enqueue_step(const fv_plan *pl, const double *in, double *out, double 
         L.flags = pl->flags;
         L.lambda_out = lambda_out;
         L.vec2 = g.even && aligned16(in) && aligned16(out);
-        apply_tuning(L);
+        apply_tuning(L, pl->tune[g.p]);
         if (L.dim == 2 && L.kernel == FV_KERNEL_WAVE && !wave2d_fits(L.p)) L.kernel = FV_KERNEL_BLOCK;
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "class launch (p=%d) failed: %s", g.p, hipGetErrorString(e));
@@ -135,6 +138,7 @@ void release_graph(fv_plan *pl) {
 
 void release(fv_plan *pl) {
     release_graph(pl);
+    if (pl->d_rexec) (void)hipFree(pl->d_rexec);
     if (pl->d_offsets) (void)hipFree(pl->d_offsets);
     if (pl->d_ids) (void)hipFree(pl->d_ids);
     if (pl->d_tasks) (void)hipFree(pl->d_tasks);
@@ -149,7 +153,8 @@ using namespace fv;
 extern "C" {
 
 fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *offsets, int32_t num_patches,
-                         int32_t dim, int32_t unknowns, uint32_t flags) {
+                         int32_t dim, int32_t unknowns, uint32_t flags, const fv_tune_entry *tune_table,
+                         int32_t tune_entries) {
     clear_error();
     if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
     *plan = nullptr;
@@ -160,9 +165,22 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     if ((flags & FV_PLAN_NO_PERSIST) && (flags & FV_PLAN_PER_CLASS))
         return fail(FV_ERR_INVALID_ARG, "FV_PLAN_NO_PERSIST and FV_PLAN_PER_CLASS exclude each other");
     if (num_patches < 1) return fail(FV_ERR_INVALID_ARG, "a plan needs at least one patch");
+    if (tune_entries < 0 || (tune_entries > 0 && !tune_table))
+        return fail(FV_ERR_INVALID_ARG, "tune_table must hold tune_entries (>= 0) entries");
     BatchShape shape;
     st = check_layout(sizes, offsets, num_patches, dim, unknowns, &shape);
     if (st != FV_OK) return st;
+    // the plan's own launch parameters: its table's entries for its (dim, unknowns), validated
+    // like fv_set_tuning's; other classes take the installed (process-wide) or default ones
+    const int pmax_t = max_p(dim);
+    std::vector<fv_tuning> own(pmax_t + 1, fv_tuning{-1, 0, 0, 0});
+    for (int32_t k = 0; k < tune_entries; ++k) {
+        const fv_tune_entry &e = tune_table[k];
+        if (e.dim != dim || e.unknowns != unknowns) continue;
+        if (e.p < 1 || e.p > pmax_t) return fail(FV_ERR_INVALID_ARG, "tune_table[%d]: p=%d outside [1, %d]", k, e.p, pmax_t);
+        if (own[e.p].kernel >= 0) return fail(FV_ERR_INVALID_ARG, "tune_table: two entries for p=%d", e.p);
+        if ((st = resolve_tuning(dim, unknowns, e.p, e.tuning, &own[e.p])) != FV_OK) return st;
+    }
     DeviceContext *ctx = nullptr;
     st = current_context(&ctx);
     if (st != FV_OK) return st;
@@ -177,6 +195,7 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     pl->num_patches = num_patches;
     pl->lo = shape.lo;
     pl->hi = shape.hi;
+    pl->tune.assign(pmax_t + 1, fv_tuning{-1, 0, 0, 0});
 
     // counting sort by size, largest first
     const int pmax = max_p(dim);
@@ -202,8 +221,9 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     }
     for (int p = pmax; p >= 1; --p) {
         if (!count[p]) continue;
+        pl->tune[p] = own[p].kernel >= 0 ? own[p] : tuning_for(dim, unknowns, p);
         if (dim == 2 && wave2d_fits(p) && !per_class) {
-            const fv_tuning tu = tuning_for(dim, unknowns, p);
+            const fv_tuning tu = pl->tune[p];
             // rows == 0: the fixed-size form of the kernel.  A class built in that form runs it
             // in the fused launch whatever its tuning: a tuned runtime-size body keeps its rows
             // there but not its block size or prefetch (one of each per fused launch), and
@@ -238,7 +258,8 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     pl->num_tasks = (int32_t)tasks.size();
 
     // device copies of the work list
-    bool ok = hipMalloc(&pl->d_offsets, sizeof(int64_t) * num_patches) == hipSuccess &&
+    bool ok = hipMalloc(&pl->d_rexec, sizeof(double)) == hipSuccess &&
+              hipMalloc(&pl->d_offsets, sizeof(int64_t) * num_patches) == hipSuccess &&
               hipMalloc(&pl->d_ids, sizeof(int32_t) * num_patches) == hipSuccess &&
               (tasks.empty() || hipMalloc(&pl->d_tasks, sizeof(WaveTask) * tasks.size()) == hipSuccess);
     if (!ok) {
@@ -257,16 +278,39 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     return FV_OK;
 }
 
-fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patches_out, double dt, double h,
-                          double gamma, double *lambda_out, void *stream) {
+fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patches_out, double dt,
+                          const double *dt_dev, double h, double gamma, double *lambda_out, void *stream) {
     clear_error();
     if (!plan) return fail(FV_ERR_INVALID_ARG, "plan must be non-null");
-    fv_status st = check_scalars(plan->dim, plan->nq, dt, h, gamma, 0);
+    fv_status st = check_scalars(plan->dim, plan->nq, dt_dev ? 1.0 : dt, h, gamma, 0);
     if (st != FV_OK) return st;
     if ((st = check_device(plan)) != FV_OK) return st;
     if ((st = plan_buffers(plan, patches_in, patches_out, lambda_out)) != FV_OK) return st;
-    return enqueue_step(plan, patches_in, patches_out, dt / h, nullptr, gamma, lambda_out,
-                        static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!dt_dev) return enqueue_step(plan, patches_in, patches_out, dt / h, nullptr, gamma, lambda_out, s);
+    if (!aligned8(dt_dev)) return fail(FV_ERR_INVALID_ARG, "dt_dev must be 8-byte aligned");
+    {
+        const uintptr_t d0 = reinterpret_cast<uintptr_t>(dt_dev), d1 = d0 + sizeof(double);
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(patches_out + plan->lo),
+                        a1 = reinterpret_cast<uintptr_t>(patches_out + plan->hi);
+        const uintptr_t l0 = reinterpret_cast<uintptr_t>(lambda_out),
+                        l1 = reinterpret_cast<uintptr_t>(lambda_out + (lambda_out ? plan->num_patches : 0));
+        if (overlap(d0, d1, a0, a1) || overlap(d0, d1, l0, l1))
+            return fail(FV_ERR_OVERLAP, "dt_dev overlaps patches_out or lambda_out");
+    }
+    // r = dt / h on the device (correctly rounded, as the host's), read by the step's launches
+    if (launch_ratio(dt_dev, h, plan->d_rexec, s) != hipSuccess)
+        return fail(FV_ERR_LAUNCH, "launch of the step-size ratio failed");
+    return enqueue_step(plan, patches_in, patches_out, 0.0, plan->d_rexec, gamma, lambda_out, s);
+}
+
+fv_status fv_plan_get_tuning(const fv_plan *plan, int32_t p, fv_tuning *tuning) {
+    clear_error();
+    if (!plan || !tuning) return fail(FV_ERR_INVALID_ARG, "plan and tuning must be non-null");
+    if (p < 1 || p >= (int32_t)plan->tune.size() || plan->tune[p].kernel < 0)
+        return fail(FV_ERR_INVALID_ARG, "the plan has no patches of size %d", p);
+    *tuning = plan->tune[p];
+    return FV_OK;
 }
 
 fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, double *buf_b, double h, double gamma,

@@ -17,6 +17,17 @@
 // task, tasks in memory order) in pinned staging memory and runs the whole
 // batch in one fused launch; FV_SERVE_PLAIN runs each batch through the plain per-batch
 // path (validation, grouping by size, one launch per size class).
+//
+// Meshes of different dimensions (a 2D mesh of mixed patch sizes next to a 3D
+// one) share one server, one stream and one budget.  Failures: a batch whose
+// completion event reports an error (anything but "not ready") is re-run from
+// its input slot, which no update overwrites, into its output slot again, up
+// to max_retries times, unless a later batch in flight has already used its
+// output; then, or when the retries are spent, poll / drain / run_trace
+// return FV_ERR_LAUNCH with the detail.  A batch still running deadline_ms
+// after its launch also makes them return FV_ERR_LAUNCH instead of waiting on.
+// fv_server_inject forces either outcome from the host for tests: the batch
+// runs normally and only its completion check is overridden.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +35,8 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <thread>
 #include <vector>
 
 #include "fvpatch.h"
@@ -39,6 +52,8 @@ int64_t now_ns() {
 }
 
 struct Mesh {
+    int32_t dim = 2, nq = 5;
+    double h = 1.0;
     std::vector<int32_t> sizes;
     std::vector<int64_t> off;   // offset of each patch inside one slot (doubles)
     std::vector<uint8_t> cur;   // slot holding each patch's current state
@@ -49,8 +64,15 @@ struct Mesh {
 struct Request {
     int64_t ticket = 0;
     int32_t mesh = 0, first = 0, count = 0;
+    int32_t retries = 0;  // re-runs after failed completions so far
     double dt = 0.0;
     int64_t arrival_ns = 0;
+};
+
+// A test hook's override of a batch's completion check.
+struct Injection {
+    int32_t kind = 0;   // FV_INJECT_FAIL or FV_INJECT_HANG
+    int32_t times = 0;  // FV_INJECT_FAIL: completion checks still to report a failure
 };
 
 // Pinned + device staging of one in-flight batch (recycled, never freed while the server lives).
@@ -69,6 +91,7 @@ struct Inflight {
     int staging = -1;
     int64_t bytes = 0;
     int64_t cells = 0;
+    int64_t launch_ns = 0;
     hipEvent_t done = nullptr;  // event recorded after the batch's launches
 };
 
@@ -86,9 +109,13 @@ struct fv_server {
     std::vector<Staging> staging;
     std::vector<hipEvent_t> spare_events;
     std::vector<double> latency_ms;
+    std::vector<fv_batch_record> log;  // one record per completed batch
+    std::map<int64_t, Injection> inject;
     int64_t next_ticket = 1;
     int64_t submitted = 0, completed = 0, cells_updated = 0, peak_queue = 0, peak_inflight = 0;
+    int64_t failed = 0, retried = 0;
     int64_t first_arrival_ns = -1, last_completion_ns = -1;
+    int64_t t0_ns = 0;  // creation time: origin of the batch log's times
 };
 
 namespace fv {
@@ -124,7 +151,7 @@ fv_status ensure_staging(fv_server *s, Staging &st, int32_t count) {
 // Launch one batch (fused mode): task list of the wave kernel for 2D p <= 62,
 // per-class launches otherwise.  Descriptors go through the staging buffer.
 fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
-    const int dim = s->cfg.dim, nq = s->cfg.unknowns;
+    const int dim = m.dim, nq = m.nq;
     const int pmax = max_p(dim);
     const int32_t n = r.count;
     int64_t *hin = static_cast<int64_t *>(st.host);
@@ -188,7 +215,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
     const int64_t *dout = din + n;
     const int32_t *did = reinterpret_cast<const int32_t *>(dout + n);
     const WaveTask *dtask = reinterpret_cast<const WaveTask *>(did + n + (n & 1));
-    const double r_host = r.dt / s->cfg.h;
+    const double r_host = r.dt / m.h;
     if (ntask > 0) {
         TaskLaunch T;
         T.in = m.buf;
@@ -244,10 +271,10 @@ fv_status launch_plain(fv_server *s, Mesh &m, const Request &r, Staging &st) {
         out_off[k] = (m.cur[t] ? 0 : m.slot_doubles) + m.off[t];
     }
     BatchShape shape;
-    fv_status stt = check_layout(m.sizes.data() + r.first, in_off.data(), n, s->cfg.dim, s->cfg.unknowns, &shape);
+    fv_status stt = check_layout(m.sizes.data() + r.first, in_off.data(), n, m.dim, m.nq, &shape);
     if (stt != FV_OK) return stt;
-    return plain_update(m.buf, m.buf, m.sizes.data() + r.first, in_off.data(), n, s->cfg.dim, s->cfg.unknowns, r.dt,
-                        s->cfg.h, s->cfg.gamma, s->cfg.flags, st.lambda, s->stream, shape, out_off.data());
+    return plain_update(m.buf, m.buf, m.sizes.data() + r.first, in_off.data(), n, m.dim, m.nq, r.dt, m.h,
+                        s->cfg.gamma, s->cfg.flags, st.lambda, s->stream, shape, out_off.data());
 }
 
 hipEvent_t take_event(fv_server *s) {
@@ -261,25 +288,116 @@ hipEvent_t take_event(fv_server *s) {
     return e;
 }
 
-// Retire completed batches (in order); record their latency.
-void retire(fv_server *s, bool wait) {
+enum class Check { Done, Pending, Failed };
+
+// The completion check of an in-flight batch: its event's status, overridden by
+// a test injection (a forced failure is reported only once the batch has run).
+Check check_done(fv_server *s, const Inflight &f, hipError_t *err) {
+    hipError_t e = hipEventQuery(f.done);
+    auto it = s->inject.find(f.req.ticket);
+    if (it != s->inject.end()) {
+        if (it->second.kind == FV_INJECT_HANG) return Check::Pending;
+        if (it->second.kind == FV_INJECT_FAIL && it->second.times > 0 && e == hipSuccess) {
+            if (--it->second.times == 0) s->inject.erase(it);
+            e = hipErrorLaunchFailure;
+        }
+    }
+    *err = e;
+    if (e == hipSuccess) return Check::Done;
+    if (e == hipErrorNotReady) return Check::Pending;
+    return Check::Failed;
+}
+
+void restore_parity(fv_server *s, const Request &r) {
+    Mesh &m = s->meshes[r.mesh];
+    for (int32_t k = 0; k < r.count; ++k) m.cur[r.first + k] ^= 1u;
+}
+
+void release_inflight(fv_server *s, Inflight &f) {
+    s->inflight_bytes -= f.bytes;
+    s->staging[f.staging].busy = false;
+    s->spare_events.push_back(f.done);
+}
+
+// The oldest in-flight batch reported an error.  Its input slot still holds the
+// patches' state from before it unless a later batch in flight on the same
+// patches has read its output and written that slot: then the batch is lost.
+// Otherwise its patches are set back to that state and it is queued first again
+// (a re-run writes its output slot anew), or, with its retries spent, dropped.
+fv_status handle_failure(fv_server *s, hipError_t e) {
+    Inflight f = s->inflight.front();
+    const Request &r = f.req;
+    for (size_t k = 1; k < s->inflight.size(); ++k) {
+        const Request &g = s->inflight[k].req;
+        if (g.mesh == r.mesh && g.first < r.first + r.count && r.first < g.first + g.count) {
+            release_inflight(s, f);
+            s->inflight.pop_front();
+            s->failed++;
+            return fail(FV_ERR_LAUNCH,
+                        "batch %lld (mesh %d, patches [%d, %d)) failed (%s) after batch %lld had used its output: "
+                        "the state of those patches is lost",
+                        (long long)r.ticket, r.mesh, r.first, r.first + r.count, hipGetErrorString(e),
+                        (long long)g.ticket);
+        }
+    }
+    restore_parity(s, r);
+    release_inflight(s, f);
+    s->inflight.pop_front();
+    if (r.retries >= s->cfg.max_retries) {
+        s->failed++;
+        return fail(FV_ERR_LAUNCH,
+                    "batch %lld (mesh %d, patches [%d, %d)) failed (%s) after %d re-runs; its patches keep their "
+                    "state from before it",
+                    (long long)r.ticket, r.mesh, r.first, r.first + r.count, hipGetErrorString(e), r.retries);
+    }
+    Request again = r;
+    again.retries++;
+    s->retried++;
+    s->queue.push_front(again);
+    return FV_OK;
+}
+
+// Retire finished batches in order, recording their latency.  wait: keep
+// checking the oldest batch until it finishes (or its deadline passes).
+fv_status retire(fv_server *s, bool wait) {
     while (!s->inflight.empty()) {
         Inflight &f = s->inflight.front();
-        if (wait) {
-            if (hipEventSynchronize(f.done) != hipSuccess) break;
-        } else if (hipEventQuery(f.done) != hipSuccess) {
-            break;
+        hipError_t e = hipSuccess;
+        const Check c = check_done(s, f, &e);
+        if (c == Check::Pending) {
+            const int64_t t = now_ns();
+            if (s->cfg.deadline_ms > 0.0 && (double)(t - f.launch_ns) * 1e-6 > s->cfg.deadline_ms)
+                return fail(FV_ERR_LAUNCH, "batch %lld still running %.3f ms after its launch (deadline %.3f ms)",
+                            (long long)f.req.ticket, (double)(t - f.launch_ns) * 1e-6, s->cfg.deadline_ms);
+            if (!wait) break;
+            std::this_thread::yield();
+            continue;
+        }
+        if (c == Check::Failed) {
+            const fv_status st = handle_failure(s, e);
+            if (st != FV_OK) return st;
+            continue;
         }
         const int64_t t = now_ns();
         s->latency_ms.push_back((double)(t - f.req.arrival_ns) * 1e-6);
+        fv_batch_record rec;
+        rec.ticket = f.req.ticket;
+        rec.arrival_ns = f.req.arrival_ns - s->t0_ns;
+        rec.launch_ns = f.launch_ns - s->t0_ns;
+        rec.done_ns = t - s->t0_ns;
+        rec.cells = f.cells;
+        rec.mesh = f.req.mesh;
+        rec.count = f.req.count;
+        rec.retries = f.req.retries;
+        rec.reserved = 0;
+        s->log.push_back(rec);
         s->completed++;
         s->cells_updated += f.cells;
         s->last_completion_ns = t;
-        s->inflight_bytes -= f.bytes;
-        s->staging[f.staging].busy = false;
-        s->spare_events.push_back(f.done);
+        release_inflight(s, f);
         s->inflight.pop_front();
     }
+    return FV_OK;
 }
 
 // Admit queued batches while the budget and the in-flight limit allow.
@@ -310,12 +428,13 @@ fv_status admit(fv_server *s) {
         f.req = r;
         f.staging = si;
         f.bytes = b;
+        f.launch_ns = now_ns();
         f.done = take_event(s);
         if (!f.done || hipEventRecord(f.done, s->stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "event record failed");
         for (int32_t k = 0; k < r.count; ++k) {
             const int32_t t = r.first + k;
             m.cur[t] ^= 1u;
-            f.cells += (int64_t)std::pow(m.sizes[t], s->cfg.dim);
+            f.cells += (int64_t)std::pow(m.sizes[t], m.dim);
         }
         st.busy = true;
         s->inflight_bytes += b;
@@ -345,6 +464,8 @@ void fill_stats(const fv_server *s, fv_server_stats *out) {
     out->peak_queued = s->peak_queue;
     out->peak_inflight = s->peak_inflight;
     out->cells_updated = s->cells_updated;
+    out->failed = s->failed;
+    out->retried = s->retried;
     out->resident_bytes = s->resident_bytes;
     out->budget_bytes = s->cfg.budget_bytes;
     out->p50_ms = percentile(s->latency_ms, 0.50);
@@ -376,11 +497,14 @@ fv_status fv_server_create(fv_server **server, const fv_server_config *cfg) {
     clear_error();
     if (!server || !cfg) return fail(FV_ERR_INVALID_ARG, "server and cfg must be non-null");
     *server = nullptr;
-    fv_status st = check_scalars(cfg->dim, cfg->unknowns, 1.0, cfg->h, cfg->gamma, cfg->flags);
+    fv_status st = check_scalars(2, 5, 1.0, 1.0, cfg->gamma, cfg->flags);
     if (st != FV_OK) return st;
     if (cfg->budget_bytes <= 0) return fail(FV_ERR_INVALID_ARG, "budget_bytes must be > 0");
     if (cfg->mode != FV_SERVE_FUSED && cfg->mode != FV_SERVE_PLAIN) return fail(FV_ERR_INVALID_ARG, "unknown mode %d", cfg->mode);
     if (cfg->max_inflight < 0 || cfg->max_inflight > 1024) return fail(FV_ERR_INVALID_ARG, "max_inflight must be in [0, 1024]");
+    if (cfg->max_retries < 0 || cfg->max_retries > 16) return fail(FV_ERR_INVALID_ARG, "max_retries must be in [0, 16]");
+    if (!std::isfinite(cfg->deadline_ms) || cfg->deadline_ms < 0.0)
+        return fail(FV_ERR_INVALID_ARG, "deadline_ms must be finite and >= 0");
     DeviceContext *ctx = nullptr;
     if ((st = current_context(&ctx)) != FV_OK) return st;
     auto *s = new fv_server();
@@ -392,27 +516,32 @@ fv_status fv_server_create(fv_server **server, const fv_server_config *cfg) {
         return fail(FV_ERR_LAUNCH, "stream creation failed");
     }
     s->staging.resize(s->cfg.max_inflight);
+    s->t0_ns = now_ns();
     *server = s;
     return FV_OK;
 }
 
-fv_status fv_server_add_mesh(fv_server *s, const int32_t *sizes, int32_t num_patches, const double *host_state,
-                             int32_t *mesh_id) {
+fv_status fv_server_add_mesh(fv_server *s, int32_t dim, int32_t unknowns, double h, const int32_t *sizes,
+                             int32_t num_patches, const double *host_state, int32_t *mesh_id) {
     clear_error();
     fv_status st = check_server(s);
     if (st != FV_OK) return st;
+    if ((st = check_scalars(dim, unknowns, 1.0, h, s->cfg.gamma, 0)) != FV_OK) return st;
     if (!sizes || !host_state || !mesh_id || num_patches < 1)
         return fail(FV_ERR_INVALID_ARG, "sizes, host_state, mesh_id and num_patches >= 1 are required");
     Mesh m;
+    m.dim = dim;
+    m.nq = unknowns;
+    m.h = h;
     m.sizes.assign(sizes, sizes + num_patches);
     m.off.resize(num_patches);
     m.cur.assign(num_patches, 0);
     int64_t o = 0;
-    const int pmax = max_p(s->cfg.dim);
+    const int pmax = max_p(dim);
     for (int32_t t = 0; t < num_patches; ++t) {
         if (sizes[t] < 1 || sizes[t] > pmax) return fail(FV_ERR_INVALID_ARG, "sizes[%d]=%d outside [1, %d]", t, sizes[t], pmax);
         m.off[t] = o;
-        o += patch_doubles(sizes[t], s->cfg.dim, s->cfg.unknowns);
+        o += patch_doubles(sizes[t], dim, unknowns);
     }
     m.slot_doubles = o + (o & 1);  // keep the second slot 16-byte aligned
     const int64_t bytes = 2 * m.slot_doubles * (int64_t)sizeof(double);
@@ -461,8 +590,8 @@ fv_status fv_server_poll(fv_server *s, fv_server_stats *stats) {
     clear_error();
     fv_status st = check_server(s);
     if (st != FV_OK) return st;
-    retire(s, false);
-    st = admit(s);
+    st = retire(s, false);
+    if (st == FV_OK) st = admit(s);
     fill_stats(s, stats);
     return st;
 }
@@ -473,7 +602,10 @@ fv_status fv_server_drain(fv_server *s, fv_server_stats *stats) {
     if (st != FV_OK) return st;
     while (!s->queue.empty() || !s->inflight.empty()) {
         if ((st = admit(s)) != FV_OK) return st;  // FV_ERR_BUDGET if a batch can never fit
-        retire(s, true);
+        if ((st = retire(s, true)) != FV_OK) {
+            fill_stats(s, stats);
+            return st;
+        }
     }
     fill_stats(s, stats);
     return FV_OK;
@@ -490,13 +622,17 @@ fv_status fv_server_run_trace(fv_server *s, const fv_serve_request *reqs, int64_
     for (int64_t k = 0; k < n; ++k) {
         const int64_t due = t0 + reqs[k].arrival_ns;
         while (now_ns() < due) {
-            retire(s, false);
-            if ((st = admit(s)) != FV_OK) return st;
+            if ((st = retire(s, false)) != FV_OK || (st = admit(s)) != FV_OK) {
+                fill_stats(s, stats);
+                return st;
+            }
         }
         st = fv_server_submit(s, reqs[k].mesh, reqs[k].first, reqs[k].count, reqs[k].dt, due, nullptr);
         if (st != FV_OK) return st;
-        retire(s, false);
-        if ((st = admit(s)) != FV_OK) return st;
+        if ((st = retire(s, false)) != FV_OK || (st = admit(s)) != FV_OK) {
+            fill_stats(s, stats);
+            return st;
+        }
     }
     return fv_server_drain(s, stats);
 }
@@ -509,12 +645,39 @@ fv_status fv_server_read_mesh(fv_server *s, int32_t mesh_id, double *host_state)
     if ((st = fv_server_drain(s, nullptr)) != FV_OK) return st;
     const Mesh &m = s->meshes[mesh_id];
     for (size_t t = 0; t < m.sizes.size(); ++t) {
-        const int64_t n = patch_doubles(m.sizes[t], s->cfg.dim, s->cfg.unknowns);
+        const int64_t n = patch_doubles(m.sizes[t], m.dim, m.nq);
         const double *src = m.buf + (m.cur[t] ? m.slot_doubles : 0) + m.off[t];
         if (hipMemcpyAsync(host_state + m.off[t], src, n * sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess)
             return fail(FV_ERR_LAUNCH, "read-back failed");
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "read-back failed");
+    return FV_OK;
+}
+
+fv_status fv_server_inject(fv_server *s, int64_t ticket, int32_t kind, int32_t times) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (ticket < 1) return fail(FV_ERR_INVALID_ARG, "tickets start at 1");
+    if (kind == 0) {
+        s->inject.erase(ticket);
+        return FV_OK;
+    }
+    if (kind != FV_INJECT_FAIL && kind != FV_INJECT_HANG) return fail(FV_ERR_INVALID_ARG, "unknown injection %d", kind);
+    if (kind == FV_INJECT_FAIL && times < 1) return fail(FV_ERR_INVALID_ARG, "times must be >= 1");
+    s->inject[ticket] = Injection{kind, times};
+    return FV_OK;
+}
+
+fv_status fv_server_batch_log(fv_server *s, fv_batch_record *records, int64_t capacity, int64_t *count) {
+    clear_error();
+    fv_status st = check_server(s);
+    if (st != FV_OK) return st;
+    if (!count || capacity < 0 || (capacity > 0 && !records))
+        return fail(FV_ERR_INVALID_ARG, "count must be non-null and records hold capacity entries");
+    const int64_t n = std::min<int64_t>(capacity, (int64_t)s->log.size());
+    if (n > 0) std::memcpy(records, s->log.data(), sizeof(fv_batch_record) * (size_t)n);
+    *count = (int64_t)s->log.size();
     return FV_OK;
 }
 

@@ -2,8 +2,8 @@
 //
 // The paper's patches are separate allocations on the CPU heap that are
 // brought to the accelerator one by one; those scattered transfers dominate
-// its runtime (Sec. 6, Fig. 4), and recycling device allocations instead of
-// freeing them ("managed memory", Sec. 5) was its best remedy.  Three ways to
+// its runtime (Sec. 5, Fig. 4), and recycling device allocations instead of
+// freeing them ("managed memory", Sec. 4) was its best remedy.  Three ways to
 // move such patches through the fused update:
 //   per patch   every patch copied to a recycled device area with its own
 //               synchronous hipMemcpy from pageable memory, one launch over

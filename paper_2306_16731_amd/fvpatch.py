@@ -35,14 +35,18 @@ FV_MAX_P_3D = 24
 
 # Every symbol the header declares (checked by the tests against include/fvpatch.h).
 EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_create", "fv_plan_execute",
-           "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_server_create",
+           "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_plan_get_tuning",
+           "fv_server_create",
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
-           "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_mesh_create",
+           "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy", "fv_server_inject",
+           "fv_server_batch_log", "fv_mesh_create",
            "fv_mesh_halo_fill", "fv_mesh_step", "fv_local_dt", "fv_mesh_destroy", "fv_flavour_update",
            "fv_host_patches_update", "fv_host_alloc", "fv_host_free", "fv_pde_unknowns", "fv_pde_batch_update", "fv_status_string",
-           "fv_last_error", "fv_version"]
+           "fv_last_error", "fv_version", "fv_build_id"]
 FV_SERVE_FUSED = 0
 FV_SERVE_PLAIN = 1
+FV_INJECT_FAIL = 1
+FV_INJECT_HANG = 2
 FV_HALO_FROM_IN = 0x4
 FV_PLAN_NO_PERSIST = 0x100
 FV_PLAN_PER_CLASS = 0x200
@@ -97,9 +101,9 @@ class fv_plan_stats(ctypes.Structure):
 
 
 class fv_server_config(ctypes.Structure):
-    _fields_ = [("budget_bytes", ctypes.c_int64), ("dim", ctypes.c_int32), ("unknowns", ctypes.c_int32),
-                ("h", ctypes.c_double), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("mode", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("gamma", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("mode", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("max_retries", ctypes.c_int32),
+                ("deadline_ms", ctypes.c_double)]
 
 
 class fv_serve_request(ctypes.Structure):
@@ -113,11 +117,17 @@ SERVE_REQUEST_DTYPE = np.dtype([("arrival_ns", "<i8"), ("mesh", "<i4"), ("first"
 
 class fv_server_stats(ctypes.Structure):
     _fields_ = ([(n, ctypes.c_int64) for n in ("submitted", "completed", "queued", "inflight", "peak_queued",
-                                               "peak_inflight", "cells_updated", "resident_bytes", "budget_bytes")]
+                                               "peak_inflight", "cells_updated", "failed", "retried",
+                                               "resident_bytes", "budget_bytes")]
                 + [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "cell_updates_per_s")])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+BATCH_RECORD_DTYPE = np.dtype([("ticket", "<i8"), ("arrival_ns", "<i8"), ("launch_ns", "<i8"), ("done_ns", "<i8"),
+                               ("cells", "<i8"), ("mesh", "<i4"), ("count", "<i4"), ("retries", "<i4"),
+                               ("reserved", "<i4")])
 
 
 class fv_transfer_config(ctypes.Structure):
@@ -137,7 +147,9 @@ _lib = None
 
 
 def load(path: str = LIBRARY):
-    """Load libfvpatch.so (built by ``python -m paper_2306_16731_amd.build``)."""
+    """Load libfvpatch.so (built by ``python -m paper_2306_16731_amd.build``).  A library built from
+    other sources than the ones beside it (its fv_build_id() differs from the hash of the current
+    sources) is refused with ImportError, unless FVPATCH_ALLOW_STALE=1."""
     global _lib
     if _lib is not None:
         return _lib
@@ -145,6 +157,14 @@ def load(path: str = LIBRARY):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2306_16731_amd.build` "
                           "(there is no fallback implementation)")
     lib = ctypes.CDLL(path)
+    lib.fv_build_id.argtypes = []
+    lib.fv_build_id.restype = ctypes.c_char_p
+    if path == LIBRARY and os.environ.get("FVPATCH_ALLOW_STALE") != "1":
+        from . import build as _build
+        built, now = lib.fv_build_id().decode(), _build.source_hash()
+        if built != now:
+            raise ImportError(f"{path} was built from other sources (build id {built}, sources {now}): rebuild "
+                              "it with `python -m paper_2306_16731_amd.build`")
     vp, i32, i64, f64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
     lib.fv_patch_batch_update.argtypes = [vp, vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp, vp]
     lib.fv_patch_batch_update.restype = ctypes.c_int
@@ -159,9 +179,11 @@ def load(path: str = LIBRARY):
     lib.fv_get_tuning.argtypes = [i32, i32, i32, ctypes.POINTER(fv_tuning)]
     lib.fv_get_tuning.restype = ctypes.c_int
     pp = ctypes.POINTER(ctypes.c_void_p)
-    lib.fv_plan_create.argtypes = [pp, vp, vp, i32, i32, i32, u32]
+    lib.fv_plan_create.argtypes = [pp, vp, vp, i32, i32, i32, u32, vp, i32]
     lib.fv_plan_create.restype = ctypes.c_int
-    lib.fv_plan_execute.argtypes = [vp, vp, vp, f64, f64, f64, vp, vp]
+    lib.fv_plan_get_tuning.argtypes = [vp, i32, ctypes.POINTER(fv_tuning)]
+    lib.fv_plan_get_tuning.restype = ctypes.c_int
+    lib.fv_plan_execute.argtypes = [vp, vp, vp, f64, vp, f64, f64, vp, vp]
     lib.fv_plan_execute.restype = ctypes.c_int
     lib.fv_plan_capture_steps.argtypes = [vp, i32, vp, vp, f64, f64, f64, vp, vp, vp]
     lib.fv_plan_capture_steps.restype = ctypes.c_int
@@ -173,7 +195,9 @@ def load(path: str = LIBRARY):
     lib.fv_plan_destroy.restype = ctypes.c_int
     sp = ctypes.POINTER(fv_server_stats)
     lib.fv_server_create.argtypes = [pp, ctypes.POINTER(fv_server_config)]
-    lib.fv_server_add_mesh.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.fv_server_add_mesh.argtypes = [vp, i32, i32, f64, vp, i32, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.fv_server_inject.argtypes = [vp, i64, i32, i32]
+    lib.fv_server_batch_log.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]
     lib.fv_server_submit.argtypes = [vp, i32, i32, i32, f64, i64, ctypes.POINTER(ctypes.c_int64)]
     lib.fv_server_poll.argtypes = [vp, sp]
     lib.fv_server_drain.argtypes = [vp, sp]
@@ -182,6 +206,7 @@ def load(path: str = LIBRARY):
     lib.fv_server_stats_get.argtypes = [vp, sp]
     lib.fv_server_destroy.argtypes = [vp]
     for name in ("fv_server_create", "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain",
+                 "fv_server_inject", "fv_server_batch_log",
                  "fv_server_run_trace", "fv_server_read_mesh", "fv_server_stats_get", "fv_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     lib.fv_mesh_create.argtypes = [pp, vp, vp, vp, i32, i32, i32]
@@ -296,14 +321,35 @@ def fv_get_tuning(dim: int, unknowns: int, p: int) -> dict:
 
 
 # ---------------------------------------------------------------- plans (batching form)
-def fv_plan_create(sizes, offsets, num_patches: int, dim: int, unknowns: int, flags: int = 0,
+class fv_tune_entry(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("unknowns", ctypes.c_int32), ("p", ctypes.c_int32), ("tuning", fv_tuning)]
+
+
+def tune_table(entries) -> ctypes.Array | None:
+    """A plan's tuning table from {(dim, unknowns, p): {kernel, block, prefetch, rows}} (or a list of
+    (dim, unknowns, p, dict) tuples); None for no entries."""
+    items = list(entries.items()) if isinstance(entries, dict) else [((d, n, p), t) for d, n, p, t in entries]
+    if not items:
+        return None
+    arr = (fv_tune_entry * len(items))()
+    for k, ((d, n, p), t) in enumerate(items):
+        tt = t if isinstance(t, fv_tuning) else fv_tuning(**{f: int(t.get(f, 0)) for f in ("kernel", "block",
+                                                                                            "prefetch", "rows")})
+        arr[k] = fv_tune_entry(int(d), int(n), int(p), tt)
+    return arr
+
+
+def fv_plan_create(sizes, offsets, num_patches: int, dim: int, unknowns: int, flags: int = 0, tune=None,
                    raise_on_error: bool = True):
-    """Build a plan; returns its handle (an int), or (status, None) when raise_on_error is False."""
+    """Build a plan; returns its handle (an int), or (status, None) when raise_on_error is False.
+    tune: the plan's own tuning table (see tune_table), or None."""
     lib = load()
     h = ctypes.c_void_p()
     sz, sz_p = _host_array(sizes, np.int32)
     of, of_p = _host_array(offsets, np.int64)
-    st = lib.fv_plan_create(ctypes.byref(h), sz_p, of_p, int(num_patches), int(dim), int(unknowns), int(flags))
+    table = tune_table(tune) if tune is not None else None
+    st = lib.fv_plan_create(ctypes.byref(h), sz_p, of_p, int(num_patches), int(dim), int(unknowns), int(flags),
+                            table, len(table) if table is not None else 0)
     del sz, of
     if raise_on_error:
         _check(st)
@@ -311,10 +357,17 @@ def fv_plan_create(sizes, offsets, num_patches: int, dim: int, unknowns: int, fl
     return st, h.value
 
 
+def fv_plan_get_tuning(plan, p: int) -> dict:
+    t = fv_tuning()
+    _check(load().fv_plan_get_tuning(plan, int(p), ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in fv_tuning._fields_}
+
+
 def fv_plan_execute(plan, patches_in, patches_out, dt: float, h: float, gamma: float = 1.4, lambda_out=None,
-                    stream=None, raise_on_error: bool = True) -> int:
-    st = load().fv_plan_execute(plan, _dev_ptr(patches_in), _dev_ptr(patches_out), float(dt), float(h), float(gamma),
-                                _dev_ptr(lambda_out), _stream_handle(stream))
+                    stream=None, dt_dev=None, raise_on_error: bool = True) -> int:
+    """One step of the plan; dt_dev (a device double) replaces the host dt when given."""
+    st = load().fv_plan_execute(plan, _dev_ptr(patches_in), _dev_ptr(patches_out), float(dt), _dev_ptr(dt_dev),
+                                float(h), float(gamma), _dev_ptr(lambda_out), _stream_handle(stream))
     return _check(st) if raise_on_error else st
 
 
@@ -486,10 +539,10 @@ def fv_host_patches_update(patches_in, patches_out, sizes, num_patches: int, dim
 
 
 # ---------------------------------------------------------------- servers (serving form)
-def fv_server_create(budget_bytes: int, dim: int, unknowns: int, h: float, gamma: float = 1.4, flags: int = 0,
-                     mode: int = 0, max_inflight: int = 0, raise_on_error: bool = True):
-    cfg = fv_server_config(int(budget_bytes), int(dim), int(unknowns), float(h), float(gamma), int(flags), int(mode),
-                           int(max_inflight), 0)
+def fv_server_create(budget_bytes: int, gamma: float = 1.4, flags: int = 0, mode: int = 0, max_inflight: int = 0,
+                     max_retries: int = 0, deadline_ms: float = 0.0, raise_on_error: bool = True):
+    cfg = fv_server_config(int(budget_bytes), float(gamma), int(flags), int(mode), int(max_inflight),
+                           int(max_retries), float(deadline_ms))
     hdl = ctypes.c_void_p()
     st = load().fv_server_create(ctypes.byref(hdl), ctypes.byref(cfg))
     if raise_on_error:
@@ -498,17 +551,34 @@ def fv_server_create(budget_bytes: int, dim: int, unknowns: int, h: float, gamma
     return st, hdl.value
 
 
-def fv_server_add_mesh(server, sizes, host_state, raise_on_error: bool = True):
+def fv_server_add_mesh(server, dim: int, unknowns: int, h: float, sizes, host_state, raise_on_error: bool = True):
     """Register a mesh (host_state: float64 array in the contiguous layout); returns its id."""
     sz, sz_p = _host_array(sizes, np.int32)
     state = np.ascontiguousarray(host_state, dtype=np.float64)
     mid = ctypes.c_int32(-1)
-    st = load().fv_server_add_mesh(server, sz_p, len(sz), state.ctypes.data, ctypes.byref(mid))
+    st = load().fv_server_add_mesh(server, int(dim), int(unknowns), float(h), sz_p, len(sz), state.ctypes.data,
+                                   ctypes.byref(mid))
     del sz
     if raise_on_error:
         _check(st)
         return mid.value
     return st, mid.value
+
+
+def fv_server_inject(server, ticket: int, kind: int, times: int = 0, raise_on_error: bool = True) -> int:
+    """Test hook: override the completion check of batch `ticket` (FV_INJECT_FAIL / FV_INJECT_HANG; 0 clears)."""
+    st = load().fv_server_inject(server, int(ticket), int(kind), int(times))
+    return _check(st) if raise_on_error else st
+
+
+def fv_server_batch_log(server) -> np.ndarray:
+    """Records of the completed batches (structured array of BATCH_RECORD_DTYPE)."""
+    n = ctypes.c_int64(0)
+    _check(load().fv_server_batch_log(server, None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=BATCH_RECORD_DTYPE)
+    if n.value:
+        _check(load().fv_server_batch_log(server, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out
 
 
 def fv_server_submit(server, mesh: int, first: int, count: int, dt: float, arrival_ns: int = 0,

@@ -62,6 +62,56 @@ def call(**kw):
     return F.fv_patch_batch_update(raise_on_error=False, **args)
 
 
+def test_build_id_is_the_hash_of_the_sources():
+    """The loaded library reports the hash of the sources it was built from, and the loader refuses
+    a library whose id differs from the sources beside it."""
+    assert F.load().fv_build_id().decode() == fvbuild.source_hash()
+    assert fvbuild.stale() is False
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures and numpy record types have the header's sizes and field
+    offsets (a C program compiled against include/fvpatch.h prints them)."""
+    import subprocess
+    structs = {"fv_tuning": F.fv_tuning, "fv_plan_stats": F.fv_plan_stats, "fv_server_config": F.fv_server_config,
+               "fv_serve_request": F.fv_serve_request, "fv_server_stats": F.fv_server_stats,
+               "fv_transfer_config": F.fv_transfer_config, "fv_transfer_stats": F.fv_transfer_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fvpatch.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    for fname in F.BATCH_RECORD_DTYPE.names:
+        lines.append(f'printf("fv_batch_record.{fname} %zu\\n", offsetof(fv_batch_record, {fname}));')
+    lines.append('printf("fv_batch_record %zu\\n", sizeof(fv_batch_record));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.split("\n") if line)
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
+    assert int(got["fv_batch_record"]) == F.BATCH_RECORD_DTYPE.itemsize
+    for fname in F.BATCH_RECORD_DTYPE.names:
+        assert int(got[f"fv_batch_record.{fname}"]) == F.BATCH_RECORD_DTYPE.fields[fname][1], fname
+
+
+def test_server_config_validation():
+    """fv_server_create rejects bad configurations before touching a device."""
+    for kw in (dict(max_retries=-1), dict(max_retries=17), dict(deadline_ms=-1.0), dict(deadline_ms=float("nan")),
+               dict(max_inflight=2000), dict(mode=7), dict(gamma=1.0), dict(flags=0x80)):
+        args = dict(budget_bytes=1 << 30)
+        args.update(kw)
+        st, h = F.fv_server_create(raise_on_error=False, **args)
+        assert st == F.FV_ERR_INVALID_ARG, kw
+    st, h = F.fv_server_create(0, raise_on_error=False)
+    assert st == F.FV_ERR_INVALID_ARG
+
+
 def test_status_strings():
     assert F.fv_status_string(F.FV_OK) == "ok"
     assert F.fv_status_string(F.FV_ERR_OVERLAP) == "overlapping buffers"
@@ -164,7 +214,36 @@ def test_plan_validation_before_device():
     assert st == F.FV_ERR_NO_DEVICE and not h
     assert F.fv_plan_destroy(None) == F.FV_OK
     assert F.load().fv_plan_replay(None, None) == F.FV_ERR_INVALID_ARG
-    assert F.load().fv_plan_execute(None, IN, OUT, 1e-3, 1 / 48, 1.4, None, None) == F.FV_ERR_INVALID_ARG
+    assert F.load().fv_plan_execute(None, IN, OUT, 1e-3, None, 1 / 48, 1.4, None, None) == F.FV_ERR_INVALID_ARG
+    assert F.load().fv_plan_get_tuning(None, 4, None) == F.FV_ERR_INVALID_ARG
+
+
+def test_plan_tuning_table_validation_before_device():
+    """A plan's own tuning table is checked like fv_set_tuning's argument, before any device work;
+    entries for another (dim, unknowns) are ignored."""
+    base = dict(sizes=[4, 4], offsets=None, num_patches=2, dim=2, unknowns=5)
+    bad = [
+        ({(2, 5, 4): dict(kernel=9)}, F.FV_ERR_INVALID_ARG),
+        ({(2, 5, 4): dict(kernel=F.FV_KERNEL_FIXED)}, F.FV_ERR_UNSUPPORTED),       # no fixed build for p = 4
+        ({(2, 5, 4): dict(kernel=F.FV_KERNEL_WAVE, block=100)}, F.FV_ERR_INVALID_ARG),
+        ({(2, 5, 65): dict(kernel=F.FV_KERNEL_BLOCK)}, F.FV_ERR_INVALID_ARG),
+        ([(2, 5, 4, dict(kernel=F.FV_KERNEL_WAVE)), (2, 5, 4, dict(kernel=F.FV_KERNEL_BLOCK))], F.FV_ERR_INVALID_ARG),
+    ]
+    for tune, status in bad:
+        st, h = F.fv_plan_create(raise_on_error=False, tune=tune, **base)
+        assert st == status and not h, (tune, st, F.fv_last_error())
+    # an entry for another dimension is ignored: the call gets as far as the device check
+    st, h = F.fv_plan_create(raise_on_error=False, tune={(3, 5, 99): dict(kernel=9)}, **base)
+    try:
+        import torch
+        expect = F.FV_OK if torch.cuda.is_available() else F.FV_ERR_NO_DEVICE
+    except ImportError:
+        expect = F.FV_ERR_NO_DEVICE
+    assert st == expect, F.fv_last_error()
+    if h:
+        F.fv_plan_destroy(h)
+    assert F.load().fv_plan_create(ctypes.byref(ctypes.c_void_p()), (ctypes.c_int32 * 2)(4, 4), None, 2, 2, 5, 0,
+                                   None, 3) == F.FV_ERR_INVALID_ARG
 
 
 def test_tuning_table_on_host():

@@ -174,6 +174,43 @@ def test_evenly_spaced_offsets(dim, p, base, gap, periodic):
     assert hp.lambda_error(results["even"][1], want_lam) <= TOL
 
 
+@pytest.mark.parametrize("kernel", ["tile", "wave", "block"])
+@pytest.mark.parametrize("p,gap", [(7, 1), (17, 3), (9, 1)])
+def test_evenly_spaced_offsets_tuned_odd_patches(kernel, p, gap):
+    """Patches with an odd number of doubles at an even spacing (the gap makes the stride even)
+    under every runtime-size kernel the tuner may install: the evenly spaced fast path must not
+    take 16-byte accesses for them; the result equals the descriptor path's and the oracle's."""
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"evenly spaced odd patches p={p} gap={gap} kernel={kernel}")
+    kid = {"tile": fvpatch.FV_KERNEL_TILE, "wave": fvpatch.FV_KERNEL_WAVE, "block": fvpatch.FV_KERNEL_BLOCK}[kernel]
+    T, dim = 67, 2
+    vol = (p + 2) ** dim * 5
+    assert vol % 2 == 1 and (vol + gap) % 2 == 0
+    compact = wl.make_uniform(T, p, dim=dim, seed=63)
+    offs = np.arange(T, dtype=np.int64) * (vol + gap)
+    total = int(offs[-1] + vol + 2)
+    data = np.random.Generator(np.random.PCG64(64)).uniform(-1, 1, total)
+    for t in range(T):
+        data[offs[t]:offs[t] + vol] = compact.data[t * vol:(t + 1) * vol]
+    fvpatch.fv_set_tuning(dim, 5, p, {"kernel": kid})
+    try:
+        got, lam = hp.gpu_step(data, compact.sizes, offs, dim, 5, 1.2e-3, wl.H_DEFAULT, wl.GAMMA, False)
+    finally:
+        fvpatch.fv_set_tuning(dim, 5, p, None)
+    mask = np.ones(total, bool)
+    for t in range(T):
+        mask[offs[t]:offs[t] + vol] = False
+    assert np.array_equal(got[mask], data[mask]), "bytes outside the patches were written"
+    want, want_lam = oracle.batch_update(compact.data, compact.sizes, compact.offsets, dim, 5, 1.2e-3,
+                                         wl.H_DEFAULT, wl.GAMMA, False)
+    got_c = np.concatenate([got[o:o + vol] for o in offs])
+    inner = np.zeros((p + 2, p + 2), bool)
+    inner[1:-1, 1:-1] = True
+    sel = np.tile(np.repeat(inner.ravel(), 5), T)
+    assert np.all(hp.component_errors(got_c[sel], want[sel], 5) <= TOL)
+    assert hp.lambda_error(lam, want_lam) <= TOL
+
+
 def test_single_patch_and_zero_patches():
     import torch
     from paper_2306_16731_amd import fvpatch

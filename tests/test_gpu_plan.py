@@ -47,11 +47,11 @@ def oracle_dts(batch, steps, periodic, dt0, h=wl.H_DEFAULT, cfl=wl.CFL):
     return dts
 
 
-def run_plan(batch, dts, periodic, flags=0):
+def run_plan(batch, dts, periodic, flags=0, tune=None):
     import torch
     from paper_2306_16731_amd import fvpatch
     plan = fvpatch.fv_plan_create(batch.sizes, batch.offsets, batch.num_patches, batch.dim, batch.nq,
-                                  flags | (fvpatch.FV_HALO_PERIODIC if periodic else 0))
+                                  flags | (fvpatch.FV_HALO_PERIODIC if periodic else 0), tune=tune)
     try:
         info = fvpatch.fv_plan_info(plan)
         a = hp.to_dev(batch.data)
@@ -147,16 +147,96 @@ def test_plan_mixed_sizes_runtime_size_bodies(periodic, persistent):
     from paper_2306_16731_amd import fvpatch
     _announce(f"plan: mixed sizes, runtime-size bodies, periodic={periodic}, persistent={persistent}")
     b = wl.make_mixed(1500, choices=(4, 7, 12, 20, 9), seed=24)
-    try:
-        for p in (4, 7, 12, 20):
-            fvpatch.fv_set_tuning(2, 5, p, dict(kernel=fvpatch.FV_KERNEL_WAVE, block=256, prefetch=3, rows=4))
-        dts = oracle_dts(b, 3, periodic, 1.5e-3)
-        got, lams, info = run_plan(b, dts, periodic, 0 if persistent else fvpatch.FV_PLAN_NO_PERSIST)
-        assert info["prefetch"] == 3
-    finally:
-        for p in (4, 7, 12, 20):
-            fvpatch.fv_set_tuning(2, 5, p, None)
+    table = {(2, 5, p): dict(kernel=fvpatch.FV_KERNEL_WAVE, block=256, prefetch=3, rows=4) for p in (4, 7, 12, 20)}
+    dts = oracle_dts(b, 3, periodic, 1.5e-3)
+    got, lams, info = run_plan(b, dts, periodic, 0 if persistent else fvpatch.FV_PLAN_NO_PERSIST, tune=table)
+    assert info["prefetch"] == 3
     check_against_oracle(b, dts, periodic, got, lams)
+
+
+def test_two_plans_with_their_own_tuning_tables_side_by_side():
+    """Two plans over the same mixed batch, each launching every class on its own kernel with its own
+    table (tile / block / wave kernels with different blocks and rows per class), stepped alternately
+    in one process: each reports its own resolved tuning, the process-wide tuning is untouched, and
+    both match the oracle (and each other, bit for bit: every kernel rounds the same way)."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce("two plans, two tuning tables")
+    K = fvpatch
+    b = wl.make_mixed(900, choices=(4, 7, 12, 9), seed=25)
+    tables = {
+        "a": {(2, 5, 4): dict(kernel=K.FV_KERNEL_TILE, block=64), (2, 5, 7): dict(kernel=K.FV_KERNEL_BLOCK, block=128),
+              (2, 5, 12): dict(kernel=K.FV_KERNEL_WAVE, block=128, prefetch=2, rows=8),
+              (3, 5, 8): dict(kernel=K.FV_KERNEL_BLOCK, block=128)},   # another dim: ignored
+        "b": {(2, 5, 4): dict(kernel=K.FV_KERNEL_WAVE, block=256, prefetch=4, rows=4),
+              (2, 5, 7): dict(kernel=K.FV_KERNEL_WAVE, block=128, prefetch=2, rows=6),
+              (2, 5, 12): dict(kernel=K.FV_KERNEL_BLOCK, block=256), (2, 5, 9): dict(kernel=K.FV_KERNEL_TILE)},
+    }
+    before = {p: K.fv_get_tuning(2, 5, p) for p in (4, 7, 9, 12)}
+    flags = K.FV_PLAN_PER_CLASS | K.FV_HALO_PERIODIC
+    plans = {k: K.fv_plan_create(b.sizes, b.offsets, b.num_patches, 2, 5, flags, tune=t) for k, t in tables.items()}
+    try:
+        assert {p: K.fv_get_tuning(2, 5, p) for p in (4, 7, 9, 12)} == before
+        assert K.fv_plan_get_tuning(plans["a"], 4)["kernel"] == K.FV_KERNEL_TILE
+        assert K.fv_plan_get_tuning(plans["b"], 4)["kernel"] == K.FV_KERNEL_WAVE
+        assert K.fv_plan_get_tuning(plans["a"], 12) == dict(kernel=K.FV_KERNEL_WAVE, block=128, prefetch=2, rows=8)
+        assert K.fv_plan_get_tuning(plans["b"], 12)["kernel"] == K.FV_KERNEL_BLOCK
+        assert K.fv_plan_get_tuning(plans["a"], 9) == before[9]     # no entry: the installed default
+        assert K.fv_plan_get_tuning(plans["b"], 9)["kernel"] == K.FV_KERNEL_TILE
+        dts = oracle_dts(b, 3, True, 1.2e-3)
+        bufs = {k: [hp.to_dev(b.data), None] for k in plans}
+        for k in bufs:
+            bufs[k][1] = bufs[k][0].clone()
+        lams = {k: torch.empty((len(dts), b.num_patches), dtype=torch.float64, device="cuda") for k in plans}
+        for step, dt in enumerate(dts):
+            for k, plan in plans.items():      # alternate between the plans every step
+                K.fv_plan_execute(plan, bufs[k][0], bufs[k][1], dt, wl.H_DEFAULT, wl.GAMMA, lams[k][step])
+                bufs[k].reverse()
+        torch.cuda.synchronize()
+        got = {k: (bufs[k][0].cpu().numpy(), list(lams[k].cpu().numpy())) for k in plans}
+    finally:
+        for plan in plans.values():
+            K.fv_plan_destroy(plan)
+    assert np.array_equal(got["a"][0], got["b"][0])
+    for k in plans:
+        check_against_oracle(b, dts, True, *got[k])
+
+
+@pytest.mark.parametrize("name,T", [("c3_2d_mixed_T200000", 1200), ("c4_3d_p8_T32768", 100)])
+def test_plan_execute_with_device_dt(name, T):
+    """fv_plan_execute with dt in device memory: the step reads it when it runs, and the result equals
+    the host-dt step bit for bit (dt / h is correctly rounded on both sides)."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"plan execute with device dt: {name} T={T}")
+    b, _ = wl.build_workload(name, seed=26, num_patches=T)
+    plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, b.dim, b.nq, fvpatch.FV_PLAN_NO_PERSIST if b.dim == 2 else 0)
+    try:
+        dts = [1.3e-3, 0.7e-3, 1.1e-3]
+        res = {}
+        for mode in ("host", "device"):
+            a = hp.to_dev(b.data)
+            c = a.clone()
+            lam = torch.empty((len(dts), T), dtype=torch.float64, device="cuda")
+            dt_dev = torch.full((1,), 99.0, dtype=torch.float64, device="cuda")
+            for k, dt in enumerate(dts):
+                if mode == "host":
+                    fvpatch.fv_plan_execute(plan, a, c, dt, wl.H_DEFAULT, wl.GAMMA, lam[k])
+                else:
+                    dt_dev.fill_(dt)     # ordered before the step on the same stream
+                    fvpatch.fv_plan_execute(plan, a, c, -1.0, wl.H_DEFAULT, wl.GAMMA, lam[k], dt_dev=dt_dev)
+                a, c = c, a
+            torch.cuda.synchronize()
+            res[mode] = (a.cpu().numpy(), lam.cpu().numpy())
+        d = hp.to_dev(b.data)
+        out = d.clone()
+        assert fvpatch.fv_plan_execute(plan, d, out, 1e-3, wl.H_DEFAULT, wl.GAMMA, None, dt_dev=out[3:4],
+                                       raise_on_error=False) == fvpatch.FV_ERR_OVERLAP
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+    assert np.array_equal(res["host"][0], res["device"][0])
+    assert np.array_equal(res["host"][1], res["device"][1])
+    check_against_oracle(b, dts, False, res["device"][0], list(res["device"][1]))
 
 
 def test_plan_mixed_with_large_class_odd_offsets_periodic():
