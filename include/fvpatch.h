@@ -257,7 +257,9 @@ fv_status fv_plan_execute(fv_plan *plan, const double *patches_in, double *patch
  * dt_dev[k+1] = cfl h / (dim max lambda) on the device (NaN-propagating).
  * dt_dev: device [steps + 1].  `stream` must be a non-null stream; before
  * capturing, the call clears two internal words on `stream` and waits for it.
- * Replaces a previous capture of the plan. */
+ * Replaces a previous capture of the plan.  The graph refers to buf_a, buf_b,
+ * lambda_out and dt_dev: they must stay allocated until the plan is destroyed
+ * or captures again. */
 fv_status fv_plan_capture_steps(fv_plan *plan, int32_t steps, double *buf_a, double *buf_b, double h, double gamma,
                                 double cfl, double *lambda_out, double *dt_dev, void *stream);
 

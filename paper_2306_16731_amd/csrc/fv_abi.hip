@@ -164,7 +164,12 @@ struct DeviceContext {
 };
 
 static std::mutex g_ctx_mu;
-static std::vector<DeviceContext *> g_ctx;
+// Per-device contexts live until the process ends: the registry is never destroyed, so
+// no static destructor runs while another thread may still be inside the library.
+static std::vector<DeviceContext *> &contexts() {
+    static auto *v = new std::vector<DeviceContext *>();
+    return *v;
+}
 
 fv_status current_context(DeviceContext **out) {
     int n = 0;
@@ -175,6 +180,7 @@ fv_status current_context(DeviceContext **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(FV_ERR_NO_DEVICE, "hipGetDevice failed");
     std::lock_guard<std::mutex> g(g_ctx_mu);
+    std::vector<DeviceContext *> &g_ctx = contexts();
     if ((int)g_ctx.size() < n) g_ctx.resize(n, nullptr);
     if (!g_ctx[dev]) {
         auto *c = new DeviceContext();

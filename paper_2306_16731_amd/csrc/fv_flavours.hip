@@ -391,11 +391,12 @@ struct Workspace {
     hipEvent_t exec_done = nullptr;  // completion of the task graph of a call
 };
 std::mutex g_ws_mu;
-std::vector<Workspace> g_ws;
 
+// One workspace per device, kept until the process ends (the registry is never destroyed).
 Workspace &workspace(int dev) {
-    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    return g_ws[dev];
+    static auto *ws = new std::vector<Workspace>();
+    if ((int)ws->size() <= dev) ws->resize(dev + 1);
+    return (*ws)[dev];
 }
 
 fv_status ensure(Workspace &w, size_t bytes) {

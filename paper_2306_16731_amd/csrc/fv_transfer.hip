@@ -178,9 +178,11 @@ struct Transfer {
 };
 
 std::mutex g_mu;
-std::vector<Transfer *> g_transfer;
 
+// Per-device transfer state, kept until the process ends (the registry is never destroyed).
 Transfer *transfer_for(int dev) {
+    static auto *all = new std::vector<Transfer *>();
+    std::vector<Transfer *> &g_transfer = *all;
     std::lock_guard<std::mutex> g(g_mu);
     if ((int)g_transfer.size() <= dev) g_transfer.resize(dev + 1, nullptr);
     if (!g_transfer[dev]) g_transfer[dev] = new Transfer();
@@ -524,15 +526,18 @@ struct PinnedBlock {
     double *dev;
 };
 std::mutex g_pin_mu;
-std::map<uintptr_t, PinnedBlock> g_pinned;
+std::map<uintptr_t, PinnedBlock> &pinned_blocks() {  // never destroyed, like the blocks it lists
+    static auto *m = new std::map<uintptr_t, PinnedBlock>();
+    return *m;
+}
 
 // The device address of host range [p, p + bytes) if it lies inside one pinned
 // block, else null.
 const double *pinned_device(const void *p, size_t bytes) {
     const uintptr_t a = reinterpret_cast<uintptr_t>(p);
     std::lock_guard<std::mutex> g(g_pin_mu);
-    auto it = g_pinned.upper_bound(a);
-    if (it == g_pinned.begin()) return nullptr;
+    auto it = pinned_blocks().upper_bound(a);
+    if (it == pinned_blocks().begin()) return nullptr;
     --it;
     if (a + bytes > it->first + it->second.bytes) return nullptr;
     return it->second.dev + (a - it->first) / sizeof(double);
@@ -679,7 +684,7 @@ extern "C" fv_status fv_host_alloc(size_t bytes, void **ptr) {
     }
     {
         std::lock_guard<std::mutex> g(g_pin_mu);
-        g_pinned[reinterpret_cast<uintptr_t>(h)] = PinnedBlock{bytes, static_cast<double *>(d)};
+        pinned_blocks()[reinterpret_cast<uintptr_t>(h)] = PinnedBlock{bytes, static_cast<double *>(d)};
     }
     *ptr = h;
     return FV_OK;
@@ -690,9 +695,9 @@ extern "C" fv_status fv_host_free(void *ptr) {
     if (!ptr) return FV_OK;
     {
         std::lock_guard<std::mutex> g(g_pin_mu);
-        auto it = g_pinned.find(reinterpret_cast<uintptr_t>(ptr));
-        if (it == g_pinned.end()) return fail(FV_ERR_INVALID_ARG, "pointer was not returned by fv_host_alloc");
-        g_pinned.erase(it);
+        auto it = pinned_blocks().find(reinterpret_cast<uintptr_t>(ptr));
+        if (it == pinned_blocks().end()) return fail(FV_ERR_INVALID_ARG, "pointer was not returned by fv_host_alloc");
+        pinned_blocks().erase(it);
     }
     if (hipHostFree(ptr) != hipSuccess) {
         (void)hipGetLastError();
