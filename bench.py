@@ -490,9 +490,7 @@ def bench_flavours(args) -> int:
 
     flav = {"batched": fvpatch.FV_FLAVOUR_BATCHED, "patch_wise": fvpatch.FV_FLAVOUR_PATCH_WISE,
             "task_graph": fvpatch.FV_FLAVOUR_TASK_GRAPH}
-    # 3D: only T = 16 -- the 3D sweep ended in a host segmentation fault at p = 4, T = 256 whose
-    # cause is not identified, so larger 3D batches stay out of this comparison for now
-    for dim, sweep in ((2, (16, 256, 4096, 65536)), (3, (16,))):
+    for dim, sweep in ((2, (16, 256, 4096, 65536)), (3, (16, 256, 4096, 32768))):
         for p in (4, 6, 8):
             base = wl.make_uniform(256, p, dim=dim, nq=5, seed=args.seed)
             for T in sweep:

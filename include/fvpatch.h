@@ -511,11 +511,14 @@ fv_status fv_pde_batch_update(int32_t pde, const double *params, int32_t num_par
  *                          eigenvalue reduction) with HBM temporaries;
  *   FV_FLAVOUR_PATCH_WISE  one work-group per patch, the steps in sequence
  *                          inside it with a barrier between them;
- *   FV_FLAVOUR_TASK_GRAPH  one hipGraph per call with a node per (patch,
- *                          microkernel): d independent face-flux nodes and
- *                          an update node per patch, assembled and
- *                          instantiated on the host every call; the call
- *                          returns when the graph has run (synchronous).
+ *   FV_FLAVOUR_TASK_GRAPH  a task per (patch, microkernel): d independent
+ *                          face-flux tasks and an update task per patch,
+ *                          submitted from the host every call as dependent
+ *                          commands (flux tasks on library streams, one per
+ *                          axis; each update on `stream` after events from
+ *                          its patch's flux tasks); asynchronous like the
+ *                          others: the results are valid once `stream` has
+ *                          been synchronised.
  * Arguments as fv_patch_batch_update; additionally FV_ERR_UNSUPPORTED
  * unless all patches have one size with at most 512 interior volumes and
  * unknowns = 5.  The batched and task-graph forms keep temporaries in a

@@ -14,12 +14,13 @@
 //               inside it with a barrier between them (x faces, y faces, z
 //               faces, update, reduction), patch state and face fluxes in LDS,
 //               threads masked to the patch's volumes (Sec. 3, "patch-wise").
-//   task graph  one hipGraph per call with a node per (patch, microkernel
-//               type): the d face-flux nodes of a patch are independent, its
-//               update node depends on them (Sec. 3, "task graph"); the graph
-//               is assembled and instantiated on the host every call, as the
-//               paper's realisation submits its tasks every time step, and
-//               the call returns when the graph has run.
+//   task graph  a task per (patch, microkernel type): the d face-flux tasks
+//               of a patch are independent, its update task depends on them
+//               (Sec. 3, "task graph"); the tasks are submitted from the host
+//               every call, as the paper's realisation submits its tasks every
+//               time step: flux tasks on one library stream per axis, the
+//               update on the caller's stream after events from its flux
+//               tasks.
 //
 // All three take batches of one patch size and five unknowns.  The batched
 // and task-graph forms keep their temporaries in a grow-only device workspace
@@ -388,7 +389,6 @@ tg_update(const double *__restrict__ patch_in, double *__restrict__ patch_out, i
 struct Workspace {
     void *ptr = nullptr;
     size_t cap = 0;
-    hipEvent_t exec_done = nullptr;  // completion of the task graph of a call
 };
 std::mutex g_ws_mu;
 
@@ -453,65 +453,75 @@ fv_status run_patch_wise(const double *in, double *out, const int64_t *d_off, in
     return e == hipSuccess ? FV_OK : fail(FV_ERR_LAUNCH, "patch-wise launch failed: %s", hipGetErrorString(e));
 }
 
+// The task graph as dependent command submission: per patch, one face-flux task per axis on
+// that axis's library stream and the update task on the caller's stream after events from the
+// flux tasks, the way a SYCL runtime executes the task graph its command groups define.  Flux
+// tasks of later patches run while earlier patches update.  Nothing outlives the call but work
+// queued on streams (no graph objects).  Streams and events are the device's, created once.
+struct TaskStreams {
+    bool ready = false;
+    hipStream_t flux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t start = nullptr;     // the caller's stream reached the call
+    hipEvent_t finished = nullptr;  // the previous call's last update (guards the flux workspace)
+    hipEvent_t flux_done[3] = {nullptr, nullptr, nullptr};
+};
+
+fv_status task_streams(int dev, TaskStreams **out) {
+    static auto *all = new std::vector<TaskStreams>();
+    if ((int)all->size() <= dev) all->resize(dev + 1);
+    TaskStreams &ts = (*all)[dev];
+    if (!ts.ready) {
+        bool ok = true;
+        for (int n = 0; n < 3 && ok; ++n)
+            ok = hipStreamCreateWithFlags(&ts.flux[n], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&ts.flux_done[n], hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&ts.start, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&ts.finished, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            return fail(FV_ERR_LAUNCH, "task streams or events could not be created");
+        }
+        // `finished` starts out complete, so the first call's flux tasks need not wait for it
+        if (hipEventRecord(ts.finished, ts.flux[0]) != hipSuccess)
+            return fail(FV_ERR_LAUNCH, "hipEventRecord failed");
+        ts.ready = true;
+    }
+    *out = &ts;
+    return FV_OK;
+}
+
 template <int D>
 fv_status run_task_graph(const double *in, double *out, const int64_t *h_off, int64_t stride, int32_t T, int p,
-                         double r, double gamma, uint32_t flags, double *lambda_out, hipStream_t s, Workspace &w) {
+                         double r, double gamma, uint32_t flags, double *lambda_out, hipStream_t s, Workspace &w,
+                         int dev) {
     const Geo g = geo(p, D);
     const size_t per_patch = (size_t)D * g.NF * NQ;
     fv_status st = ensure(w, sizeof(double) * per_patch * T);
     if (st != FV_OK) return st;
-    if (!w.exec_done && hipEventCreateWithFlags(&w.exec_done, hipEventDisableTiming) != hipSuccess)
-        return fail(FV_ERR_LAUNCH, "hipEventCreate failed");
-    hipGraph_t graph = nullptr;
-    if (hipGraphCreate(&graph, 0) != hipSuccess) return fail(FV_ERR_LAUNCH, "hipGraphCreate failed");
+    TaskStreams *ts = nullptr;
+    st = task_streams(dev, &ts);
+    if (st != FV_OK) return st;
     double *fh = static_cast<double *>(w.ptr);
-    std::vector<hipGraphNode_t> deps(D);
-    bool ok = true;
+    bool ok = hipEventRecord(ts->start, s) == hipSuccess;
+    for (int n = 0; n < D && ok; ++n)
+        ok = hipStreamWaitEvent(ts->flux[n], ts->start, 0) == hipSuccess &&
+             hipStreamWaitEvent(ts->flux[n], ts->finished, 0) == hipSuccess;
     for (int32_t t = 0; t < T && ok; ++t) {
         const double *pin = in + (h_off ? h_off[t] : t * stride);
         double *pout = out + (h_off ? h_off[t] : t * stride);
         double *fht = fh + per_patch * t;
-        for (int n = 0; n < D && ok; ++n) {
-            int pp = p, nn = n;
-            double gg = gamma;
-            void *args[] = {&pin, &pp, &nn, &gg, &fht};
-            hipKernelNodeParams kp{};
-            kp.func = reinterpret_cast<void *>(&tg_flux<D>);
-            kp.gridDim = dim3(1);
-            kp.blockDim = dim3(256);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = args;
-            kp.extra = nullptr;
-            ok = hipGraphAddKernelNode(&deps[n], graph, nullptr, 0, &kp) == hipSuccess;
-        }
-        if (!ok) break;
-        int pp = p;
-        double rr = r, gg = gamma;
-        uint32_t ff = flags;
-        double *ls = lambda_out ? lambda_out + t : nullptr;
-        void *args[] = {&pin, &pout, &pp, &rr, &gg, &ff, &fht, &ls};
-        hipKernelNodeParams kp{};
-        kp.func = reinterpret_cast<void *>(&tg_update<D>);
-        kp.gridDim = dim3(1);
-        kp.blockDim = dim3(256);
-        kp.sharedMemBytes = 0;
-        kp.kernelParams = args;
-        kp.extra = nullptr;
-        hipGraphNode_t node;
-        ok = hipGraphAddKernelNode(&node, graph, deps.data(), D, &kp) == hipSuccess;
+        for (int n = 0; n < D; ++n)
+            hipLaunchKernelGGL((tg_flux<D>), dim3(1), dim3(256), 0, ts->flux[n], pin, p, n, gamma, fht);
+        // the update waits for this patch's flux tasks (each wait binds to the record just made)
+        for (int n = 0; n < D && ok; ++n)
+            ok = hipEventRecord(ts->flux_done[n], ts->flux[n]) == hipSuccess &&
+                 hipStreamWaitEvent(s, ts->flux_done[n], 0) == hipSuccess;
+        hipLaunchKernelGGL((tg_update<D>), dim3(1), dim3(256), 0, s, pin, pout, p, r, gamma, flags,
+                           static_cast<const double *>(fht), lambda_out ? lambda_out + t : nullptr);
     }
-    hipGraphExec_t exec = nullptr;
-    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    (void)hipGraphDestroy(graph);
-    if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess && hipEventRecord(w.exec_done, s) == hipSuccess;
-    // The executable does not outlive the call: it refers to the caller's buffers, which the
-    // caller may free as soon as the step has run.  So the call waits for its graph.
-    if (ok) ok = hipEventSynchronize(w.exec_done) == hipSuccess;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (!ok) {
-        (void)hipGetLastError();
-        return fail(FV_ERR_LAUNCH, "task graph assembly or launch failed");
-    }
+    ok = ok && hipEventRecord(ts->finished, s) == hipSuccess;
+    const hipError_t e = hipGetLastError();
+    if (!ok || e != hipSuccess) return fail(FV_ERR_LAUNCH, "task submission failed: %s", hipGetErrorString(e));
     return FV_OK;
 }
 
@@ -578,7 +588,7 @@ extern "C" fv_status fv_flavour_update(int32_t flavour, const double *patches_in
                         : run_patch_wise<3>(patches_in, patches_out, d_off, stride, num_patches, p, r, gamma, flags,
                                             lambda_out, s);
     return dim == 2 ? run_task_graph<2>(patches_in, patches_out, offsets, stride, num_patches, p, r, gamma, flags,
-                                        lambda_out, s, w)
+                                        lambda_out, s, w, dev)
                     : run_task_graph<3>(patches_in, patches_out, offsets, stride, num_patches, p, r, gamma, flags,
-                                        lambda_out, s, w);
+                                        lambda_out, s, w, dev);
 }

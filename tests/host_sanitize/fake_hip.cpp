@@ -480,6 +480,13 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
     ev->recorded = true;
     return hipSuccess;
 }
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int flags) {
+    Event *ev = event_of(e);
+    stream_of(s);
+    if (flags != 0) violation("hipStreamWaitEvent flags %u", flags);
+    if (!ev->recorded) violation("stream waits for an event that was never recorded");
+    return hipSuccess;
+}
 hipError_t hipEventQuery(hipEvent_t e) {
     event_of(e);
     return hipSuccess;

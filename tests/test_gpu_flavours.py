@@ -44,6 +44,13 @@ def flavour_step(flavour, data, sizes, offsets, dim, dt, h, periodic, with_lambd
 
 
 FLAVOURS = {"batched": 1, "patch_wise": 2, "task_graph": 3}
+# An earlier realisation of the task graph as a hipGraph (assembled, instantiated, launched and
+# destroyed every call) aborted the host process on the GPU machine right after
+# test_task_graph_twice_in_a_row (SIGABRT from a non-Python thread, no GPU fault), and a benchmark
+# sweep of it ended in a host segmentation fault; no cause was found in its code, so that form was
+# removed.  The task graph is now submitted as dependent commands on streams (no graph objects).
+HIPGRAPH_TASK_GRAPH_OFF = ("tests the removed hipGraph task-graph form, which aborted the host process on "
+                           "the GPU box with no cause shown in its code")
 CASES = [(2, 4), (2, 6), (2, 8), (2, 16), (3, 4), (3, 6), (3, 8)]
 
 
@@ -86,6 +93,7 @@ def test_flavour_gapped_offsets_and_no_reduction(name):
     assert np.all(hp.component_errors(got[~mask], want[~mask], 5) <= TOL)
 
 
+@pytest.mark.skip(reason=HIPGRAPH_TASK_GRAPH_OFF)
 def test_task_graph_twice_in_a_row():
     """The second call waits for the first call's graph before replacing it."""
     from paper_2306_16731_amd import fvpatch
@@ -95,4 +103,34 @@ def test_task_graph_twice_in_a_row():
     s1, _ = oracle.batch_update(b.data, b.sizes, b.offsets, 3, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, False)
     s2, wl2 = oracle.batch_update(s1, b.sizes, b.offsets, 3, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, False)
     assert np.all(hp.component_errors(g2, s2, 5) <= TOL)
+    assert hp.lambda_error(l2, wl2) <= TOL
+
+
+def test_task_submission_calls_in_a_row_buffers_freed():
+    """The dependent-command task graph: three calls queued on one stream with no synchronisation
+    between them (the second reads the first's output), then the first call's buffers freed and a
+    larger batch (the flux workspace grows): every result equals the oracle's chain."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce("task graph: calls in a row")
+    b = wl.make_uniform(9, 4, dim=3, nq=5, seed=62)
+    a = hp.to_dev(b.data)
+    c = a.clone()
+    d = a.clone()
+    lam = torch.full((9,), -1.0, dtype=torch.float64, device="cuda")
+    for src, dst in ((a, c), (c, d), (d, a)):
+        fvpatch.fv_flavour_update(3, src, dst, b.sizes, None, 9, 3, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, 0, lam)
+    torch.cuda.synchronize()
+    got = a.cpu().numpy()
+    s_ = b.data
+    for _ in range(3):
+        s_, wl_ = oracle.batch_update(s_, b.sizes, b.offsets, 3, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, False)
+    assert np.all(hp.component_errors(got, s_, 5) <= TOL)
+    assert hp.lambda_error(lam.cpu().numpy(), wl_) <= TOL
+    del a, c, d
+    torch.cuda.empty_cache()
+    b2 = wl.make_uniform(300, 6, dim=3, nq=5, seed=63)
+    g2, l2 = flavour_step(3, b2.data, b2.sizes, None, 3, 1e-3, wl.H_DEFAULT, True)
+    w2, wl2 = oracle.batch_update(b2.data, b2.sizes, b2.offsets, 3, 5, 1e-3, wl.H_DEFAULT, wl.GAMMA, True)
+    assert np.all(hp.component_errors(g2, w2, 5) <= TOL)
     assert hp.lambda_error(l2, wl2) <= TOL
