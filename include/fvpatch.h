@@ -126,6 +126,37 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
                                 double dt, double h, double gamma, uint32_t flags,
                                 double *lambda_out, void *stream);
 
+/* Most patches one fv_patch_batch_update_noalloc call takes. */
+#define FV_NOALLOC_MAX_PATCHES 262144
+
+/*
+ * fv_patch_batch_update_noalloc -- fv_patch_batch_update for callers that
+ * cannot allocate memory: code that runs between hipGraph captures, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * (bit for bit) and errors as fv_patch_batch_update, plus:
+ *   - num_patches <= FV_NOALLOC_MAX_PATCHES, else FV_ERR_INVALID_ARG before
+ *     any device work;
+ *   - the call never allocates device or pinned memory (no hipMalloc,
+ *     hipHostMalloc or hipFree): patches that are not equal-size and evenly
+ *     spaced take their size-sorted descriptors (12 bytes per patch) through
+ *     a fixed array of 3 MiB in the library's device image (each GPU the
+ *     library runs on holds its own copy until the process ends) and a fixed
+ *     host staging array, copied with one hipMemcpyAsync from pageable
+ *     memory (so a call may wait for the previous call's copy, which follows
+ *     the work queued before it on that stream);
+ *   - every call on one GPU shares that array: calls are serialised on the
+ *     host, and calls on ONE stream are ordered; calls that overlap on two
+ *     streams of one GPU race on the descriptors and give undefined results.
+ * The first call on a device also resolves the array's device address and
+ * creates one event (set-up work, done once per device).  Not capturable
+ * into a hipGraph (the pageable copy).
+ */
+fv_status fv_patch_batch_update_noalloc(const double *patches_in, double *patches_out,
+                                        const int32_t *sizes, const int64_t *offsets,
+                                        int32_t num_patches, int32_t dim, int32_t unknowns,
+                                        double dt, double h, double gamma, uint32_t flags,
+                                        double *lambda_out, void *stream);
+
 /*
  * Launch parameters of the update kernel for one patch class (dim, unknowns,
  * p).  The library picks defaults; the autotuner measures candidates and

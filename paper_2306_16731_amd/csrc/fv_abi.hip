@@ -443,6 +443,79 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
     return st != FV_OK ? st : rs;
 }
 
+// ---------------------------------------------------------------- no-allocation launch
+// Descriptor memory of fv_patch_batch_update_noalloc: (offset, id) per patch, 12 bytes, in
+// a fixed array of the device image.  Each GPU holds its own copy at its own address until
+// the process ends.  In host code `scratch` is only a host-side stand-in: kernels and copies
+// take the device address resolved once per device (NoallocDevice::ptr).
+constexpr size_t kNoallocBytes = (size_t)FV_NOALLOC_MAX_PATCHES * (sizeof(int64_t) + sizeof(int32_t));
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kNoallocDevices = 64;
+struct NoallocDevice {
+    bool ready = false;
+    void *ptr = nullptr;          // this GPU's copy of `scratch`
+    hipEvent_t staged = nullptr;  // recorded after each upload from the host staging array
+};
+// All state below is guarded by g_noalloc_mu: calls are serialised on the host.
+static std::mutex g_noalloc_mu;
+static NoallocDevice g_noalloc_dev[kNoallocDevices];
+static hipEvent_t g_noalloc_last_upload = nullptr;  // the upload that last read the staging array
+alignas(64) static unsigned char g_noalloc_host[kNoallocBytes];
+static std::pair<int64_t, int64_t> g_noalloc_sort[FV_NOALLOC_MAX_PATCHES];
+
+// Set-up on the first call on a device (that device current): the device address of
+// `scratch` and the upload event.
+static fv_status noalloc_device(int device, NoallocDevice **out) {
+    if (device < 0 || device >= kNoallocDevices)
+        return fail(FV_ERR_UNSUPPORTED, "device %d: the no-allocation entry point serves devices 0..%d", device,
+                    kNoallocDevices - 1);
+    NoallocDevice &d = g_noalloc_dev[device];
+    if (!d.ready) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FV_ERR_LAUNCH, "device address of the descriptor array unavailable: %s", hipGetErrorString(e));
+        if (!d.staged && hipEventCreateWithFlags(&d.staged, hipEventDisableTiming) != hipSuccess)
+            return fail(FV_ERR_LAUNCH, "hipEventCreate failed");
+        d.ptr = ptr;
+        d.ready = true;
+    }
+    *out = &d;
+    return FV_OK;
+}
+
+static fv_status noalloc_update(const double *in, double *out, const int32_t *sizes, const int64_t *offsets,
+                                int32_t T, int32_t dim, int32_t nq, double dt, double h, double gamma,
+                                uint32_t flags, double *lambda_out, hipStream_t stream) {
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    BatchShape shape;
+    fv_status st = check_batch(in, out, sizes, offsets, T, dim, nq, lambda_out, &shape, g_noalloc_sort,
+                               FV_NOALLOC_MAX_PATCHES);
+    if (st != FV_OK) return st;
+    DeviceContext *ctx = nullptr;
+    st = current_context(&ctx);
+    if (st != FV_OK) return st;
+    NoallocDevice *nd = nullptr;
+    st = noalloc_device(ctx->device, &nd);
+    if (st != FV_OK) return st;
+    const UpdateLaunch L = launch_template(in, out, dim, nq, dt, h, gamma, flags, lambda_out, nullptr);
+    bool taken = false;
+    st = regular_launch(L, offsets, T, shape, stream, &taken);  // no descriptors at all
+    if (st != FV_OK || taken) return st;
+    // the staging array may still feed the previous upload
+    if (g_noalloc_last_upload && hipEventSynchronize(g_noalloc_last_upload) != hipSuccess)
+        return fail(FV_ERR_LAUNCH, "wait for the previous descriptor upload failed");
+    DescriptorGroups grp;
+    build_descriptors(sizes, offsets, nullptr, T, dim, nq, g_noalloc_host, &grp);
+    if (hipMemcpyAsync(nd->ptr, g_noalloc_host, descriptor_bytes(T, false), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+        return fail(FV_ERR_LAUNCH, "descriptor upload failed");
+    if (hipEventRecord(nd->staged, stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "hipEventRecord failed");
+    g_noalloc_last_upload = nd->staged;
+    return launch_descriptor_groups(L, nd->ptr, grp, stream);
+}
+
 // Unknowns and parameters of a built-in PDE in dim dimensions.
 fv_status pde_shape(int32_t pde, int32_t dim, int32_t *nq, int32_t *nprm) {
     if (dim != 2 && dim != 3) return fail(FV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", dim);
@@ -556,6 +629,22 @@ fv_status fv_patch_batch_update(const double *patches_in, double *patches_out, c
     if (st != FV_OK) return st;
     return plain_update(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, dt, h, gamma, flags,
                         lambda_out, static_cast<hipStream_t>(stream), shape, nullptr);
+}
+
+fv_status fv_patch_batch_update_noalloc(const double *patches_in, double *patches_out, const int32_t *sizes,
+                                        const int64_t *offsets, int32_t num_patches, int32_t dim, int32_t unknowns,
+                                        double dt, double h, double gamma, uint32_t flags, double *lambda_out,
+                                        void *stream) {
+    clear_error();
+    fv_status st = check_scalars(dim, unknowns, dt, h, gamma, flags);
+    if (st != FV_OK) return st;
+    if (num_patches < 0) return fail(FV_ERR_INVALID_ARG, "num_patches must be >= 0");
+    if (num_patches > FV_NOALLOC_MAX_PATCHES)
+        return fail(FV_ERR_INVALID_ARG, "%d patches exceed the %d the no-allocation entry point's descriptor array holds",
+                    num_patches, FV_NOALLOC_MAX_PATCHES);
+    if (num_patches == 0) return FV_OK;
+    return noalloc_update(patches_in, patches_out, sizes, offsets, num_patches, dim, unknowns, dt, h, gamma, flags,
+                          lambda_out, static_cast<hipStream_t>(stream));
 }
 
 fv_status fv_pde_unknowns(int32_t pde, int32_t dim, int32_t *unknowns, int32_t *num_params) {

@@ -32,9 +32,10 @@ FV_ERR_OVERLAP = -7
 FV_HALO_PERIODIC = 0x2
 FV_MAX_P_2D = 64
 FV_MAX_P_3D = 24
+FV_NOALLOC_MAX_PATCHES = 262144
 
 # Every symbol the header declares (checked by the tests against include/fvpatch.h).
-EXPORTS = ["fv_patch_batch_update", "fv_set_tuning", "fv_get_tuning", "fv_plan_create", "fv_plan_execute",
+EXPORTS = ["fv_patch_batch_update", "fv_patch_batch_update_noalloc", "fv_set_tuning", "fv_get_tuning", "fv_plan_create", "fv_plan_execute",
            "fv_plan_capture_steps", "fv_plan_replay", "fv_plan_info", "fv_plan_destroy", "fv_plan_get_tuning",
            "fv_server_create",
            "fv_server_add_mesh", "fv_server_submit", "fv_server_poll", "fv_server_drain", "fv_server_run_trace",
@@ -168,6 +169,8 @@ def load(path: str = LIBRARY):
     vp, i32, i64, f64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
     lib.fv_patch_batch_update.argtypes = [vp, vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp, vp]
     lib.fv_patch_batch_update.restype = ctypes.c_int
+    lib.fv_patch_batch_update_noalloc.argtypes = [vp, vp, vp, vp, i32, i32, i32, f64, f64, f64, u32, vp, vp]
+    lib.fv_patch_batch_update_noalloc.restype = ctypes.c_int
     lib.fv_status_string.argtypes = [ctypes.c_int]
     lib.fv_status_string.restype = ctypes.c_char_p
     lib.fv_last_error.argtypes = []
@@ -297,6 +300,21 @@ def fv_patch_batch_update(patches_in, patches_out, sizes, offsets, num_patches: 
     st = lib.fv_patch_batch_update(_dev_ptr(patches_in), _dev_ptr(patches_out), sz_p, of_p, int(num_patches),
                                    int(dim), int(unknowns), float(dt), float(h), float(gamma), int(flags),
                                    _dev_ptr(lambda_out), _stream_handle(stream))
+    del sz, of
+    return _check(st) if raise_on_error else st
+
+
+def fv_patch_batch_update_noalloc(patches_in, patches_out, sizes, offsets, num_patches: int, dim: int,
+                                  unknowns: int, dt: float, h: float, gamma: float = 1.4, flags: int = 0,
+                                  lambda_out=None, stream=None, raise_on_error: bool = True) -> int:
+    """fv_patch_batch_update without any memory allocation in the library (fixed descriptor
+    array, at most FV_NOALLOC_MAX_PATCHES patches); see include/fvpatch.h."""
+    lib = load()
+    sz, sz_p = _host_array(sizes, np.int32)
+    of, of_p = _host_array(offsets, np.int64)
+    st = lib.fv_patch_batch_update_noalloc(_dev_ptr(patches_in), _dev_ptr(patches_out), sz_p, of_p,
+                                           int(num_patches), int(dim), int(unknowns), float(dt), float(h),
+                                           float(gamma), int(flags), _dev_ptr(lambda_out), _stream_handle(stream))
     del sz, of
     return _check(st) if raise_on_error else st
 

@@ -20,6 +20,9 @@
 
 #include "fvpatch.h"
 
+// calls of the stand-in runtime's allocation and free routines so far (fake_hip.cpp)
+extern "C" long fake_hip_alloc_calls();
+
 namespace {
 
 int g_calls = 0;
@@ -120,6 +123,41 @@ void plain_updates() {
         dev_free(in);
         dev_free(out);
     }
+}
+
+void noalloc_updates() {
+    std::puts("scenario: the no-allocation entry point");
+    for (int round = 0; round < 2; ++round) {
+        for (int dim : {2, 3}) {
+            const std::vector<int> ch = dim == 2 ? std::vector<int>{3, 5, 9, 17, 40} : std::vector<int>{4, 6, 8, 11};
+            // the second round takes smaller batches through the same descriptor array
+            Layout L = scattered(round == 0 ? 900 : 150, ch, dim, 5, 40 + round);
+            const int T = (int)L.sizes.size();
+            double *in = dev_alloc(L.extent), *out = dev_alloc(L.extent), *lam = dev_alloc(T);
+            const long a1 = fake_hip_alloc_calls();
+            for (uint32_t flags : {0u, (uint32_t)FV_HALO_PERIODIC, (uint32_t)FV_HALO_FROM_IN})
+                OK(fv_patch_batch_update_noalloc(in, out, L.sizes.data(), L.offsets.data(), T, dim, 5, 1e-3, 0.02,
+                                                 1.4, flags, round ? lam : nullptr, nullptr));
+            std::vector<int32_t> same(T, ch[0]);
+            OK(fv_patch_batch_update_noalloc(in, out, same.data(), nullptr, T / 2, dim, 5, 1e-3, 0.02, 1.4, 0, lam,
+                                             nullptr));
+            FAILS(fv_patch_batch_update_noalloc(in, in, L.sizes.data(), L.offsets.data(), T, dim, 5, 1e-3, 0.02, 1.4,
+                                                0, nullptr, nullptr),
+                  FV_ERR_OVERLAP);
+            if (fake_hip_alloc_calls() != a1) {
+                std::fprintf(stderr, "fv_patch_batch_update_noalloc allocated or freed memory\n");
+                std::exit(3);
+            }
+            dev_free(in);
+            dev_free(out);
+            dev_free(lam);
+        }
+    }
+    std::vector<int32_t> big(FV_NOALLOC_MAX_PATCHES + 1, 3);
+    FAILS(fv_patch_batch_update_noalloc(reinterpret_cast<double *>(64), reinterpret_cast<double *>(1 << 30),
+                                        big.data(), nullptr, (int)big.size(), 2, 5, 1e-3, 0.02, 1.4, 0, nullptr,
+                                        nullptr),
+          FV_ERR_INVALID_ARG);
 }
 
 void pde_updates() {
@@ -367,6 +405,7 @@ void tuning() {
 int main() {
     std::printf("library %d, build %s\n", fv_version(), fv_build_id());
     plain_updates();
+    noalloc_updates();
     pde_updates();
     plans();
     flavour_matrix();

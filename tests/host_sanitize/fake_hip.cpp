@@ -16,6 +16,7 @@
 // events are objects whose use after destruction the sanitizer sees; every
 // enqueued operation completes at once.  Any violation prints a message and
 // the stack and aborts.
+#include <atomic>
 #include <cxxabi.h>
 #include <hip/hip_runtime_api.h>
 #include <sanitizer/common_interface_defs.h>
@@ -31,6 +32,8 @@
 #include <vector>
 
 namespace {
+
+std::atomic<long> g_alloc_calls{0};
 
 // Every registry is constructed on first use and never destroyed: the library's
 // module constructors register kernels before this file's static objects would
@@ -356,6 +359,7 @@ const char *hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error
 
 // ----------------------------------------------------------------- memory
 static hipError_t fake_alloc(void **ptr, size_t size, Kind kind) {
+    g_alloc_calls.fetch_add(1);
     if (!ptr) return hipErrorInvalidValue;
     void *p = std::aligned_alloc(256, ((size ? size : 1) + 255) / 256 * 256);
     if (!p) return hipErrorOutOfMemory;
@@ -385,9 +389,18 @@ static hipError_t fake_free(void *p, Kind kind) {
     return hipSuccess;
 }
 hipError_t hipMalloc(void **ptr, size_t size) { return fake_alloc(ptr, size, Kind::Device); }
-hipError_t hipFree(void *p) { return fake_free(p, Kind::Device); }
+hipError_t hipFree(void *p) {
+    g_alloc_calls.fetch_add(1);
+    return fake_free(p, Kind::Device);
+}
 hipError_t hipHostMalloc(void **ptr, size_t size, unsigned int) { return fake_alloc(ptr, size, Kind::Host); }
-hipError_t hipHostFree(void *p) { return fake_free(p, Kind::Host); }
+hipError_t hipHostFree(void *p) {
+    g_alloc_calls.fetch_add(1);
+    return fake_free(p, Kind::Host);
+}
+// calls of the allocation and free routines so far (the driver checks that the
+// no-allocation entry point makes none)
+long fake_hip_alloc_calls() { return g_alloc_calls.load(); }
 hipError_t hipHostGetDevicePointer(void **devPtr, void *hstPtr, unsigned int) {
     std::lock_guard<std::recursive_mutex> g(g_mu);
     const auto *a = live_at(reinterpret_cast<uintptr_t>(hstPtr));

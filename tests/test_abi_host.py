@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_header_constants_match_binding():
     hdr = open(os.path.join(ROOT, "include", "fvpatch.h")).read()
-    for name in ["FV_MAX_P_2D", "FV_MAX_P_3D"]:
+    for name in ["FV_MAX_P_2D", "FV_MAX_P_3D", "FV_NOALLOC_MAX_PATCHES"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name)
     for name in ["FV_HALO_PERIODIC", "FV_HALO_FROM_IN", "FV_PLAN_NO_PERSIST", "FV_PLAN_PER_CLASS"]:
         assert int(re.search(rf"#define {name} (0x[0-9a-f]+)u", hdr).group(1), 16) == getattr(F, name), name
@@ -118,7 +118,7 @@ def test_status_strings():
     assert F.fv_version() >= 100
 
 
-@pytest.mark.parametrize("kw,status", [
+INVALID_CALLS = [
     (dict(dim=1), F.FV_ERR_INVALID_ARG),
     (dict(dim=4), F.FV_ERR_INVALID_ARG),
     (dict(unknowns=3), F.FV_ERR_INVALID_ARG),
@@ -148,11 +148,49 @@ def test_status_strings():
     (dict(patches_out=IN + 8 * 100), F.FV_ERR_OVERLAP),      # in and out overlap
     (dict(patches_out=IN), F.FV_ERR_OVERLAP),
     (dict(lambda_out=OUT + 8), F.FV_ERR_OVERLAP),
-])
+]
+
+
+@pytest.mark.parametrize("kw,status", INVALID_CALLS)
 def test_invalid_arguments_rejected_before_device(kw, status):
     st = call(**kw)
     assert st == status, (st, F.fv_last_error())
     assert F.fv_last_error() != ""
+
+
+def call_noalloc(**kw):
+    args = dict(patches_in=IN, patches_out=OUT, sizes=[4] * 3, offsets=None, num_patches=3, dim=2, unknowns=5,
+                dt=1e-3, h=1 / 48, gamma=1.4, flags=0, lambda_out=LAM, stream=0)
+    args.update(kw)
+    return F.fv_patch_batch_update_noalloc(raise_on_error=False, **args)
+
+
+@pytest.mark.parametrize("kw,status", INVALID_CALLS)
+def test_noalloc_rejects_the_same_arguments_before_device(kw, status):
+    st = call_noalloc(**kw)
+    assert st == status, (st, F.fv_last_error())
+    assert F.fv_last_error() != ""
+
+
+def test_noalloc_limits_and_no_device():
+    """More patches than the fixed descriptor array holds is an argument error, raised before
+    anything else is looked at; valid calls reach the device check."""
+    T = F.FV_NOALLOC_MAX_PATCHES + 1
+    assert call_noalloc(num_patches=T, sizes=np.full(T, 4, np.int32)) == F.FV_ERR_INVALID_ARG
+    assert str(F.FV_NOALLOC_MAX_PATCHES) in F.fv_last_error()
+    assert call_noalloc(num_patches=0, sizes=None, patches_in=0, patches_out=0) == F.FV_OK
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    assert call_noalloc() == F.FV_ERR_NO_DEVICE
+    assert call_noalloc(offsets=[360, 0, 180]) == F.FV_ERR_NO_DEVICE
+    T = F.FV_NOALLOC_MAX_PATCHES
+    sizes = np.full(T, 2, np.int32)
+    offs = (np.arange(T, dtype=np.int64)[::-1] * 80).copy()  # unsorted: checked in the fixed sort array
+    assert call_noalloc(num_patches=T, sizes=sizes, offsets=offs) == F.FV_ERR_NO_DEVICE
 
 
 def test_zero_patches_is_a_noop():
