@@ -11,6 +11,7 @@ numpy PCG64(seed): arrival gaps, sizes, classes.
 from __future__ import annotations
 
 import json
+import sys
 import time
 
 import numpy as np
@@ -99,9 +100,12 @@ def bench_main(args) -> int:
     t_build = time.perf_counter() - t_build
     trace = make_trace(rate, seconds, [patches_2d, patches_3d], seed=args.seed)
     res = {}
+    print(f"serving: meshes built in {t_build:.1f} s, trace of {len(trace)} batches over {seconds:.0f} s",
+          file=sys.stderr, flush=True)
     for mode, name in ((fv.FV_SERVE_FUSED, "fused"), (fv.FV_SERVE_PLAIN, "plain")):
         st, log, _ = run(mode, [m2, m3], trace)
         res[name] = (st, log)
+        print(f"serving: {name} replay done ({st['completed']} batches)", file=sys.stderr, flush=True)
     for name, (st, log) in res.items():
         other = "plain" if name == "fused" else "fused"
         overall = latency_summary(log)
