@@ -106,9 +106,11 @@ def main() -> int:
                          "latency: launch-to-done p50/p99 of config 1 (16 patches of 3^2, cache-resident)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
     ap.add_argument("--tuning-table", default=None, help="install this autotuner table instead of tuning now")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="run 4 update launches and one 849,346,560-byte device copy, for rocprofv3 --pmc "
-                         "FETCH_SIZE / WRITE_SIZE runs (the copy's reading is the counters' scale), then exit")
+    ap.add_argument("--traffic-probe", nargs="?", const="c2", choices=["c2", "c3", "c4"], default=None,
+                    help="run 4 launches of one workload's update (c2: the headline plain launch; c3: config 3's "
+                         "fused plan launch, one wave per task; c4: config 4's plain launch, 3D 8^3, not periodic) "
+                         "and one device copy of its state, for rocprofv3 --pmc runs (the copy's reading is the "
+                         "counters' scale), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,6 +145,8 @@ def main() -> int:
     if args.form == "serving":
         from paper_2306_16731_amd import serving
         return serving.bench_main(args)
+    if args.traffic_probe in ("c3", "c4"):
+        return traffic_probe(args)
     dev = torch.device("cuda:0")
     name = "c2_2d_p16_T65536"
     b, spec = wl.build_workload(name, seed=args.seed)
@@ -278,6 +282,42 @@ SETTLE_STEPS = 100  # untimed steps (warmup included) before the headline sample
 SAMPLES = 16        # K-step windows whose median is the headline
 CPU_TARGET_CORE_S = 16.0  # CPU work of the oracle's sample, in core-seconds
 ORACLE_US_PER_PATCH_STEP = 40.0  # one core, one 16 x 16 patch, one step (measured on the host CPUs)
+
+
+def traffic_probe(args) -> int:
+    """--traffic-probe c3 / c4: four launches of the workload's update on its state, then one device copy of
+    the state (bytes known), for rocprofv3 counter runs; prints one JSON line."""
+    import torch
+
+    from paper_2306_16731_amd import fvpatch
+    from paper_2306_16731_amd import workloads as wl
+
+    name = {"c3": "c3_2d_mixed_T200000", "c4": "c4_3d_p8_T32768"}[args.traffic_probe]
+    b, spec = wl.build_workload(name, seed=args.seed)
+    T, dim, nq = b.num_patches, b.dim, b.nq
+    flags = fvpatch.FV_HALO_PERIODIC if spec["periodic"] else 0
+    a = torch.from_numpy(b.data).to("cuda")
+    c = a.clone()
+    lam = torch.empty(T, dtype=torch.float64, device="cuda")
+    h, gamma, dt = wl.H_DEFAULT, wl.GAMMA, 1.0e-4
+    plan = None
+    if args.traffic_probe == "c3":
+        plan = fvpatch.fv_plan_create(b.sizes, b.offsets, T, dim, nq, flags | fvpatch.FV_PLAN_NO_PERSIST)
+    try:
+        for _ in range(4):
+            if plan is not None:
+                fvpatch.fv_plan_execute(plan, a, c, dt, h, gamma, lam)
+            else:
+                fvpatch.fv_patch_batch_update(a, c, b.sizes, b.offsets, T, dim, nq, dt, h, gamma, flags, lam)
+        c.copy_(a)  # plain copy of known size: a.numel() * 8 bytes read and written
+        torch.cuda.synchronize()
+    finally:
+        if plan is not None:
+            fvpatch.fv_plan_destroy(plan)
+    alg = int(sum(alg_bytes_per_patch(int(p), dim, nq, spec["periodic"], True) for p in b.sizes))
+    print(json.dumps({"traffic_probe": args.traffic_probe, "workload": name, "copy_bytes": a.numel() * 8,
+                      "alg_bytes_per_launch": alg, "kernel_sources_sha": kernel_sha()}))
+    return 0
 
 
 def cpu_sample_patches(args, T: int, steps: int) -> int:

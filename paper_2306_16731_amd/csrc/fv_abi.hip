@@ -346,6 +346,7 @@ fv_status regular_launch(const UpdateLaunch &tmpl, const int64_t *offsets, int32
     L.vec2 = (L.stride % 2 == 0) && patch_doubles(shape.uniform_p, dim, nq) % 2 == 0 && aligned16(L.in) &&
              aligned16(L.out);
     tune_launch(L);
+    if (L.pde == kPdeEuler && L.kernel == FV_KERNEL_FIXED && fixed_odd_rows(dim, L.p, nq)) L.vec2 = aligned16(L.out);
     hipError_t e = launch_update(L, stream);
     if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
     return FV_OK;
@@ -404,6 +405,8 @@ fv_status launch_descriptor_groups(const UpdateLaunch &tmpl, const void *dev, co
         L.ids = did + g.start[p];
         L.vec2 = bufs16 && !g.odd[p] && patch_doubles(p, tmpl.dim, tmpl.nq) % 2 == 0;
         tune_launch(L);
+        if (L.pde == kPdeEuler && L.kernel == FV_KERNEL_FIXED && fixed_odd_rows(tmpl.dim, p, tmpl.nq))
+            L.vec2 = aligned16(tmpl.out);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "kernel launch failed (p=%d): %s", p, hipGetErrorString(e));
     }

@@ -42,6 +42,8 @@ struct fv_plan {
     int32_t ring_words = 0;
     int32_t prefetch = 0;
     bool even_offsets = true;  // every wave-task patch starts at an even double and has even rows
+    bool odd_rows_only = true;  // every wave task runs a fixed-size body with odd rows (16-byte bursts need
+                                // only aligned buffers)
     struct Group {
         int32_t p, first, count;
         bool even;  // every patch of the class starts at an even double and spans an even number of them
@@ -90,7 +92,7 @@ fv_status enqueue_step(const fv_plan *pl, const double *in, double *out, double 
         T.nq = pl->nq;
         T.ring_words = pl->ring_words;
         T.prefetch = pl->prefetch;
-        T.vec2 = pl->even_offsets && aligned16(in) && aligned16(out);
+        T.vec2 = (pl->even_offsets || pl->odd_rows_only) && aligned16(in) && aligned16(out);
         T.persistent = pl->persistent;
         T.r = r;
         T.r_dev = r_dev;
@@ -118,6 +120,7 @@ fv_status enqueue_step(const fv_plan *pl, const double *in, double *out, double 
         L.vec2 = g.even && aligned16(in) && aligned16(out);
         apply_tuning(L, pl->tune[g.p]);
         if (L.dim == 2 && L.kernel == FV_KERNEL_WAVE && !wave2d_fits(L.p)) L.kernel = FV_KERNEL_BLOCK;
+        if (L.kernel == FV_KERNEL_FIXED && fixed_odd_rows(L.dim, L.p, L.nq)) L.vec2 = aligned16(out);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "class launch (p=%d) failed: %s", g.p, hipGetErrorString(e));
     }
@@ -243,6 +246,7 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
             if (((p + 2) * unknowns) % 2) pl->even_offsets = false;
             for (int32_t k = start[p]; k < start[p] + count[p]; ++k)
                 if (hoff[k] & 1) pl->even_offsets = false;
+            if (!(fixed && fixed_odd_rows(dim, p, unknowns))) pl->odd_rows_only = false;
         } else {
             bool even = patch_doubles(p, dim, unknowns) % 2 == 0;
             for (int32_t k = start[p]; k < start[p] + count[p] && even; ++k) even = (hoff[k] & 1) == 0;

@@ -169,7 +169,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
     }
     int32_t fill[FV_MAX_P_2D + 2];
     std::memcpy(fill, start, sizeof(fill));
-    bool even = true;
+    bool even = true, odd_rows_only = true;
     for (int32_t k = 0; k < n; ++k) {
         const int32_t t = r.first + k;
         const int32_t j = fill[m.sizes[t]]++;
@@ -201,6 +201,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
                 prefetch = (tu.kernel == FV_KERNEL_WAVE || tu.kernel == FV_KERNEL_FIXED) ? tu.prefetch : 0;
             }
             if (((p + 2) * nq) % 2) even = false;
+            if (!(fixed && fixed_odd_rows(dim, p, nq))) odd_rows_only = false;
         } else {
             classes.push_back(Cls{p, start[p], count[p]});
         }
@@ -228,7 +229,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
         T.nq = nq;
         T.ring_words = ring_words;
         T.prefetch = prefetch;
-        T.vec2 = even && ((reinterpret_cast<uintptr_t>(m.buf) & 15u) == 0);
+        T.vec2 = (even || odd_rows_only) && ((reinterpret_cast<uintptr_t>(m.buf) & 15u) == 0);
         T.persistent = false;
         T.r = r_host;
         T.gamma = s->cfg.gamma;

@@ -320,7 +320,10 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     constexpr int ROWD = W * NQ;
     constexpr int PF = FixedShape<P>::PF;
     constexpr int R = FixedShape<P>::R;
-    static_assert(VEC == 1 || ROWD % 2 == 0, "16-byte bursts need whole 16-byte rows");
+    // VEC = 2: 16-byte burst stores.  Rows of an even number of doubles need every patch at an even
+    // offset; rows of an odd number (odd p + 2 with N = 5) need only a 16-byte aligned output buffer:
+    // each run of whole rows is written as the 16-byte pairs that start at its first even double,
+    // plus its first and last double on their own (whole-row bursts; the others stay 8-byte).
     typedef double dv2 __attribute__((ext_vector_type(2)));
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));  // lane-derived values stay inside the task (see the bursts below)
@@ -432,7 +435,58 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
                 wave_lds_fence();
-                if (kWholeRows) {
+                if constexpr (kWholeRows && VEC == 2 && ROWD % 2 == 1) {
+                    // whole rows of an odd number of doubles: per slot one run of len doubles at a
+                    // parity of its own; pair m starts at double par + 2 m of the run (the pairs a slot
+                    // has fewer of repeat its last one), then the run's first and last double
+                    const int len = nrows * ROWD;
+                    const int per = len / 2;
+                    const int total = ppw * per;
+#pragma unroll
+                    for (int j = 0; j < (total + 63) / 64; ++j) {
+                        const int c = ln + 64 * j < total ? ln + 64 * j : total - 1;
+                        int sl = c / per;
+                        int m = c - sl * per;
+                        sl = item0 + sl < num_items ? sl : 0;
+                        const int64_t base = bases[sl] + (int64_t)k0 * ROWD;
+                        const int par = (int)(base & 1);
+                        m = m < (len - par) / 2 ? m : (len - par) / 2 - 1;
+                        const double *src = ring + sl * R * ROWD + par + 2 * m;
+                        dv2 v;
+                        v.x = src[0];
+                        v.y = src[1];
+                        __builtin_nontemporal_store(v, reinterpret_cast<dv2 *>(out + base + par) + m);
+                    }
+                    constexpr int ends = 2 * ppw;
+#pragma unroll
+                    for (int j = 0; j < (ends + 63) / 64; ++j) {
+                        const int c = ln + 64 * j < ends ? ln + 64 * j : ends - 1;
+                        int sl = c >> 1;
+                        const int e = (c & 1) ? len - 1 : 0;
+                        sl = item0 + sl < num_items ? sl : 0;
+                        __builtin_nontemporal_store(ring[sl * R * ROWD + e], out + bases[sl] + (int64_t)k0 * ROWD + e);
+                    }
+                    // y-halo rows: row P+1 takes row 1, row 0 takes row P (interior columns)
+                    if (PERIODIC && (k0 == 1 || kk == P)) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (h == 0 ? k0 != 1 : kk != P) continue;
+                            const int from = h == 0 ? 0 : rr;
+                            const int dest = h == 0 ? P + 1 : 0;
+                            constexpr int iper = P * NQ;
+                            constexpr int itotal = ppw * iper;
+#pragma unroll
+                            for (int jj = 0; jj < (itotal + 63) / 64; ++jj) {
+                                const int c = ln + 64 * jj < itotal ? ln + 64 * jj : itotal - 1;
+                                int sl = c / iper;
+                                const int d = c - sl * iper;
+                                sl = item0 + sl < num_items ? sl : 0;
+                                __builtin_nontemporal_store(ring[(sl * R + from) * ROWD + NQ + d],
+                                                            out + bases[sl] + (int64_t)dest * ROWD + NQ + d);
+                            }
+                        }
+                    }
+                } else if (kWholeRows) {
                     // whole rows (x-halo volumes hold their wrapped copies, or their input values)
                     const int per = nrows * ROWD / VEC;
                     const int total = ppw * per;
@@ -534,11 +588,11 @@ __device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in,
         return false;
     } else {
         switch (p) {
-            case 3: fixed_task_body<3, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 5: fixed_task_body<5, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 9: fixed_task_body<9, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 3: fixed_task_body<3, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 5: fixed_task_body<5, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 9: fixed_task_body<9, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
             case 16: fixed_task_body<16, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 17: fixed_task_body<17, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 17: fixed_task_body<17, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
         }
         return false;
     }
@@ -801,11 +855,11 @@ int wave2d_fixed_ring_words(int p) {
 hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream) {
     if (L.nq != 5) return hipErrorInvalidValue;
     switch (L.p) {
-        case 3: return fixed_periodic<3, 1>(L, stream);
-        case 5: return fixed_periodic<5, 1>(L, stream);
-        case 9: return fixed_periodic<9, 1>(L, stream);
+        case 3: return L.vec2 ? fixed_periodic<3, 2>(L, stream) : fixed_periodic<3, 1>(L, stream);
+        case 5: return L.vec2 ? fixed_periodic<5, 2>(L, stream) : fixed_periodic<5, 1>(L, stream);
+        case 9: return L.vec2 ? fixed_periodic<9, 2>(L, stream) : fixed_periodic<9, 1>(L, stream);
         case 16: return L.vec2 ? fixed_periodic<16, 2>(L, stream) : fixed_periodic<16, 1>(L, stream);
-        case 17: return fixed_periodic<17, 1>(L, stream);
+        case 17: return L.vec2 ? fixed_periodic<17, 2>(L, stream) : fixed_periodic<17, 1>(L, stream);
     }
     return hipErrorInvalidValue;
 }
