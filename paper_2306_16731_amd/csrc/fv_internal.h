@@ -113,8 +113,9 @@ hipError_t launch_update2d_tasks(const TaskLaunch &T, hipStream_t stream);
 // Fixed-size form of the same kernel (compile-time patch size; N = 5 and
 // p in {3, 5, 9, 16, 17}).
 bool wave2d_fixed(int p, int nq);
-// The 2D fixed-size kernel for p with rows of an odd number of doubles: its 16-byte burst form
-// (vec2) needs only a 16-byte aligned output buffer, whatever the patches' offsets.
+// The 2D fixed-size kernel for p with rows of an odd number of doubles: its vec2 form needs only a
+// 16-byte aligned output buffer, whatever the patches' offsets (p = 17 writes whole rows in 16-byte
+// pairs; p = 3, 5, 9 ignore vec2).
 inline bool fixed_odd_rows(int dim, int p, int nq) { return dim == 2 && wave2d_fixed(p, nq) && ((p + 2) * nq) % 2 == 1; }
 int wave2d_fixed_ring_words(int p);
 void wave2d_fixed_shape(int p, int *prefetch, int *rows);

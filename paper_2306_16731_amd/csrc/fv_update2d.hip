@@ -323,7 +323,9 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     // VEC = 2: 16-byte burst stores.  Rows of an even number of doubles need every patch at an even
     // offset; rows of an odd number (odd p + 2 with N = 5) need only a 16-byte aligned output buffer:
     // each run of whole rows is written as the 16-byte pairs that start at its first even double,
-    // plus its first and last double on their own (whole-row bursts; the others stay 8-byte).
+    // plus its first and last double on their own.  The fixed sizes use that form for p = 17 only
+    // (runs of 12 rows of 95 doubles): for the shorter runs of p = 3 and 5 the separate ends cost more
+    // than the wider stores save, at p = 9 it is even, and interior-only runs stay in 8-byte chunks.
     typedef double dv2 __attribute__((ext_vector_type(2)));
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));  // lane-derived values stay inside the task (see the bursts below)
@@ -588,9 +590,9 @@ __device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in,
         return false;
     } else {
         switch (p) {
-            case 3: fixed_task_body<3, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 5: fixed_task_body<5, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 9: fixed_task_body<9, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 3: fixed_task_body<3, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 5: fixed_task_body<5, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+            case 9: fixed_task_body<9, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
             case 16: fixed_task_body<16, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
             case 17: fixed_task_body<17, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
         }
@@ -855,9 +857,9 @@ int wave2d_fixed_ring_words(int p) {
 hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream) {
     if (L.nq != 5) return hipErrorInvalidValue;
     switch (L.p) {
-        case 3: return L.vec2 ? fixed_periodic<3, 2>(L, stream) : fixed_periodic<3, 1>(L, stream);
-        case 5: return L.vec2 ? fixed_periodic<5, 2>(L, stream) : fixed_periodic<5, 1>(L, stream);
-        case 9: return L.vec2 ? fixed_periodic<9, 2>(L, stream) : fixed_periodic<9, 1>(L, stream);
+        case 3: return fixed_periodic<3, 1>(L, stream);
+        case 5: return fixed_periodic<5, 1>(L, stream);
+        case 9: return fixed_periodic<9, 1>(L, stream);
         case 16: return L.vec2 ? fixed_periodic<16, 2>(L, stream) : fixed_periodic<16, 1>(L, stream);
         case 17: return L.vec2 ? fixed_periodic<17, 2>(L, stream) : fixed_periodic<17, 1>(L, stream);
     }
