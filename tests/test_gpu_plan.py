@@ -273,23 +273,29 @@ def test_plan_3d():
     check_against_oracle(b, dts, False, got, lams)
 
 
-@pytest.mark.parametrize("name,T,periodic,per_class", [("c3_2d_mixed_T200000", 2500, False, False),
-                                                       ("c3_2d_mixed_T200000", 2500, True, True),
-                                                       ("c4_3d_p8_T32768", 200, False, False),
-                                                       ("c2_2d_p16_T65536", 600, True, False)])
-def test_graph_replay_with_device_dt(name, T, periodic, per_class):
+@pytest.mark.parametrize("name,T,periodic,per_class,from_in", [("c3_2d_mixed_T200000", 2500, False, False, False),
+                                                               ("c3_2d_mixed_T200000", 2500, True, True, False),
+                                                               ("c3_2d_mixed_T200000", 2500, False, False, True),
+                                                               ("c4_3d_p8_T32768", 200, False, False, False),
+                                                               ("c4_3d_p8_T32768", 200, False, False, True),
+                                                               ("c2_2d_p16_T65536", 600, True, False, False)])
+def test_graph_replay_with_device_dt(name, T, periodic, per_class, from_in):
     """k steps captured in one graph; step sizes formed on the device from each step's
     eigenvalues.  Replayed twice with eager work and synchronisations in between;
     every replay is checked against the oracle run with the device's step sizes,
-    and those step sizes against the ones the oracle's own eigenvalues give."""
+    and those step sizes against the ones the oracle's own eigenvalues give.  With
+    FV_HALO_FROM_IN the output halos take the input's values, which here are the initial
+    halos in both buffers, so the whole state still equals the oracle's."""
     import torch
     from paper_2306_16731_amd import fvpatch
-    _announce(f"graph: {name} T={T}, periodic={periodic}, per_class={per_class}, 5 steps x 2 replays")
+    _announce(f"graph: {name} T={T}, periodic={periodic}, per_class={per_class}, from_in={from_in}, "
+              "5 steps x 2 replays")
     b, _ = wl.build_workload(name, seed=23, num_patches=T)
     steps = 5
     plan = fvpatch.fv_plan_create(b.sizes, b.offsets, b.num_patches, b.dim, b.nq,
                                   (fvpatch.FV_HALO_PERIODIC if periodic else 0) |
-                                  (fvpatch.FV_PLAN_PER_CLASS if per_class else 0))
+                                  (fvpatch.FV_PLAN_PER_CLASS if per_class else 0) |
+                                  (fvpatch.FV_HALO_FROM_IN if from_in else 0))
     try:
         bufa = hp.to_dev(b.data)
         bufb = bufa.clone()
