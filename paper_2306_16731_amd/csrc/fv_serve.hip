@@ -14,8 +14,8 @@
 // arrival-to-completion latency.
 //
 // Two launch modes: FV_SERVE_FUSED builds the batch's task list (one wave per
-// task, tasks in memory order) in pinned staging memory and runs the whole
-// batch in one fused launch; FV_SERVE_PLAIN runs each batch through the plain per-batch
+// task, tasks in memory order) in pinned staging memory, which the kernel reads
+// in place, and runs the whole batch in one fused launch; FV_SERVE_PLAIN runs each batch through the plain per-batch
 // path (validation, grouping by size, one launch per size class).
 //
 // Meshes of different dimensions (a 2D mesh of mixed patch sizes next to a 3D
@@ -75,10 +75,11 @@ struct Injection {
     int32_t times = 0;  // FV_INJECT_FAIL: completion checks still to report a failure
 };
 
-// Pinned + device staging of one in-flight batch (recycled, never freed while the server lives).
+// Pinned staging of one in-flight batch's descriptors, which its kernels read in place over the
+// bus (no copy to device memory first), and its lambda (recycled, never freed while the server lives).
 struct Staging {
     void *host = nullptr;
-    void *dev = nullptr;
+    void *host_dev = nullptr;  // the device's address of `host`
     size_t cap = 0;
     double *lambda = nullptr;  // device [cap_patches]
     int32_t cap_patches = 0;
@@ -122,7 +123,8 @@ namespace fv {
 namespace {
 
 int64_t batch_bytes(const Request &r) {
-    // descriptors (in and out offsets, ids, tasks) + lambda of the batch
+    // the batch's working set, counted against the budget: its descriptors (in and out offsets, ids,
+    // tasks; in pinned staging) and its lambda
     return (int64_t)r.count * (8 + 8 + 4 + 16 + 8);
 }
 
@@ -131,17 +133,18 @@ fv_status ensure_staging(fv_server *s, Staging &st, int32_t count) {
     if (st.cap >= need && st.cap_patches >= count) return FV_OK;
     if (st.busy) return fail(FV_ERR_LAUNCH, "staging buffer in use");
     if (st.host) (void)hipHostFree(st.host);
-    if (st.dev) (void)hipFree(st.dev);
     if (st.lambda) (void)hipFree(st.lambda);
-    st.host = st.dev = nullptr;
+    st.host = st.host_dev = nullptr;
     st.lambda = nullptr;
     st.cap = 0;
     st.cap_patches = 0;
     const int32_t cp = std::max<int32_t>(count, 4096);
     const size_t cap = (size_t)cp * (8 + 8 + 4 + sizeof(WaveTask)) + 16;  // + padding before the task list
-    if (hipHostMalloc(&st.host, cap, hipHostMallocDefault) != hipSuccess || hipMalloc(&st.dev, cap) != hipSuccess ||
+    if (hipHostMalloc(&st.host, cap, hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&st.lambda, sizeof(double) * cp) != hipSuccess)
         return fail(FV_ERR_OOM, "staging allocation failed");
+    if (hipHostGetDevicePointer(&st.host_dev, st.host, 0) != hipSuccess || !st.host_dev)
+        return fail(FV_ERR_LAUNCH, "no device address for the pinned staging");
     st.cap = cap;
     st.cap_patches = cp;
     (void)s;
@@ -209,10 +212,8 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
     // one wave per task: tasks in memory order keep the resident waves on neighbouring patches
     std::stable_sort(htask, htask + ntask,
                      [&](const WaveTask &a, const WaveTask &b) { return hin[a.first] < hin[b.first]; });
-    const size_t bytes = (size_t)(reinterpret_cast<char *>(htask + ntask) - static_cast<char *>(st.host));
-    if (hipMemcpyAsync(st.dev, st.host, bytes, hipMemcpyHostToDevice, s->stream) != hipSuccess)
-        return fail(FV_ERR_LAUNCH, "descriptor upload failed");
-    const int64_t *din = static_cast<const int64_t *>(st.dev);
+    // the kernels read the descriptors in place: the staging stays untouched until the batch retires
+    const int64_t *din = static_cast<const int64_t *>(st.host_dev);
     const int64_t *dout = din + n;
     const int32_t *did = reinterpret_cast<const int32_t *>(dout + n);
     const WaveTask *dtask = reinterpret_cast<const WaveTask *>(did + n + (n & 1));
@@ -699,7 +700,6 @@ fv_status fv_server_destroy(fv_server *s) {
     for (auto e : s->spare_events) (void)hipEventDestroy(e);
     for (auto &st : s->staging) {
         if (st.host) (void)hipHostFree(st.host);
-        if (st.dev) (void)hipFree(st.dev);
         if (st.lambda) (void)hipFree(st.lambda);
     }
     for (auto &m : s->meshes)
