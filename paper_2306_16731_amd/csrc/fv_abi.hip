@@ -146,8 +146,8 @@ fv_status check_batch(const double *in, const double *out, const int32_t *sizes,
 
 // ---------------------------------------------------------------- device context
 struct DescSlot {
-    void *host = nullptr;    // pinned staging
-    void *dev = nullptr;     // device copy
+    void *host = nullptr;    // pinned staging, which the kernels read in place
+    void *dev = nullptr;     // the device's address of `host`
     size_t cap = 0;
     hipEvent_t done = nullptr;
     bool used = false;
@@ -209,12 +209,12 @@ fv_status acquire_slot(DeviceContext *c, size_t bytes, DescSlot **out) {
         return fail(FV_ERR_LAUNCH, "hipEventCreate failed");
     if (s.cap < bytes) {
         if (s.host) (void)hipHostFree(s.host);
-        if (s.dev) (void)hipFree(s.dev);
         s.host = s.dev = nullptr;
         s.cap = 0;
         size_t cap = std::max<size_t>(bytes, 1 << 16);
         if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) return fail(FV_ERR_OOM, "pinned allocation of %zu bytes failed", cap);
-        if (hipMalloc(&s.dev, cap) != hipSuccess) return fail(FV_ERR_OOM, "device allocation of %zu bytes failed", cap);
+        if (hipHostGetDevicePointer(&s.dev, s.host, 0) != hipSuccess || !s.dev)
+            return fail(FV_ERR_LAUNCH, "no device address for the pinned descriptor staging");
         s.cap = cap;
     }
     *out = &s;
@@ -430,17 +430,14 @@ fv_status plain_update(const double *in, double *out, const int32_t *sizes, cons
         st = regular_launch(L, offsets, T, shape, stream, &taken);
         if (st != FV_OK || taken) return st;
     }
-    // Group the patches by size (counting sort), upload (offset, id) lists.
+    // Group the patches by size (counting sort) into (offset, id) lists in a pinned slot, which the
+    // kernels read in place (the slot is reused only after the launches that read it have run).
     const size_t bytes = descriptor_bytes(T, out_offsets != nullptr);
     DescSlot *slot = nullptr;
     st = acquire_slot(ctx, bytes, &slot);
     if (st != FV_OK) return st;
     DescriptorGroups g;
     build_descriptors(sizes, offsets, out_offsets, T, dim, nq, slot->host, &g);
-    if (hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
-        (void)release_slot(slot, stream);
-        return fail(FV_ERR_LAUNCH, "descriptor upload failed");
-    }
     st = launch_descriptor_groups(L, slot->dev, g, stream);
     const fv_status rs = release_slot(slot, stream);
     return st != FV_OK ? st : rs;
