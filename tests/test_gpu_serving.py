@@ -262,3 +262,29 @@ def test_deadline_ends_a_wait_for_a_batch_that_never_finishes():
     finally:
         fv.fv_server_destroy(srv)
     assert np.all(hp.component_errors(got, oracle_replay(mesh, seq), 5) <= TOL)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fused", "plain"])
+def test_checkpoint_and_resume_in_a_new_server(mode):
+    """Checkpoint / resume: a server replays the first half of a mixed 2D / 3D trace, its meshes are
+    read back to the host and registered in a NEW server, which replays the second half.  The end state
+    equals, bit for bit, one server replaying the whole trace, and the oracle to 1e-12."""
+    from paper_2306_16731_amd import serving
+    _announce(f"checkpoint / resume, mode={mode}")
+    m2 = wl.make_mixed(240, (3, 5, 9, 17), dim=2, nq=5, seed=62)
+    m3 = wl.make_uniform(40, 8, dim=3, nq=5, seed=63)
+    trace = serving.make_trace(600.0, 0.2, [240, 40], weights=(4, 1), max_batch=64, dt=(7e-4, 5e-4), seed=64)
+    k = len(trace) // 2
+    _, _, whole = serving.run(mode, [m2, m3], trace, budget=1 << 30, max_inflight=4, read_back=True)
+    _, _, (s2, s3) = serving.run(mode, [m2, m3], trace[:k], budget=1 << 30, max_inflight=4, read_back=True)
+    snap2 = wl.Batch(s2, m2.sizes, m2.offsets, m2.dim, m2.nq)
+    snap3 = wl.Batch(s3, m3.sizes, m3.offsets, m3.dim, m3.nq)
+    rest = trace[k:].copy()
+    rest["arrival_ns"] -= rest["arrival_ns"][0]
+    _, log, resumed = serving.run(mode, [snap2, snap3], rest, budget=1 << 30, max_inflight=4, read_back=True)
+    assert len(log) == len(rest)
+    for a, b in zip(whole, resumed):
+        assert np.array_equal(a, b)
+    for mesh_id, mesh, got in ((0, m2, resumed[0]), (1, m3, resumed[1])):
+        seq = [(int(r["first"]), int(r["count"]), float(r["dt"])) for r in trace if r["mesh"] == mesh_id]
+        assert np.all(hp.component_errors(got, oracle_replay(mesh, seq), 5) <= TOL), mesh_id
