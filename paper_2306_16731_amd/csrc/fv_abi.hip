@@ -146,6 +146,7 @@ fv_status check_batch(const double *in, const double *out, const int32_t *sizes,
 
 // ---------------------------------------------------------------- device context
 struct DescSlot {
+    std::mutex busy;         // held by the call that fills the slot, from acquire_slot to release_slot
     void *host = nullptr;    // pinned staging, which the kernels read in place
     void *dev = nullptr;     // the device's address of `host`
     size_t cap = 0;
@@ -201,9 +202,16 @@ fv_status current_context(DeviceContext **out) {
 // Take a descriptor slot with at least `bytes` of pinned and device memory,
 // waiting for the last launch that used it.
 fv_status acquire_slot(DeviceContext *c, size_t bytes, DescSlot **out) {
-    std::lock_guard<std::mutex> g(c->mu);
-    DescSlot &s = c->slots[c->next];
-    c->next = (c->next + 1) % DeviceContext::kSlots;
+    DescSlot *sp = nullptr;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        sp = &c->slots[c->next];
+        c->next = (c->next + 1) % DeviceContext::kSlots;
+    }
+    DescSlot &s = *sp;
+    // With more concurrent callers than slots, a call on another thread may still be filling this
+    // slot: wait for it to release the slot, then for the launches that read it.
+    std::unique_lock<std::mutex> hold(s.busy);
     if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(FV_ERR_LAUNCH, "descriptor event wait failed");
     if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return fail(FV_ERR_LAUNCH, "hipEventCreate failed");
@@ -211,20 +219,29 @@ fv_status acquire_slot(DeviceContext *c, size_t bytes, DescSlot **out) {
         if (s.host) (void)hipHostFree(s.host);
         s.host = s.dev = nullptr;
         s.cap = 0;
+        s.used = false;
         size_t cap = std::max<size_t>(bytes, 1 << 16);
         if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) return fail(FV_ERR_OOM, "pinned allocation of %zu bytes failed", cap);
         if (hipHostGetDevicePointer(&s.dev, s.host, 0) != hipSuccess || !s.dev)
             return fail(FV_ERR_LAUNCH, "no device address for the pinned descriptor staging");
         s.cap = cap;
     }
+    hold.release();  // unlocked by release_slot
     *out = &s;
     return FV_OK;
 }
 
+// Marks the slot's contents as read by the work enqueued on `stream` so far and hands it back.
 fv_status release_slot(DescSlot *s, hipStream_t stream) {
-    if (hipEventRecord(s->done, stream) != hipSuccess) return fail(FV_ERR_LAUNCH, "hipEventRecord failed");
-    s->used = true;
-    return FV_OK;
+    const hipError_t e = hipEventRecord(s->done, stream);
+    if (e == hipSuccess) {
+        s->used = true;
+    } else {
+        (void)hipStreamSynchronize(stream);  // no event to wait on later: let the readers finish now
+        s->used = false;
+    }
+    s->busy.unlock();
+    return e == hipSuccess ? FV_OK : fail(FV_ERR_LAUNCH, "hipEventRecord failed");
 }
 
 // ---------------------------------------------------------------- tuning table

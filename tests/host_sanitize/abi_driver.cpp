@@ -12,20 +12,24 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <random>
+#include <thread>
 #include <vector>
 
 #include "fvpatch.h"
 
 // calls of the stand-in runtime's allocation and free routines so far (fake_hip.cpp)
 extern "C" long fake_hip_alloc_calls();
+// a pause the stand-in runtime takes at the start of every kernel launch (fake_hip.cpp)
+extern "C" void fake_hip_set_launch_sleep_us(int us);
 
 namespace {
 
-int g_calls = 0;
+std::atomic<int> g_calls{0};
 
 void expect(fv_status got, fv_status want, const char *what, int line) {
     ++g_calls;
@@ -158,6 +162,34 @@ void noalloc_updates() {
                                         big.data(), nullptr, (int)big.size(), 2, 5, 1e-3, 0.02, 1.4, 0, nullptr,
                                         nullptr),
           FV_ERR_INVALID_ARG);
+}
+
+// Calls from more threads than the library keeps descriptor slots, each on its own buffers, with
+// batches that grow so that slots are reallocated while other threads' calls are under way.
+void concurrent_updates() {
+    std::puts("scenario: calls from 12 threads at once");
+    fake_hip_set_launch_sleep_us(200);  // each call holds its descriptor slot across a slow launch
+    std::vector<std::thread> pool;
+    for (int w = 0; w < 12; ++w) {
+        pool.emplace_back([w] {
+            for (int k = 0; k < 10; ++k) {
+                // up to 12,000 patches: (offset, id) lists beyond the slots' first 64 KiB
+                Layout L = scattered(300 + 1300 * ((w + k) % 10), {3, 5}, 2, 5, 1000u * w + k);
+                const int T = (int)L.sizes.size();
+                double *in = dev_alloc(L.extent), *out = dev_alloc(L.extent), *lam = dev_alloc(T);
+                OK(fv_patch_batch_update(in, out, L.sizes.data(), L.offsets.data(), T, 2, 5, 1e-3, 0.02, 1.4,
+                                         (uint32_t)(k % 3 == 0 ? FV_HALO_PERIODIC : 0), lam, nullptr));
+                if (k % 3 == 1)
+                    OK(fv_patch_batch_update_noalloc(in, out, L.sizes.data(), L.offsets.data(), T, 2, 5, 1e-3, 0.02,
+                                                     1.4, 0, lam, nullptr));
+                dev_free(in);
+                dev_free(out);
+                dev_free(lam);
+            }
+        });
+    }
+    for (auto &t : pool) t.join();
+    fake_hip_set_launch_sleep_us(0);
 }
 
 void pde_updates() {
@@ -406,6 +438,7 @@ int main() {
     std::printf("library %d, build %s\n", fv_version(), fv_build_id());
     plain_updates();
     noalloc_updates();
+    concurrent_updates();
     pde_updates();
     plans();
     flavour_matrix();
@@ -413,6 +446,6 @@ int main() {
     meshes();
     transfers();
     tuning();
-    std::printf("ok: %d checked calls\n", g_calls);
+    std::printf("ok: %d checked calls\n", g_calls.load());
     return 0;
 }

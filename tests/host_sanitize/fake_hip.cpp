@@ -22,6 +22,7 @@
 #include <sanitizer/common_interface_defs.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -29,11 +30,13 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace {
 
 std::atomic<long> g_alloc_calls{0};
+std::atomic<int> g_launch_sleep_us{0};  // a pause at the start of every launch (widens race windows)
 
 // Every registry is constructed on first use and never destroyed: the library's
 // module constructors register kernels before this file's static objects would
@@ -285,6 +288,7 @@ hipError_t __hipPopCallConfiguration(dim3 *gridDim, dim3 *blockDim, size_t *shar
 }
 
 hipError_t hipLaunchKernel(const void *f, dim3 grid, dim3 block, void **args, size_t shmem, hipStream_t stream) {
+    if (const int us = g_launch_sleep_us.load()) std::this_thread::sleep_for(std::chrono::microseconds(us));
     std::lock_guard<std::recursive_mutex> g(g_mu);
     const KernelInfo &k = kernel(f);
     check_config(k, grid, block, shmem);
@@ -401,6 +405,7 @@ hipError_t hipHostFree(void *p) {
 // calls of the allocation and free routines so far (the driver checks that the
 // no-allocation entry point makes none)
 long fake_hip_alloc_calls() { return g_alloc_calls.load(); }
+void fake_hip_set_launch_sleep_us(int us) { g_launch_sleep_us.store(us); }
 hipError_t hipHostGetDevicePointer(void **devPtr, void *hstPtr, unsigned int) {
     std::lock_guard<std::recursive_mutex> g(g_mu);
     const auto *a = live_at(reinterpret_cast<uintptr_t>(hstPtr));
