@@ -93,6 +93,8 @@ typedef enum fv_status {
 /* Largest interior size per axis this build accepts, per dimension. */
 #define FV_MAX_P_2D 64
 #define FV_MAX_P_3D 24
+/* Every patch lies below this offset (in doubles). */
+#define FV_MAX_OFFSET (1LL << 48)
 
 /*
  * fv_patch_batch_update -- one explicit Euler step over a batch of patches
@@ -104,8 +106,11 @@ typedef enum fv_status {
  *                patches_in over the batch's extent (FV_ERR_OVERLAP).
  *   sizes        host [num_patches]: interior volumes per axis p_t,
  *                1 <= p_t <= FV_MAX_P_2D (2D) / FV_MAX_P_3D (3D).
- *   offsets      host [num_patches]: start of patch t in doubles (>= 0); the
- *                patches' ranges must not overlap (FV_ERR_OVERLAP).  NULL
+ *   offsets      host [num_patches]: start of patch t in doubles; every
+ *                patch lies in [0, FV_MAX_OFFSET) (2^48 doubles, far beyond
+ *                any device's memory; the bound keeps address arithmetic
+ *                from wrapping); the patches' ranges must not overlap
+ *                (FV_ERR_OVERLAP).  NULL
  *                means contiguous patches, offsets[t] = t (p+2)^d N, and then
  *                every sizes[t] must be equal.
  *   num_patches  T >= 0; T == 0 is a no-op that returns FV_OK.

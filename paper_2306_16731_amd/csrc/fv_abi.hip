@@ -89,8 +89,9 @@ fv_status check_layout(const int32_t *sizes, const int64_t *offsets, int32_t num
         int64_t prev_end = -1;
         for (int32_t t = 0; t < num_patches; ++t) {
             const int64_t o = offsets[t];
-            if (o < 0) return fail(FV_ERR_INVALID_ARG, "offsets[%d]=%lld is negative", t, (long long)o);
-            const int64_t e = o + patch_doubles(sizes[t], dim, nq);
+            const int64_t e = o + patch_doubles(sizes[t], dim, nq);  // no overflow: o < 2^48 is checked first
+            if (o < 0 || o >= FV_MAX_OFFSET || e > FV_MAX_OFFSET)
+                return fail(FV_ERR_INVALID_ARG, "patch %d at offset %lld does not lie in [0, 2^48)", t, (long long)o);
             lo = std::min(lo, o);
             hi = std::max(hi, e);
             if (o < prev_end) sorted = false;

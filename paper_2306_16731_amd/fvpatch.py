@@ -32,6 +32,7 @@ FV_ERR_OVERLAP = -7
 FV_HALO_PERIODIC = 0x2
 FV_MAX_P_2D = 64
 FV_MAX_P_3D = 24
+FV_MAX_OFFSET = 1 << 48
 FV_NOALLOC_MAX_PATCHES = 262144
 
 # Every symbol the header declares (checked by the tests against include/fvpatch.h).

@@ -46,6 +46,7 @@ def test_header_constants_match_binding():
     hdr = open(os.path.join(ROOT, "include", "fvpatch.h")).read()
     for name in ["FV_MAX_P_2D", "FV_MAX_P_3D", "FV_NOALLOC_MAX_PATCHES"]:
         assert int(re.search(rf"#define {name} (\d+)", hdr).group(1)) == getattr(F, name)
+    assert 1 << int(re.search(r"#define FV_MAX_OFFSET \(1LL << (\d+)\)", hdr).group(1)) == F.FV_MAX_OFFSET
     for name in ["FV_HALO_PERIODIC", "FV_HALO_FROM_IN", "FV_PLAN_NO_PERSIST", "FV_PLAN_PER_CLASS"]:
         assert int(re.search(rf"#define {name} (0x[0-9a-f]+)u", hdr).group(1), 16) == getattr(F, name), name
     for name in ["FV_KERNEL_AUTO", "FV_KERNEL_BLOCK", "FV_KERNEL_WAVE", "FV_KERNEL_TILE", "FV_KERNEL_FIXED"]:
@@ -143,6 +144,8 @@ INVALID_CALLS = [
     (dict(dim=3, sizes=[25, 4, 4]), F.FV_ERR_INVALID_ARG),
     (dict(sizes=[4, 5, 4]), F.FV_ERR_INVALID_ARG),           # offsets NULL needs equal sizes
     (dict(offsets=[0, -5, 200]), F.FV_ERR_INVALID_ARG),
+    (dict(offsets=[0, 1 << 62, 200]), F.FV_ERR_INVALID_ARG),   # beyond FV_MAX_OFFSET
+    (dict(offsets=[0, (1 << 48) - 100, 200]), F.FV_ERR_INVALID_ARG),
     (dict(offsets=[0, 100, 400]), F.FV_ERR_OVERLAP),         # patch 0 spans 180 doubles
     (dict(offsets=[400, 0, 100]), F.FV_ERR_OVERLAP),         # unsorted and overlapping
     (dict(patches_out=IN + 8 * 100), F.FV_ERR_OVERLAP),      # in and out overlap
@@ -213,6 +216,67 @@ def test_valid_arguments_without_a_gpu_report_no_device():
     assert call(flags=F.FV_HALO_FROM_IN | F.FV_HALO_PERIODIC) == F.FV_ERR_NO_DEVICE
     st, h = F.fv_plan_create([4, 4], None, 2, 2, 5, F.FV_HALO_FROM_IN | F.FV_PLAN_PER_CLASS, raise_on_error=False)
     assert st == F.FV_ERR_NO_DEVICE and not h
+
+
+def _expected_status(sizes, offsets, out, lam, dim=2, nq=5):
+    """Brute-force model of the layout and buffer checks: every patch range, every pair."""
+    if any(o < 0 or o + (p + 2) ** dim * nq > F.FV_MAX_OFFSET for p, o in zip(sizes, offsets)):
+        return F.FV_ERR_INVALID_ARG
+    ranges = [(o, o + (p + 2) ** dim * nq) for p, o in zip(sizes, offsets)]
+    for a in range(len(ranges)):
+        for b in range(a + 1, len(ranges)):
+            if ranges[a][0] < ranges[b][1] and ranges[b][0] < ranges[a][1]:
+                return F.FV_ERR_OVERLAP
+    lo, hi = min(r[0] for r in ranges), max(r[1] for r in ranges)
+    spans = {"in": (IN + 8 * lo, IN + 8 * hi), "out": (out + 8 * lo, out + 8 * hi)}
+    if spans["in"][0] < spans["out"][1] and spans["out"][0] < spans["in"][1]:
+        return F.FV_ERR_OVERLAP
+    if lam is not None:
+        l0, l1 = lam, lam + 8 * len(sizes)
+        if any(l0 < b and a < l1 for a, b in spans.values()):
+            return F.FV_ERR_OVERLAP
+    return F.FV_ERR_NO_DEVICE
+
+
+def test_layout_checks_match_a_brute_force_model():
+    """Random batches (gapped, shuffled, overlapping, out of range) and buffer placements: the library's
+    verdict before any device work equals the pairwise check's."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible: a valid call would launch on the fake addresses")
+    except ImportError:
+        pass
+    from hypothesis import given, settings, strategies as stg
+
+    big = stg.sampled_from([-1, F.FV_MAX_OFFSET - 500, F.FV_MAX_OFFSET - 100, F.FV_MAX_OFFSET, 1 << 62])
+
+    @stg.composite
+    def batches(draw):
+        T = draw(stg.integers(1, 12))
+        sizes = draw(stg.lists(stg.integers(1, 9), min_size=T, max_size=T))
+        gap = stg.one_of(*[stg.integers(0, 60)] * 7, stg.integers(-150, -1))
+        gaps = draw(stg.lists(gap, min_size=T, max_size=T))
+        offsets, pos = [], 0
+        for p, g in zip(sizes, gaps):
+            pos = max(0, pos + g)
+            offsets.append(pos)
+            pos += (p + 2) ** 2 * 5
+        offsets = draw(stg.permutations(offsets))
+        if draw(stg.integers(0, 9)) == 0:
+            offsets[draw(stg.integers(0, T - 1))] = draw(big)
+        out = draw(stg.sampled_from([OUT] * 4 + [IN, IN + 8 * 50, IN + 8 * pos, IN + 8 * (pos - 1), IN - 8 * 300]))
+        lam = draw(stg.sampled_from([None, LAM, LAM, IN, OUT + 8 * 7, IN - 8 * T, IN - 8 * (T - 1)]))
+        return sizes, offsets, out, lam
+
+    @settings(max_examples=400, deadline=None, derandomize=True)
+    @given(batches())
+    def check(case):
+        sizes, offsets, out, lam = case
+        st = call(sizes=sizes, offsets=offsets, num_patches=len(sizes), patches_out=out, lambda_out=lam)
+        assert st == _expected_status(sizes, offsets, out, lam), (case, st, F.fv_last_error())
+
+    check()
 
 
 def test_error_raises_with_detail():
