@@ -117,7 +117,9 @@ bool wave2d_fixed(int p, int nq);
 // 16-byte aligned output buffer, whatever the patches' offsets (p = 17 writes whole rows in 16-byte
 // pairs; p = 3, 5, 9 ignore vec2).
 inline bool fixed_odd_rows(int dim, int p, int nq) { return dim == 2 && wave2d_fixed(p, nq) && ((p + 2) * nq) % 2 == 1; }
-int wave2d_fixed_ring_words(int p);
+// LDS words per wave of a fixed-size body in the task-list launch; whole_rows: the launch writes
+// whole output rows (periodic halo or FV_HALO_FROM_IN), else interior-only rows.
+int wave2d_fixed_ring_words(int p, bool whole_rows);
 void wave2d_fixed_shape(int p, int *prefetch, int *rows);
 int wave2d_fixed_block();
 // 3D kernel with a patch's cross-section in one wavefront (compile-time

@@ -195,6 +195,7 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
     pl->flags = flags & (FV_HALO_PERIODIC | FV_HALO_FROM_IN);
     pl->persistent = !(flags & (FV_PLAN_NO_PERSIST | FV_PLAN_PER_CLASS));
     const bool per_class = (flags & FV_PLAN_PER_CLASS) != 0;
+    const bool whole_rows = (pl->flags & (FV_HALO_PERIODIC | FV_HALO_FROM_IN)) != 0;  // of the fused launch
     pl->num_patches = num_patches;
     pl->lo = shape.lo;
     pl->hi = shape.hi;
@@ -237,7 +238,7 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
             for (int32_t f = 0; f < count[p]; f += ppw)
                 tasks.push_back(WaveTask{p, rows, start[p] + f, std::min<int32_t>(ppw, count[p] - f)});
             pl->ring_words = std::max(pl->ring_words,
-                                      fixed ? wave2d_fixed_ring_words(p) : wave2d_ring_words(p, unknowns, rows));
+                                      fixed ? wave2d_fixed_ring_words(p, whole_rows) : wave2d_ring_words(p, unknowns, rows));
             const int64_t cells = (int64_t)count[p] * p * p;
             if (cells > best_cells) {
                 best_cells = (int32_t)std::min<int64_t>(cells, INT32_MAX);

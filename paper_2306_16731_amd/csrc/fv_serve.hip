@@ -173,6 +173,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
     int32_t fill[FV_MAX_P_2D + 2];
     std::memcpy(fill, start, sizeof(fill));
     bool even = true, odd_rows_only = true;
+    const bool whole_rows = (s->cfg.flags & (FV_HALO_PERIODIC | FV_HALO_FROM_IN)) != 0;  // of the fused launch
     for (int32_t k = 0; k < n; ++k) {
         const int32_t t = r.first + k;
         const int32_t j = fill[m.sizes[t]]++;
@@ -198,7 +199,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
             const int ppw = 64 / (p + 2);
             for (int32_t f = 0; f < count[p]; f += ppw)
                 htask[ntask++] = WaveTask{p, rows, start[p] + f, std::min<int32_t>(ppw, count[p] - f)};
-            ring_words = std::max(ring_words, fixed ? wave2d_fixed_ring_words(p) : wave2d_ring_words(p, nq, rows));
+            ring_words = std::max(ring_words, fixed ? wave2d_fixed_ring_words(p, whole_rows) : wave2d_ring_words(p, nq, rows));
             if ((int64_t)count[p] * p * p > best_cells) {
                 best_cells = (int64_t)count[p] * p * p;
                 prefetch = (tu.kernel == FV_KERNEL_WAVE || tu.kernel == FV_KERNEL_FIXED) ? tu.prefetch : 0;

@@ -282,25 +282,54 @@ __device__ __forceinline__ void wave_update(const double *__restrict__ in, doubl
 // Sizes: those of the benchmark batches (16) and the mixed-size batches
 // (3, 5, 9, 17), Euler with five unknowns.
 
-template <int P>
+// Output rows per LDS burst.  Longer bursts write longer runs at once but take more LDS per wave and
+// so leave fewer waves resident; the best depth depends on the launch:
+//   Uniform       uniform launches writing whole rows (periodic, FV_HALO_FROM_IN), meshes, other PDEs;
+//   Interior      uniform launches writing interior-only rows (their halo volumes stay untouched);
+//   TaskWhole     the task-list launch of mixed sizes writing whole rows;
+//   TaskInterior  the task-list launch writing interior-only rows.
+// Every wave of a task-list launch reserves the ring of the batch's largest size class.  Measured on
+// uniform batches of p = 16 and 17 and on the 200,000-patch mix of p = 3, 5, 9, 17 (caps 9 to 16
+// tried): interior-only rows gain from long bursts, up to 14 rows in uniform launches (p = 16: 4%
+// over 12, though five waves per CU stay resident instead of six) and 13 in the task-list launch,
+// while whole rows in the task-list launch gain from short ones, up to 10 rows (6-7% over 12: seven
+// waves per CU instead of five).  A patch of p rows up to the cap is written in one burst.
+enum class RingUse { Uniform, Interior, TaskWhole, TaskInterior };
+
+constexpr int burst_cap(RingUse u) {
+    return u == RingUse::Interior ? 14 : u == RingUse::TaskWhole ? 10 : u == RingUse::TaskInterior ? 13 : 12;
+}
+
+template <int P, RingUse U = RingUse::Uniform>
 struct FixedShape {
-    static constexpr int PF = 2;                    // rows in flight per lane
-    static constexpr int R = P <= 12 ? P : 12;      // output rows per burst
+    static constexpr int PF = 2;                                   // rows in flight per lane
+    static constexpr int R = P <= burst_cap(U) ? P : burst_cap(U);  // output rows per burst
 };
 constexpr int kFixedBlock = 64;                     // one wave per block: LDS, not registers, bounds residency
 constexpr int kTaskBlock = 64;                      // the same for the task-list kernel
 
 inline bool fixed_size(int p) { return p == 3 || p == 5 || p == 9 || p == 16 || p == 17; }
 
-template <int P, int NQ = 5>
+template <int P, RingUse U = RingUse::Uniform, int NQ = 5>
 constexpr int fixed_ring_words() {
-    return (64 / (P + 2)) * FixedShape<P>::R * (P + 2) * NQ + 64 / (P + 2);
+    return (64 / (P + 2)) * FixedShape<P, U>::R * (P + 2) * NQ + 64 / (P + 2);
+}
+
+// The ring use of a uniform launch of the fixed-size form, and of a body in the task-list launch.
+template <bool PERIODIC, bool MESH, bool WHOLE>
+constexpr RingUse uniform_use() {
+    return (PERIODIC || MESH || WHOLE) ? RingUse::Uniform : RingUse::Interior;
+}
+template <bool PERIODIC, bool WHOLE>
+constexpr RingUse task_use() {
+    return (PERIODIC || WHOLE) ? RingUse::TaskWhole : RingUse::TaskInterior;
 }
 
 // MESH: the face halos come from the neighbouring patches' interiors (the
 // halo volumes of a patch without a neighbour on that face are its own), and
 // patch t advances by dt[t] / h[t]; the output is the interior only.
-template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false>
+template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false,
+          RingUse USE = RingUse::Uniform>
 __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in, double *__restrict__ out,
                                                   const int64_t *__restrict__ offsets,
                                                   const int64_t *__restrict__ out_offsets,
@@ -318,8 +347,8 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     constexpr int W = P + 2;
     constexpr int ppw = 64 / W;
     constexpr int ROWD = W * NQ;
-    constexpr int PF = FixedShape<P>::PF;
-    constexpr int R = FixedShape<P>::R;
+    constexpr int PF = FixedShape<P, USE>::PF;
+    constexpr int R = FixedShape<P, USE>::R;
     // VEC = 2: 16-byte burst stores.  Rows of an even number of doubles need every patch at an even
     // offset; rows of an odd number (odd p + 2 with N = 5) need only a 16-byte aligned output buffer:
     // each run of whole rows is written as the 16-byte pairs that start at its first even double,
@@ -574,9 +603,8 @@ __device__ __forceinline__ void fixed_task_body(const double *__restrict__ in, d
                                              const int64_t *__restrict__ out_offsets,
                                              const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
                                              double *__restrict__ lambda_out, double *ring) {
-    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, false, WHOLE>(in, out, offsets, out_offsets, ids, 0, count, 0,
-                                                                   r, 0.0, typename EulerPDE<5>::Params{gamma},
-                                                                   lambda_out, ring);
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, false, WHOLE, task_use<PERIODIC, WHOLE>()>(
+        in, out, offsets, out_offsets, ids, 0, count, 0, r, 0.0, typename EulerPDE<5>::Params{gamma}, lambda_out, ring);
 }
 
 // Task-list body for a fixed size: false when p has no fixed-size build.
@@ -632,10 +660,10 @@ update2d_fixed_kernel(const double *__restrict__ in, double *__restrict__ out, c
     const int64_t item0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * ppw;
     if (item0 >= num_items) return;
     const double rr = r_dev ? *r_dev : r;
-    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, MESH, WHOLE>(in, out, offsets, out_offsets, ids, item0,
-                                                                  num_items, stride, rr, 0.0,
-                                                                  typename EulerPDE<5>::Params{gamma}, lambda_out,
-                                                                  lds + (size_t)wave * fixed_ring_words<P>(), mesh);
+    constexpr RingUse U = uniform_use<PERIODIC, MESH, WHOLE>();
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, MESH, WHOLE, U>(
+        in, out, offsets, out_offsets, ids, item0, num_items, stride, rr, 0.0, typename EulerPDE<5>::Params{gamma},
+        lambda_out, lds + (size_t)wave * fixed_ring_words<P, U>(), mesh);
 }
 
 // The wave form for the other PDEs of Eq. 1 (fv_pde.h) at the fixed sizes: the
@@ -802,7 +830,7 @@ static hipError_t launch_fixed(const UpdateLaunch &L, hipStream_t stream) {
     const int per_block = (B / 64) * ppw;
     const int64_t blocks = ((int64_t)L.num_items + per_block - 1) / per_block;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)fixed_ring_words<P>();
+    const size_t lds = sizeof(double) * (size_t)(B / 64) * (size_t)fixed_ring_words<P, uniform_use<PERIODIC, MESH, WHOLE>()>();
     int dev = 0, lds_max = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -843,15 +871,20 @@ void wave2d_fixed_shape(int p, int *prefetch, int *rows) {
 
 int wave2d_fixed_block() { return kFixedBlock; }
 
-int wave2d_fixed_ring_words(int p) {
+template <RingUse U>
+static int task_ring_words(int p) {
     switch (p) {
-        case 3: return fixed_ring_words<3>();
-        case 5: return fixed_ring_words<5>();
-        case 9: return fixed_ring_words<9>();
-        case 16: return fixed_ring_words<16>();
-        case 17: return fixed_ring_words<17>();
+        case 3: return fixed_ring_words<3, U>();
+        case 5: return fixed_ring_words<5, U>();
+        case 9: return fixed_ring_words<9, U>();
+        case 16: return fixed_ring_words<16, U>();
+        case 17: return fixed_ring_words<17, U>();
     }
     return 0;
+}
+
+int wave2d_fixed_ring_words(int p, bool whole_rows) {
+    return whole_rows ? task_ring_words<RingUse::TaskWhole>(p) : task_ring_words<RingUse::TaskInterior>(p);
 }
 
 hipError_t launch_update2d_fixed(const UpdateLaunch &L, hipStream_t stream) {
@@ -881,7 +914,7 @@ hipError_t launch_pde_wave(const UpdateLaunch &L, const typename PDE::Params &pr
     constexpr int ppw = 64 / (P + 2);
     const int64_t blocks = ((int64_t)L.num_items + ppw - 1) / ppw;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const size_t lds = sizeof(double) * (size_t)fixed_ring_words<P, PDE::NQ>();
+    const size_t lds = sizeof(double) * (size_t)fixed_ring_words<P, RingUse::Uniform, PDE::NQ>();
     // 16-byte row bursts where the rows are an even number of doubles (p = 16)
     if ((L.flags & kPeriodic) == 0) launch_pde_wave_form<PDE, P, 1, false>(L, prm, blocks, lds, stream);
     else if (P == 16 && L.vec2) launch_pde_wave_form<PDE, P, P == 16 ? 2 : 1, true>(L, prm, blocks, lds, stream);
