@@ -464,7 +464,8 @@ def extra_configs(args) -> dict:
         e["speedup_plan_vs_plain"] = round(r["ms"]["plain"] / r["ms"]["plan"], 3)
         e["speedup_graph_vs_plain"] = round(r["ms"]["plain"] / r["ms"]["graph"], 3)
         extra[name] = e
-    extra["timing"] = ("configs 3 / 4: median of 5 windows of 10 steps per form, HIP events on one stream, "
+    extra["timing"] = ("configs 3 / 4: median of 5 windows of 10 steps per form after at least 100 settle steps, "
+                       "HIP events on one stream, "
                        "host launch work inside the window; graph: one 10-step replay per window")
     extra["seconds"] = round(time.perf_counter() - t0, 1)
     return extra
@@ -880,8 +881,10 @@ def bench_mesh(args) -> int:
 def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, samples: int = 5, tune=None) -> dict:
     """One batching workload (config 3 or 4) through plain per-batch launches, a plan's fused launch,
     the plan's captured `steps`-step graph with device dt and, when the workload is not periodic, the
-    plan with FV_HALO_FROM_IN.  ms per step: median of `samples` windows of `steps` steps, HIP events
-    on one stream (the plain path's host work, which the plan removes, is inside the window)."""
+    plan with FV_HALO_FROM_IN.  ms per step: median of `samples` windows of `steps` steps after at least
+    SETTLE_STEPS untimed steps of the same form (a GPU left idle by the host work between forms starts
+    slow), HIP events on one stream (the plain path's host work, which the plan removes, is inside the
+    window)."""
     import numpy as np
     import torch
 
@@ -915,7 +918,8 @@ def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, sample
                                       stream=s)
         bufs.reverse()
 
-    for _ in range(3):
+    settle = max(3, SETTLE_STEPS)  # untimed steps before each form's windows (clocks settle)
+    for _ in range(settle):
         plain()
     ms["plain"] = _median_window_ms(plain, steps, samples, s)
     pflags = flags | plan_choice["flags"]
@@ -927,7 +931,7 @@ def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, sample
             fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam, stream=s)
             bufs.reverse()
 
-        for _ in range(3):
+        for _ in range(settle):
             fused()
         ms["plan"] = _median_window_ms(fused, steps, samples, s)
         fvpatch.fv_plan_capture_steps(plan, steps, a, c, h, gamma, wl.CFL, lam, dt_dev, s)
@@ -937,7 +941,7 @@ def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, sample
                 dt_dev[0] = dt
             fvpatch.fv_plan_replay(plan, s)
 
-        for _ in range(2):
+        for _ in range(max(2, settle // steps)):
             replay()
         ms["graph"] = _median_window_ms(replay, 1, samples, s) / steps
         dts = dt_dev.cpu().numpy()
@@ -950,7 +954,7 @@ def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, sample
                 fvpatch.fv_plan_execute(plan, bufs[0], bufs[1], dt, h, gamma, lam, stream=s)
                 bufs.reverse()
 
-            for _ in range(3):
+            for _ in range(settle):
                 fused_whole()
             ms["plan_halo_from_in"] = _median_window_ms(fused_whole, steps, samples, s)
             fvpatch.fv_plan_capture_steps(plan, steps, a, c, h, gamma, wl.CFL, lam, dt_dev, s)
@@ -960,7 +964,7 @@ def batching_case(name: str, args, tune_plan_mode: bool, steps: int = 10, sample
                     dt_dev[0] = dt
                 fvpatch.fv_plan_replay(plan, s)
 
-            for _ in range(2):
+            for _ in range(max(2, settle // steps)):
                 replay_whole()
             ms["graph_halo_from_in"] = _median_window_ms(replay_whole, 1, samples, s) / steps
         finally:
@@ -999,7 +1003,8 @@ def bench_batching(args) -> int:
                                "cells_per_step": r["cells"], "periodic_halo": r["periodic"]},
                     "plan": r["plan_info"] if form != "plain" else None,
                     "plan_work_split": r["plan_choice"] if form != "plain" else None,
-                    "timing": "median of 5 windows of 10 steps, HIP events on one stream, host work included"}
+                    "timing": "median of 5 windows of 10 steps after at least 100 settle steps, HIP events on one "
+                              "stream, host work included"}
             if form == "graph":
                 line["device_dt"] = r["device_dt"]
             if form in ("plan_halo_from_in", "graph_halo_from_in"):

@@ -329,7 +329,7 @@ constexpr RingUse task_use() {
 // halo volumes of a patch without a neighbour on that face are its own), and
 // patch t advances by dt[t] / h[t]; the output is the interior only.
 template <class PDE, int P, int VEC, bool PERIODIC, bool MESH = false, bool WHOLE = false,
-          RingUse USE = RingUse::Uniform>
+          RingUse USE = RingUse::Uniform, int PFX = 0>
 __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in, double *__restrict__ out,
                                                   const int64_t *__restrict__ offsets,
                                                   const int64_t *__restrict__ out_offsets,
@@ -347,7 +347,7 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     constexpr int W = P + 2;
     constexpr int ppw = 64 / W;
     constexpr int ROWD = W * NQ;
-    constexpr int PF = FixedShape<P, USE>::PF;
+    constexpr int PF = PFX > 0 ? PFX : FixedShape<P, USE>::PF;  // PFX: the caller's prefetch depth
     constexpr int R = FixedShape<P, USE>::R;
     // VEC = 2: 16-byte burst stores.  Rows of an even number of doubles need every patch at an even
     // offset; rows of an odd number (odd p + 2 with N = 5) need only a 16-byte aligned output buffer:
@@ -596,20 +596,44 @@ __device__ __forceinline__ void wave_update_fixed(const double *__restrict__ in,
     }
 }
 
-// One task of the fixed-size form.
-template <int P, int VEC, bool PERIODIC, bool WHOLE>
+// Rows in flight of a fixed-size body in a task-list launch with one wave per task: deeper than in
+// the uniform launches (config 3's mix: 6 rows for interior-only rows, 3% faster than 2; 4 for whole
+// rows, 1%).  A persistent grid, whose waves run many tasks each, was 3% slower with them, so its
+// bodies keep the uniform depth.
+constexpr int task_prefetch(RingUse u) { return u == RingUse::TaskInterior ? 6 : 4; }
+
+// One task of the fixed-size form; DEEP: the launch runs one wave per task.
+template <int P, int VEC, bool PERIODIC, bool WHOLE, bool DEEP>
 __device__ __forceinline__ void fixed_task_body(const double *__restrict__ in, double *__restrict__ out,
                                              const int64_t *__restrict__ offsets,
                                              const int64_t *__restrict__ out_offsets,
                                              const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
                                              double *__restrict__ lambda_out, double *ring) {
-    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, false, WHOLE, task_use<PERIODIC, WHOLE>()>(
+    constexpr RingUse U = task_use<PERIODIC, WHOLE>();
+    wave_update_fixed<EulerPDE<5>, P, VEC, PERIODIC, false, WHOLE, U, DEEP ? task_prefetch(U) : 0>(
         in, out, offsets, out_offsets, ids, 0, count, 0, r, 0.0, typename EulerPDE<5>::Params{gamma}, lambda_out, ring);
 }
 
 // Task-list body for a fixed size: false when p has no fixed-size build.
+template <int NQ, int VEC, bool PERIODIC, bool WHOLE, bool DEEP>
+__device__ __forceinline__ bool fixed_task_depth(int p, const double *__restrict__ in, double *__restrict__ out,
+                                                 const int64_t *__restrict__ offsets,
+                                                 const int64_t *__restrict__ out_offsets,
+                                                 const int32_t *__restrict__ ids, int64_t count, double r,
+                                                 double gamma, double *__restrict__ lambda_out, double *ring) {
+    switch (p) {
+        case 3: fixed_task_body<3, 1, PERIODIC, WHOLE, DEEP>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+        case 5: fixed_task_body<5, 1, PERIODIC, WHOLE, DEEP>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+        case 9: fixed_task_body<9, 1, PERIODIC, WHOLE, DEEP>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+        case 16: fixed_task_body<16, VEC, PERIODIC, WHOLE, DEEP>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+        case 17: fixed_task_body<17, VEC, PERIODIC, WHOLE, DEEP>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
+    }
+    return false;
+}
+
+// deep: the launch runs one wave per task (uniform across the launch).
 template <int NQ, int VEC, bool PERIODIC, bool WHOLE>
-__device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in, double *__restrict__ out,
+__device__ __forceinline__ bool fixed_task(int p, bool deep, const double *__restrict__ in, double *__restrict__ out,
                                            const int64_t *__restrict__ offsets,
                                            const int64_t *__restrict__ out_offsets,
                                            const int32_t *__restrict__ ids, int64_t count, double r, double gamma,
@@ -617,14 +641,10 @@ __device__ __forceinline__ bool fixed_task(int p, const double *__restrict__ in,
     if constexpr (NQ != 5) {
         return false;
     } else {
-        switch (p) {
-            case 3: fixed_task_body<3, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 5: fixed_task_body<5, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 9: fixed_task_body<9, 1, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 16: fixed_task_body<16, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-            case 17: fixed_task_body<17, VEC, PERIODIC, WHOLE>(in, out, offsets, out_offsets, ids, count, r, gamma, lambda_out, ring); return true;
-        }
-        return false;
+        return deep ? fixed_task_depth<NQ, VEC, PERIODIC, WHOLE, true>(p, in, out, offsets, out_offsets, ids, count, r,
+                                                                       gamma, lambda_out, ring)
+                    : fixed_task_depth<NQ, VEC, PERIODIC, WHOLE, false>(p, in, out, offsets, out_offsets, ids, count,
+                                                                        r, gamma, lambda_out, ring);
     }
 }
 
@@ -700,11 +720,13 @@ update2d_tasks_kernel(const double *__restrict__ in, double *__restrict__ out, c
     const int64_t nw = (int64_t)gridDim.x * waves;
     const double rr = r_dev ? *r_dev : r;
     double *ring = lds + (size_t)wave * ring_words;
+    const bool one_per_task = nw >= num_tasks;
     for (int64_t t = gw; t < num_tasks; t += nw) {
         const WaveTask tk = tasks[t];
         const int64_t *to = out_offsets ? out_offsets + tk.first : nullptr;
-        if (tk.rows == 0 && fixed_task<NQ, VEC, PERIODIC, WHOLE>(tk.p, in, out, offsets + tk.first, to, ids + tk.first,
-                                                          tk.count, rr, gamma, lambda_out, ring))
+        if (tk.rows == 0 && fixed_task<NQ, VEC, PERIODIC, WHOLE>(tk.p, one_per_task, in, out, offsets + tk.first, to,
+                                                                 ids + tk.first, tk.count, rr, gamma, lambda_out,
+                                                                 ring))
             continue;
         wave_update<NQ, PF, VEC>(in, out, offsets + tk.first, to, ids + tk.first, 0, tk.count, tk.p, 0, rr, gamma,
                                  (PERIODIC ? kPeriodic : 0u) | (WHOLE ? kHaloFromIn : 0u), lambda_out,
