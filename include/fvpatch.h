@@ -219,7 +219,10 @@ fv_status fv_get_tuning(int32_t dim, int32_t unknowns, int32_t p, fv_tuning *tun
  * walking the tasks largest first (default), or one wave per task with the
  * tasks in memory order (FV_PLAN_NO_PERSIST) -- plus one launch per remaining
  * class (3D, or 2D p > 62); FV_PLAN_PER_CLASS launches every class on its own
- * kernel instead.  Each plan may carry its own tuning table.  The plan
+ * kernel instead.  On large mixed batches one wave per task is the fastest
+ * of the three (its fixed-size bodies also keep more rows in flight); the
+ * autotuner times the three for a given batch.  Each plan may carry its own
+ * tuning table.  The plan
  * also captures k steps, with the time step formed on the device from each
  * step's eigenvalues, into one hipGraph that replays without host round
  * trips.  This is the paper's task fusion of T patch updates into one kernel
