@@ -122,8 +122,11 @@ typedef enum fv_status {
  *   lambda_out   device [num_patches] or NULL: per-patch max eigenvalue of
  *                the new solution; NULL skips the reduction.
  *   stream       hipStream_t or NULL.
- * Pointers must be 8-byte aligned.  The call is re-entrant; calls on the same
- * device share internal descriptor buffers guarded by events.
+ * Pointers must be 8-byte aligned.  The call is re-entrant and may be made
+ * from several threads at once: calls on the same device share a ring of
+ * pinned descriptor slots, each held by one call from filling to launch and
+ * reused after the launches that read it have run (a call waits for a slot
+ * when more calls than slots are under way).
  */
 fv_status fv_patch_batch_update(const double *patches_in, double *patches_out,
                                 const int32_t *sizes, const int64_t *offsets,
