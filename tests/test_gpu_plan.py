@@ -90,14 +90,17 @@ def test_plan_mixed_sizes(mode):
     check_against_oracle(b, dts, False, got, lams)
 
 
-@pytest.mark.parametrize("periodic", [False, True])
-def test_plan_modes_agree_bitwise(periodic):
+@pytest.mark.parametrize("periodic,from_in", [(False, False), (True, False), (False, True)])
+def test_plan_modes_agree_bitwise(periodic, from_in):
     """The fused launch and the per-class launches run the same fixed-size bodies in the same
-    order of operations, whatever their load and store widths: outputs and eigenvalues agree bit
-    for bit with each other and with the plain per-batch launch, on gapped offsets."""
+    order of operations, whatever their load and store widths, ring depths and rows in flight:
+    outputs and eigenvalues agree bit for bit with each other and with the plain per-batch launch,
+    on gapped offsets.  With FV_HALO_FROM_IN the output halos take the input's, which are the
+    initial halos in both buffers here, so the state still equals the oracle's."""
     import torch
     from paper_2306_16731_amd import fvpatch
-    _announce(f"plan modes bitwise, periodic={periodic}")
+    _announce(f"plan modes bitwise, periodic={periodic}, from_in={from_in}")
+    extra = fvpatch.FV_HALO_FROM_IN if from_in else 0
     rng = np.random.Generator(np.random.PCG64(41))
     sizes = rng.choice(np.array([3, 5, 9, 16, 17, 30], np.int32), size=700)
     compact = wl.make_batch(sizes, 2, 5, seed=42)
@@ -116,9 +119,9 @@ def test_plan_modes_agree_bitwise(periodic):
     results = {}
     for mode, flags in [("persistent", 0), ("per_task", fvpatch.FV_PLAN_NO_PERSIST),
                         ("per_class", fvpatch.FV_PLAN_PER_CLASS)]:
-        got, lams, info = run_plan(batch, dts, periodic, flags)
+        got, lams, info = run_plan(batch, dts, periodic, flags | extra)
         results[mode] = (got, np.stack(lams))
-    fl = fvpatch.FV_HALO_PERIODIC if periodic else 0
+    fl = (fvpatch.FV_HALO_PERIODIC if periodic else 0) | extra
     a = hp.to_dev(data)
     b2 = a.clone()
     lam = torch.empty((len(dts), len(sizes)), dtype=torch.float64, device="cuda")
