@@ -173,6 +173,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
     int32_t fill[FV_MAX_P_2D + 2];
     std::memcpy(fill, start, sizeof(fill));
     bool even = true, odd_rows_only = true;
+    bool odd_offset[FV_MAX_P_2D + 1] = {false};  // per size: some entry starts at an odd double
     const bool whole_rows = (s->cfg.flags & (FV_HALO_PERIODIC | FV_HALO_FROM_IN)) != 0;  // of the fused launch
     for (int32_t k = 0; k < n; ++k) {
         const int32_t t = r.first + k;
@@ -182,11 +183,14 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
         hin[j] = base_in + m.off[t];
         hout[j] = base_out + m.off[t];
         hid[j] = k;
-        if ((hin[j] | hout[j]) & 1) even = false;
+        if ((hin[j] | hout[j]) & 1) {
+            even = false;
+            odd_offset[m.sizes[t]] = true;
+        }
     }
     int32_t ntask = 0, ring_words = 0, prefetch = 0;
     int64_t best_cells = -1;
-    struct Cls { int p, first, count; };
+    struct Cls { int p, first, count; bool even; };  // even: 16-byte bursts (even offsets and patch length)
     std::vector<Cls> classes;
     for (int p = pmax; p >= 1; --p) {
         if (!count[p]) continue;
@@ -207,7 +211,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
             if (((p + 2) * nq) % 2) even = false;
             if (!(fixed && fixed_odd_rows(dim, p, nq))) odd_rows_only = false;
         } else {
-            classes.push_back(Cls{p, start[p], count[p]});
+            classes.push_back(Cls{p, start[p], count[p], !odd_offset[p] && patch_doubles(p, dim, nq) % 2 == 0});
         }
     }
     // one wave per task: tasks in memory order keep the resident waves on neighbouring patches
@@ -255,6 +259,7 @@ fv_status launch_fused(fv_server *s, Mesh &m, const Request &r, Staging &st) {
         L.gamma = s->cfg.gamma;
         L.flags = s->cfg.flags;
         L.lambda_out = st.lambda;
+        L.vec2 = c.even && ((reinterpret_cast<uintptr_t>(m.buf) & 15u) == 0);
         apply_tuning(L);
         if (L.kernel == FV_KERNEL_WAVE) L.kernel = FV_KERNEL_BLOCK;
         if (L.kernel == FV_KERNEL_TILE) L.vec2 = false;
