@@ -47,6 +47,11 @@ struct fv_plan {
     struct Group {
         int32_t p, first, count;
         bool even;  // every patch of the class starts at an even double and spans an even number of them
+        // regular: the class's patches are evenly spaced, base + i stride, with consecutive lambda
+        // indices id0 + i; it then launches without descriptors, as a plain call does
+        bool regular;
+        int64_t base, stride;
+        int32_t id0;
     };
     std::vector<Group> groups;  // classes launched per class (3D, 2D p > 62; every class with FV_PLAN_PER_CLASS)
     // launch parameters of each size class, fixed at creation (index p; kernel -1: no such class)
@@ -118,9 +123,19 @@ fv_status enqueue_step(const fv_plan *pl, const double *in, double *out, double 
         L.flags = pl->flags;
         L.lambda_out = lambda_out;
         L.vec2 = g.even && aligned16(in) && aligned16(out);
+        if (g.regular) {
+            L.in = in + g.base;
+            L.out = out + g.base;
+            L.offsets = nullptr;
+            L.ids = nullptr;
+            L.stride = g.stride;
+            L.lambda_out = lambda_out ? lambda_out + g.id0 : nullptr;
+            L.vec2 = g.stride % 2 == 0 && patch_doubles(g.p, L.dim, L.nq) % 2 == 0 && aligned16(L.in) &&
+                     aligned16(L.out);
+        }
         apply_tuning(L, pl->tune[g.p]);
         if (L.dim == 2 && L.kernel == FV_KERNEL_WAVE && !wave2d_fits(L.p)) L.kernel = FV_KERNEL_BLOCK;
-        if (L.kernel == FV_KERNEL_FIXED && fixed_odd_rows(L.dim, L.p, L.nq)) L.vec2 = aligned16(out);
+        if (L.kernel == FV_KERNEL_FIXED && fixed_odd_rows(L.dim, L.p, L.nq)) L.vec2 = aligned16(L.out);
         hipError_t e = launch_update(L, stream);
         if (e != hipSuccess) return fail(FV_ERR_LAUNCH, "class launch (p=%d) failed: %s", g.p, hipGetErrorString(e));
     }
@@ -251,7 +266,12 @@ fv_status fv_plan_create(fv_plan **plan, const int32_t *sizes, const int64_t *of
         } else {
             bool even = patch_doubles(p, dim, unknowns) % 2 == 0;
             for (int32_t k = start[p]; k < start[p] + count[p] && even; ++k) even = (hoff[k] & 1) == 0;
-            pl->groups.push_back(fv_plan::Group{p, start[p], count[p], even});
+            const int32_t f = start[p], c = count[p];
+            const int64_t stride = c > 1 ? hoff[f + 1] - hoff[f] : patch_doubles(p, dim, unknowns);
+            bool regular = stride >= patch_doubles(p, dim, unknowns);
+            for (int32_t k = 1; k < c && regular; ++k)
+                regular = hoff[f + k] == hoff[f] + (int64_t)k * stride && hid[f + k] == hid[f] + k;
+            pl->groups.push_back(fv_plan::Group{p, f, c, even, regular, hoff[f], stride, hid[f]});
         }
     }
     // One wave per task: workgroups start in task order, so tasks in memory order keep the

@@ -336,6 +336,53 @@ def test_graph_replay_with_device_dt(name, T, periodic, per_class, from_in):
         fvpatch.fv_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("dim,p,gap,per_class,flags", [(2, 17, 3, True, "periodic"), (2, 16, 0, True, "none"),
+                                                      (3, 8, 0, False, "none"), (3, 4, 2, False, "from_in"),
+                                                      (3, 6, 1, False, "periodic")])
+def test_plan_regular_class_launches_without_descriptors(dim, p, gap, per_class, flags):
+    """A class whose patches are evenly spaced, in order, launches like a plain call on such a batch (no
+    descriptors): the plan's steps equal the plain per-batch launch's bit for bit, at any spacing, and
+    the bytes between patches stay untouched."""
+    import torch
+    from paper_2306_16731_amd import fvpatch
+    _announce(f"plan: regular class dim={dim} p={p} gap={gap} per_class={per_class} flags={flags}")
+    T = 700 if dim == 2 else 300
+    compact = wl.make_uniform(T, p, dim=dim, nq=5, seed=51)
+    vol = (p + 2) ** dim * 5
+    offsets = 1 + np.arange(T, dtype=np.int64) * (vol + gap)
+    data = np.random.Generator(np.random.PCG64(52)).uniform(-1, 1, int(offsets[-1] + vol + 2))
+    for t in range(T):
+        data[offsets[t]:offsets[t] + vol] = compact.data[compact.offsets[t]:compact.offsets[t] + vol]
+    fl = {"none": 0, "periodic": fvpatch.FV_HALO_PERIODIC, "from_in": fvpatch.FV_HALO_FROM_IN}[flags]
+    sizes = np.full(T, p, np.int32)
+    dts = [1.2e-3, 0.8e-3]
+    res = {}
+    plan = fvpatch.fv_plan_create(sizes, offsets, T, dim, 5, fl | (fvpatch.FV_PLAN_PER_CLASS if per_class else 0))
+    try:
+        assert fvpatch.fv_plan_info(plan)["num_class_launches"] == 1
+        for form in ("plan", "plain"):
+            a = hp.to_dev(data)
+            b = a.clone()
+            lam = torch.empty((len(dts), T), dtype=torch.float64, device="cuda")
+            for k, dt in enumerate(dts):
+                if form == "plan":
+                    fvpatch.fv_plan_execute(plan, a, b, dt, wl.H_DEFAULT, wl.GAMMA, lam[k])
+                else:
+                    fvpatch.fv_patch_batch_update(a, b, sizes, offsets, T, dim, 5, dt, wl.H_DEFAULT, wl.GAMMA, fl,
+                                                  lam[k])
+                a, b = b, a
+            torch.cuda.synchronize()
+            res[form] = (a.cpu().numpy().view(np.int64), lam.cpu().numpy().view(np.int64))
+    finally:
+        fvpatch.fv_plan_destroy(plan)
+    assert np.array_equal(res["plan"][0], res["plain"][0])
+    assert np.array_equal(res["plan"][1], res["plain"][1])
+    mask = np.ones(len(data), bool)
+    for t in range(T):
+        mask[offsets[t]:offsets[t] + vol] = False
+    assert np.array_equal(res["plan"][0][mask], data.view(np.int64)[mask])
+
+
 def test_plan_replay_without_capture_is_an_error():
     from paper_2306_16731_amd import fvpatch
     b = wl.make_uniform(4, 5, seed=3)
